@@ -1,0 +1,478 @@
+"""ctypes binding of libcoot_mi355x.so (argument marshalling only).
+
+Every function here packs its arguments into the C structs of
+``include/coot.h`` and calls the entry point of the same name; all
+computation happens in the library's HIP kernels.  torch tensors supply
+device memory and the current HIP stream.
+
+A matrix is a 2-D tensor in column-major layout, i.e. stride (1, ld), such
+as ``torch.empty(n_cols, n_rows).t()``; a 1-D contiguous tensor is an n x 1
+column.  Expression trees are sequences of nodes with ``op``, ``a``, ``b``,
+``k`` (the op names below), or objects with a ``postfix()`` method.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from typing import Optional, Sequence
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libcoot_mi355x.so")
+# run-time compiled kernels are cached next to the library unless told otherwise
+os.environ.setdefault("COOT_CACHE_DIR", os.path.join(_HERE, "_kcache"))
+
+# ---- codes (include/coot.h) ---------------------------------------------
+OK = 0
+ERRORS = {
+    -1: "BAD_TREE", -2: "SHAPE", -3: "DTYPE", -4: "ALIAS", -5: "EMPTY", -6: "UNSUPPORTED",
+    -7: "JIT", -8: "HIP", -9: "NOMEM", -10: "ARG", -11: "NOT_INIT",
+}
+F32, F64, F16, BF16, U64 = 0, 1, 2, 3, 4
+DTYPE_CODES = {"f32": F32, "f64": F64, "f16": F16, "bf16": BF16, "u64": U64}
+OPS = {
+    "leaf": 0, "plus": 1, "minus": 2, "schur": 3, "div": 4,
+    "scal_plus": 10, "scal_minus_post": 11, "scal_minus_pre": 12, "scal_times": 13,
+    "scal_div_post": 14, "scal_div_pre": 15,
+    "exp": 20, "log": 21, "sqrt": 22, "abs": 23, "trans": 30, "conv": 31,
+}
+REDS = {
+    "accu": 0, "sum": 1, "dot": 2, "norm1": 3, "norm2": 4, "norminf": 5, "normneginf": 6,
+    "min": 7, "max": 8, "index_min": 9, "index_max": 10,
+}
+RED_PAIRWISE = 0x100
+OPERAND_HOST = 1
+EXPR_UNFUSED = 1
+PRINT_INFO = 1
+TUNE_DEFAULT, TUNE_CACHE, TUNE_MODEL = 0, 1, 2
+BATCH_NO_GRAPH, BATCH_PER_ITEM, BATCH_UNFUSED = 1, 2, 4
+N_CONFIGS = 64
+N_FEATURES = 32
+MLP_N_PARAMS = 32 * 64 + 64 + 64 * 64 + 64
+
+
+def mlp_ws_floats(B: int) -> int:
+    return B * (64 + 64 + 64) + 64 + 8
+
+
+class CootError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"coot error {code} ({ERRORS.get(code, '?')}): {msg}")
+        self.code = code
+        self.msg = msg
+
+
+# ---- structs -------------------------------------------------------------
+class Operand(C.Structure):
+    _fields_ = [("ptr", C.c_void_p), ("n_rows", C.c_int64), ("n_cols", C.c_int64), ("ld", C.c_int64),
+                ("dtype", C.c_int32), ("flags", C.c_uint32)]
+
+
+class Node(C.Structure):
+    _fields_ = [("op", C.c_int32), ("a", C.c_int32), ("b", C.c_int32), ("reserved", C.c_int32), ("k", C.c_double)]
+
+
+class Config(C.Structure):
+    _fields_ = [("ept", C.c_int32), ("block", C.c_int32), ("split", C.c_int32), ("reserved", C.c_int32)]
+
+
+class Expr(C.Structure):
+    _fields_ = [("nodes", C.POINTER(Node)), ("n_nodes", C.c_int32), ("flags", C.c_uint32), ("cfg", Config)]
+
+
+class Batch(C.Structure):
+    _fields_ = [("expr", C.POINTER(Expr)), ("n_slots", C.c_int32), ("n_items", C.c_int32),
+                ("slot_dtypes", C.POINTER(C.c_int32)), ("leaf_ptrs", C.POINTER(C.c_void_p)),
+                ("out_ptrs", C.POINTER(C.c_void_p)), ("out_dtype", C.c_int32), ("red_op", C.c_int32),
+                ("shapes", C.POINTER(C.c_int64)), ("red_expr", C.POINTER(Expr)), ("red_out", C.c_void_p),
+                ("red_dtype", C.c_int32), ("flags", C.c_uint32)]
+
+
+class Stats(C.Structure):
+    _fields_ = [("launches", C.c_int64), ("jit_compiles", C.c_int64), ("jit_disk_hits", C.c_int64),
+                ("jit_mem_hits", C.c_int64), ("jit_seconds", C.c_double)]
+
+
+# ---- library -------------------------------------------------------------
+_lib = None
+
+EXPORTS = [
+    "coot_init", "coot_finalize", "coot_eval", "coot_reduce", "coot_synchronise", "coot_last_error",
+    "coot_validate", "coot_kernel_source", "coot_precompile", "coot_batch_create", "coot_batch_run",
+    "coot_batch_destroy", "coot_config_of", "coot_set_tuning", "coot_features", "coot_autotune",
+    "coot_mlp_forward", "coot_mlp_backward", "coot_mlp_adam", "coot_model_set", "coot_model_choose",
+    "coot_get_stats", "coot_copy",
+]
+
+
+def lib():
+    """Load the HIP library; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with paper_2308_03120_amd.build.build() "
+                              "(there is no CPU fallback)")
+        L = C.CDLL(LIB_PATH)
+        P = C.POINTER
+        vp, i64, i32 = C.c_void_p, C.c_int64, C.c_int
+        L.coot_init.argtypes = [i32, C.c_uint]
+        L.coot_eval.argtypes = [P(Expr), P(Operand), i32, P(Operand), vp]
+        L.coot_reduce.argtypes = [i32, i32, P(Expr), P(Operand), i32, P(Operand), vp]
+        L.coot_synchronise.argtypes = [vp]
+        L.coot_last_error.restype = C.c_char_p
+        L.coot_validate.argtypes = [i32, i32, P(Expr), P(Operand), i32, P(Operand)]
+        L.coot_kernel_source.argtypes = [i32, i32, P(Expr), P(Operand), i32, P(Operand), C.c_char_p, i64]
+        L.coot_kernel_source.restype = i64
+        L.coot_precompile.argtypes = [i32, i32, P(Expr), P(Operand), i32, P(Operand)]
+        L.coot_batch_create.argtypes = [P(Batch), vp, P(vp)]
+        L.coot_batch_run.argtypes = [vp, vp]
+        L.coot_batch_destroy.argtypes = [vp]
+        L.coot_config_of.argtypes = [i32, P(Config)]
+        L.coot_set_tuning.argtypes = [i32, C.c_char_p]
+        L.coot_features.argtypes = [i32, i32, P(Expr), P(Operand), i32, P(Operand), P(C.c_float)]
+        L.coot_autotune.argtypes = [i32, i32, P(Expr), P(Operand), i32, P(Operand), i32, P(C.c_float), vp]
+        fp = P(C.c_float)
+        L.coot_mlp_forward.argtypes = [vp, vp, i32, vp, vp, vp]
+        L.coot_mlp_backward.argtypes = [vp, vp, vp, vp, i32, vp, vp, vp, vp]
+        L.coot_mlp_adam.argtypes = [vp, vp, vp, vp, i32, i32, C.c_float, C.c_float, C.c_float, C.c_float, vp]
+        L.coot_model_set.argtypes = [fp, fp, fp]
+        L.coot_model_choose.argtypes = [i32, i32, P(Expr), P(Operand), i32, P(Operand)]
+        L.coot_get_stats.argtypes = [P(Stats)]
+        L.coot_copy.argtypes = [vp, vp, i64, vp]
+        _lib = L
+    return _lib
+
+
+def last_error() -> str:
+    return lib().coot_last_error().decode()
+
+
+def _check(rc: int) -> int:
+    if rc < 0:
+        raise CootError(rc, last_error())
+    return rc
+
+
+# ---- marshalling ---------------------------------------------------------
+def _torch():
+    import torch
+
+    return torch
+
+
+def _dtype_code(t) -> int:
+    torch = _torch()
+    m = {torch.float32: F32, torch.float64: F64, torch.float16: F16, torch.bfloat16: BF16, torch.int64: U64}
+    if t.dtype not in m:
+        raise TypeError(f"unsupported tensor dtype {t.dtype}")
+    return m[t.dtype]
+
+
+def operand(t, host: bool = False) -> Operand:
+    """Column-major operand view of a tensor (1-D -> n x 1; 2-D with stride (1, ld))."""
+    if isinstance(t, Operand):
+        return t
+    if t.dim() == 1:
+        if t.numel() > 1 and t.stride(0) != 1:
+            raise ValueError("1-D operands must be contiguous")
+        r, c, ld = t.shape[0], 1, max(1, t.shape[0])
+    elif t.dim() == 2:
+        r, c = t.shape
+        if r > 1 and t.stride(0) != 1:
+            raise ValueError("2-D operands must be column-major (stride (1, ld)), e.g. torch.empty(c, r).t()")
+        ld = t.stride(1) if c > 1 else max(1, r)
+        if r == 1 and c > 1:
+            ld = t.stride(1)
+    else:
+        raise ValueError("operands are vectors or matrices")
+    return Operand(t.data_ptr(), r, c, ld, _dtype_code(t), OPERAND_HOST if host else 0)
+
+
+def fake_operand(n_rows: int, n_cols: int, dtype: str = "f32", ld: Optional[int] = None,
+                 ptr: int = 0x100000, flags: int = 0) -> Operand:
+    """Operand descriptor without memory, for the host-only calls."""
+    return Operand(ptr, n_rows, n_cols, ld if ld is not None else max(1, n_rows), DTYPE_CODES[dtype], flags)
+
+
+def _nodes(tree):
+    if hasattr(tree, "postfix"):
+        tree = tree.postfix()
+    arr = (Node * len(tree))()
+    for i, n in enumerate(tree):
+        if isinstance(n, (tuple, list)):
+            op, a, b, k = (list(n) + [-1, -1, 0.0])[:4]
+        else:
+            op, a, b, k = n.op, n.a, n.b, n.k
+        arr[i].op = OPS[op] if isinstance(op, str) else int(op)
+        arr[i].a = int(a)
+        arr[i].b = int(b)
+        arr[i].k = float(k)
+    return arr
+
+
+def expr(tree, cfg=None, unfused: bool = False):
+    """coot_expr for a tree; keeps the node array alive on the returned object."""
+    nodes = _nodes(tree)
+    e = Expr()
+    e.nodes = C.cast(nodes, C.POINTER(Node))
+    e.n_nodes = len(nodes)
+    e.flags = EXPR_UNFUSED if unfused else 0
+    if cfg is not None:
+        if isinstance(cfg, int):
+            cc = Config()
+            _check(lib().coot_config_of(cfg, C.byref(cc)))
+            cfg = (cc.ept, cc.block, cc.split)
+        e.cfg = Config(cfg[0], cfg[1], cfg[2], 0)
+    e._keep = nodes
+    return e
+
+
+def _ops(operands: Sequence):
+    arr = (Operand * max(1, len(operands)))()
+    for i, t in enumerate(operands):
+        arr[i] = operand(t)
+    return arr, len(operands)
+
+
+def current_stream():
+    torch = _torch()
+    if torch.cuda.is_available():
+        return torch.cuda.current_stream().cuda_stream
+    return None
+
+
+def _red_code(op, pairwise: bool) -> int:
+    c = REDS[op] if isinstance(op, str) else int(op)
+    return c | (RED_PAIRWISE if pairwise else 0)
+
+
+# ---- entry points --------------------------------------------------------
+def init(device: int = 0, print_info: bool = False) -> None:
+    _check(lib().coot_init(device, PRINT_INFO if print_info else 0))
+
+
+def finalize() -> None:
+    _check(lib().coot_finalize())
+
+
+def eval(tree, operands: Sequence, out, cfg=None, unfused: bool = False, stream=None):
+    """out = value of the tree (fused into one kernel unless unfused=True)."""
+    e = expr(tree, cfg, unfused)
+    arr, n = _ops(operands)
+    o = operand(out)
+    _check(lib().coot_eval(C.byref(e), arr, n, C.byref(o), stream if stream is not None else current_stream()))
+    return out
+
+
+def reduce(op, tree, operands: Sequence, out=None, dim: int = -1, pairwise: bool = False, cfg=None,
+           unfused: bool = False, out_dtype=None, stream=None):
+    """Reduction of the tree's value.  Allocates ``out`` on the device if not given
+    (float32/float64 by the tree's precision, int64 for indices)."""
+    torch = _torch()
+    e = expr(tree, cfg, unfused)
+    arr, n = _ops(operands)
+    if out is None:
+        opname = op if isinstance(op, str) else {v: k for k, v in REDS.items()}[op]
+        rows, cols, prec = _root_shape(tree, operands)
+        n_out = 1 if dim < 0 else (cols if dim == 0 else rows)
+        if opname.startswith("index"):
+            dt = torch.int64
+        else:
+            dt = out_dtype or (torch.float64 if prec == 64 else torch.float32)
+        dev = operands[0].device if len(operands) else "cuda"
+        out = torch.empty(n_out, dtype=dt, device=dev)
+    o = operand(out)
+    _check(lib().coot_reduce(_red_code(op, pairwise), dim, C.byref(e), arr, n, C.byref(o),
+                             stream if stream is not None else current_stream()))
+    return out
+
+
+def _root_shape(tree, operands):
+    """Shape and precision of the tree's value (host-side bookkeeping for allocation)."""
+    nodes = tree.postfix() if hasattr(tree, "postfix") else tree
+    info = []
+    for n in nodes:
+        op, a, b = (n.op, n.a, n.b) if not isinstance(n, (tuple, list)) else (n[0], n[1], n[2])
+        if op == "leaf" or op == 0:
+            t = operands[a]
+            r, c = (t.shape[0], 1) if t.dim() == 1 else (t.shape[0], t.shape[1])
+            info.append((r, c, 64 if _dtype_code(t) == F64 else 32))
+        elif op in ("trans", 30):
+            r, c, p = info[a]
+            info.append((c, r, p))
+        elif op in ("conv", 31):
+            r, c, p = info[a]
+            info.append((r, c, 64 if b == F64 else 32))
+        else:
+            info.append(info[a])
+    return info[-1]
+
+
+def synchronise(stream=None) -> None:
+    _check(lib().coot_synchronise(stream if stream is not None else current_stream()))
+
+
+def validate(red_op, dim, tree, operands: Sequence, out) -> int:
+    """Host-only argument checks; returns 0 or raises CootError."""
+    e = expr(tree)
+    arr, n = _ops(operands)
+    o = operand(out)
+    rc = -1 if red_op is None else _red_code(red_op, False)
+    return _check(lib().coot_validate(rc, dim, C.byref(e), arr, n, C.byref(o)))
+
+
+def kernel_source(red_op, dim, tree, operands: Sequence, out, cfg=None) -> str:
+    e = expr(tree, cfg)
+    arr, n = _ops(operands)
+    o = operand(out)
+    rc = -1 if red_op is None else _red_code(red_op, False)
+    size = _check(lib().coot_kernel_source(rc, dim, C.byref(e), arr, n, C.byref(o), None, 0))
+    buf = C.create_string_buffer(size + 1)
+    _check(lib().coot_kernel_source(rc, dim, C.byref(e), arr, n, C.byref(o), buf, size + 1))
+    return buf.value.decode()
+
+
+def precompile(red_op, dim, tree, operands: Sequence, out, cfg=None, pairwise: bool = False) -> int:
+    e = expr(tree, cfg)
+    arr, n = _ops(operands)
+    o = operand(out)
+    rc = -1 if red_op is None else _red_code(red_op, pairwise)
+    return _check(lib().coot_precompile(rc, dim, C.byref(e), arr, n, C.byref(o)))
+
+
+def features(red_op, dim, tree, operands: Sequence, out):
+    import numpy as np
+
+    e = expr(tree)
+    arr, n = _ops(operands)
+    o = operand(out)
+    f = np.zeros(N_FEATURES, np.float32)
+    rc = -1 if red_op is None else _red_code(red_op, False)
+    _check(lib().coot_features(rc, dim, C.byref(e), arr, n, C.byref(o), f.ctypes.data_as(C.POINTER(C.c_float))))
+    return f
+
+
+def autotune(red_op, dim, tree, operands: Sequence, out, reps: int = 5, stream=None):
+    """Time all 64 configurations; returns (best index, times in ms)."""
+    import numpy as np
+
+    e = expr(tree)
+    arr, n = _ops(operands)
+    o = operand(out)
+    t = np.zeros(N_CONFIGS, np.float32)
+    rc = -1 if red_op is None else _red_code(red_op, False)
+    best = _check(lib().coot_autotune(rc, dim, C.byref(e), arr, n, C.byref(o), reps,
+                                      t.ctypes.data_as(C.POINTER(C.c_float)),
+                                      stream if stream is not None else current_stream()))
+    return best, t
+
+
+def config_of(index: int):
+    c = Config()
+    _check(lib().coot_config_of(index, C.byref(c)))
+    return (c.ept, c.block, c.split)
+
+
+def set_tuning(mode: int, model_path: Optional[str] = None) -> None:
+    _check(lib().coot_set_tuning(mode, model_path.encode() if model_path else None))
+
+
+def model_set(params, mean, std) -> None:
+    import numpy as np
+
+    p = np.ascontiguousarray(params, np.float32)
+    m = np.ascontiguousarray(mean, np.float32)
+    s = np.ascontiguousarray(std, np.float32)
+    fp = C.POINTER(C.c_float)
+    _check(lib().coot_model_set(p.ctypes.data_as(fp), m.ctypes.data_as(fp), s.ctypes.data_as(fp)))
+
+
+def model_choose(red_op, dim, tree, operands: Sequence, out) -> int:
+    e = expr(tree)
+    arr, n = _ops(operands)
+    o = operand(out)
+    rc = -1 if red_op is None else _red_code(red_op, False)
+    return _check(lib().coot_model_choose(rc, dim, C.byref(e), arr, n, C.byref(o)))
+
+
+def mlp_forward(params, X, Y, ws=None, stream=None) -> None:
+    B = X.shape[0]
+    _check(lib().coot_mlp_forward(params.data_ptr(), X.data_ptr(), B, Y.data_ptr(),
+                                  ws.data_ptr() if ws is not None else None,
+                                  stream if stream is not None else current_stream()))
+
+
+def mlp_backward(params, X, T, M, grad, loss, ws, stream=None) -> None:
+    B = X.shape[0]
+    _check(lib().coot_mlp_backward(params.data_ptr(), X.data_ptr(), T.data_ptr(), M.data_ptr(), B,
+                                   grad.data_ptr(), loss.data_ptr() if loss is not None else None, ws.data_ptr(),
+                                   stream if stream is not None else current_stream()))
+
+
+def mlp_adam(params, grad, m, v, t: int, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8, stream=None) -> None:
+    _check(lib().coot_mlp_adam(params.data_ptr(), grad.data_ptr(), m.data_ptr(), v.data_ptr(), params.numel(), t,
+                               lr, beta1, beta2, eps, stream if stream is not None else current_stream()))
+
+
+def copy(dst, src, nbytes: Optional[int] = None, stream=None) -> None:
+    n = nbytes if nbytes is not None else src.numel() * src.element_size()
+    _check(lib().coot_copy(dst.data_ptr(), src.data_ptr(), n, stream if stream is not None else current_stream()))
+
+
+def stats() -> dict:
+    s = Stats()
+    _check(lib().coot_get_stats(C.byref(s)))
+    return {k: getattr(s, k) for k, _ in Stats._fields_}
+
+
+# ---- batched evaluation ---------------------------------------------------
+class BatchPlan:
+    """One persistent launch for many matrices (see coot_batch in coot.h)."""
+
+    def __init__(self, tree, slot_dtypes, leaf_ptrs, shapes, out_ptrs=None, out_dtype=F32, red_tree=None,
+                 red_op="accu", red_out=None, red_dtype=F32, flags=0, stream=None):
+        import numpy as np
+
+        self._e = expr(tree)
+        self._re = expr(red_tree) if red_tree is not None else None
+        n_items = len(shapes)
+        n_slots = len(slot_dtypes)
+        self._sd = (C.c_int32 * n_slots)(*slot_dtypes)
+        lp = np.ascontiguousarray(np.asarray(leaf_ptrs, dtype=np.uint64).reshape(-1))
+        self._lp = (C.c_void_p * lp.size)(*[int(x) for x in lp])
+        self._op = None
+        if out_ptrs is not None:
+            self._op = (C.c_void_p * n_items)(*[int(x) for x in out_ptrs])
+        sh = np.ascontiguousarray(np.asarray(shapes, dtype=np.int64).reshape(-1))
+        self._sh = (C.c_int64 * sh.size)(*[int(x) for x in sh])
+        b = Batch()
+        b.expr = C.pointer(self._e)
+        b.n_slots = n_slots
+        b.n_items = n_items
+        b.slot_dtypes = C.cast(self._sd, C.POINTER(C.c_int32))
+        b.leaf_ptrs = C.cast(self._lp, C.POINTER(C.c_void_p))
+        b.out_ptrs = C.cast(self._op, C.POINTER(C.c_void_p)) if self._op is not None else None
+        b.out_dtype = out_dtype
+        b.red_op = _red_code(red_op, False)
+        b.shapes = C.cast(self._sh, C.POINTER(C.c_int64))
+        b.red_expr = C.pointer(self._re) if self._re is not None else None
+        b.red_out = red_out.data_ptr() if red_out is not None else None
+        b.red_dtype = red_dtype
+        b.flags = flags
+        self._b = b
+        self.handle = C.c_void_p()
+        _check(lib().coot_batch_create(C.byref(b), stream if stream is not None else current_stream(),
+                                       C.byref(self.handle)))
+
+    def run(self, stream=None) -> None:
+        _check(lib().coot_batch_run(self.handle, stream if stream is not None else current_stream()))
+
+    def close(self) -> None:
+        if self.handle:
+            _check(lib().coot_batch_destroy(self.handle))
+            self.handle = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

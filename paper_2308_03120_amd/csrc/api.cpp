@@ -1,0 +1,506 @@
+// C ABI entry points: device state, scratch memory, launches.
+//
+// The paper's runtime layer is a singleton (coot_rt_t) of static functions on
+// raw device memory that hides the backend (Section 7).  This file plays that
+// role for one HIP backend: it turns a validated plan into a kernel launch on
+// the caller's stream, owns per-stream scratch memory for the reductions, and
+// implements the two baselines the fused form is measured against (one kernel
+// per node with temporaries; a reduction of a materialised value).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdio>
+#include <cstring>
+#include <mutex>
+#include <new>
+#include <string>
+#include <unordered_map>
+#include <vector>
+
+#include "internal.h"
+#include "jit.h"
+#include "runtime.h"
+
+namespace coot {
+
+static thread_local std::string t_err;
+
+[[noreturn]] void fail(int code, const std::string& msg) { throw Error{code, msg}; }
+void set_error(int, const std::string& msg) { t_err = msg; }
+
+State g_state;
+
+template <class F>
+static int guard(F&& f)
+{
+    try {
+        return f();
+    } catch (const Error& e) {
+        t_err = e.msg;
+        return e.code;
+    } catch (const std::bad_alloc&) {
+        t_err = "out of host memory";
+        return COOT_ERR_NOMEM;
+    } catch (const std::exception& e) {
+        t_err = e.what();
+        return COOT_ERR_ARG;
+    }
+}
+
+void hipchk(hipError_t e, const char* what)
+{
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        fail(e == hipErrorOutOfMemory ? COOT_ERR_NOMEM : COOT_ERR_HIP, std::string(what) + ": " + hipGetErrorString(e));
+    }
+}
+
+static void init_device(int device, unsigned flags)
+{
+    std::lock_guard<std::mutex> lk(g_state.mu);
+    if (g_state.init && g_state.device == device) return;
+    int n = 0;
+    hipError_t e = hipGetDeviceCount(&n);
+    if (e != hipSuccess || n == 0) {
+        (void)hipGetLastError();
+        fail(COOT_ERR_HIP, "no HIP device available");
+    }
+    if (device < 0 || device >= n) fail(COOT_ERR_ARG, "device index out of range");
+    hipchk(hipSetDevice(device), "hipSetDevice");
+    hipDeviceProp_t prop;
+    hipchk(hipGetDeviceProperties(&prop, device), "hipGetDeviceProperties");
+    g_state.device = device;
+    g_state.cus = prop.multiProcessorCount > 0 ? prop.multiProcessorCount : 256;
+    g_state.name = prop.name;
+    g_state.arch = prop.gcnArchName;
+    g_state.hbm = prop.totalGlobalMem;
+    g_state.clock_khz = prop.clockRate;
+    g_state.init = true;
+    if (flags & COOT_PRINT_INFO) {
+        printf("coot: device %d: %s (%s), %d CUs, %.0f MHz, %.1f GiB HBM, kernel cache %s\n", device, prop.name,
+               prop.gcnArchName, g_state.cus, prop.clockRate / 1000.0, prop.totalGlobalMem / 1073741824.0,
+               cache_dir().c_str());
+        fflush(stdout);
+    }
+}
+
+void ensure_init()
+{
+    if (g_state.init) return;
+    int d = 0;
+    hipchk(hipGetDevice(&d), "hipGetDevice");
+    init_device(d, 0);
+}
+
+Scratch& scratch_for(hipStream_t st, size_t part_bytes, size_t res_bytes, size_t n_counters)
+{
+    std::lock_guard<std::mutex> lk(g_state.mu);
+    Scratch& s = g_state.scratch[st];
+    if (s.part_bytes < part_bytes) {
+        if (s.part) {
+            hipchk(hipStreamSynchronize(st), "hipStreamSynchronize");
+            (void)hipFree(s.part);
+            s.part = nullptr;
+        }
+        size_t want = std::max<size_t>(part_bytes, 1 << 20);
+        hipchk(hipMalloc(&s.part, want), "hipMalloc(scratch)");
+        s.part_bytes = want;
+    }
+    if (s.res_bytes < res_bytes) {
+        if (s.res) {
+            hipchk(hipStreamSynchronize(st), "hipStreamSynchronize");
+            (void)hipFree(s.res);
+            s.res = nullptr;
+        }
+        size_t want = std::max<size_t>(res_bytes, 4096);
+        hipchk(hipMalloc(&s.res, want), "hipMalloc(result)");
+        s.res_bytes = want;
+    }
+    if (s.n_counters < n_counters) {
+        if (s.counters) {
+            hipchk(hipStreamSynchronize(st), "hipStreamSynchronize");
+            (void)hipFree(s.counters);
+            s.counters = nullptr;
+        }
+        size_t want = std::max<size_t>(n_counters, 64);
+        hipchk(hipMalloc((void**)&s.counters, want * sizeof(unsigned)), "hipMalloc(counters)");
+        hipchk(hipMemset(s.counters, 0, want * sizeof(unsigned)), "hipMemset(counters)");
+        s.n_counters = want;
+    }
+    return s;
+}
+
+static int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
+int64_t grid_cap(const LaunchCfg& c) { return (int64_t)g_state.cus * std::max(1, (256 * c.split) / c.block); }
+
+void launch(hipFunction_t f, int64_t grid, int block, coot_kargs& a, hipStream_t st)
+{
+    if (grid < 1) grid = 1;
+    if (grid > 0x7fffffff) fail(COOT_ERR_ARG, "grid too large");
+    void* params[] = {&a};
+    hipchk(hipModuleLaunchKernel(f, (unsigned)grid, 1, 1, (unsigned)block, 1, 1, 0, st, params, nullptr),
+           "hipModuleLaunchKernel");
+    g_state.launches++;
+}
+
+std::string tune_key(const Plan& p)
+{
+    int lg = 0;
+    while (lg < 62 && (int64_t(1) << (lg + 1)) <= p.n) ++lg;
+    return std::to_string(p.kind) + "|" + std::to_string(p.ve) + "|" + std::to_string(p.red_op) + "|" +
+           std::to_string(p.pairwise) + "|" + std::to_string(p.out_dtype) + "|" + p.body_sig + "|n" + std::to_string(lg);
+}
+
+LaunchCfg choose_config(const Plan& p, const coot_config& user)
+{
+    if (user.ept) return LaunchCfg{user.ept, user.block, user.split};
+    if (g_state.tune_mode != COOT_TUNE_DEFAULT) {
+        std::lock_guard<std::mutex> lk(g_state.mu);
+        auto it = g_state.tuned.find(tune_key(p));
+        if (it != g_state.tuned.end()) return config_of(it->second);
+    }
+    if (g_state.tune_mode == COOT_TUNE_MODEL && g_state.model_ok) {
+        int idx = model_pick(p);
+        if (idx >= 0) return config_of(idx);
+    }
+    return default_config(p);
+}
+
+// grid, block and second-launch details for a plan
+struct Geometry {
+    int64_t grid;
+    int block;
+    int64_t splits;
+    int64_t comb_grid;
+    size_t part_bytes;
+};
+
+static Geometry geometry(const Plan& p, const LaunchCfg& c)
+{
+    Geometry G{1, c.block, 1, 0, 0};
+    const int64_t cap = grid_cap(c);
+    switch (p.kind) {
+    case K_EW_FLAT:
+    case K_RED_FLAT: {
+        int64_t nv = p.n / p.ve;
+        G.grid = std::max<int64_t>(1, std::min(ceil_div(nv, (int64_t)c.block * c.ept), cap));
+        if (p.kind == K_RED_FLAT) G.grid = std::min<int64_t>(G.grid, 8192);
+        break;
+    }
+    case K_EW_TILED:
+    case K_RED_TILED: {
+        int64_t nt = ceil_div(p.rows, 64) * ceil_div(p.cols, 64);
+        G.block = 256;
+        G.grid = std::max<int64_t>(1, std::min(nt, (int64_t)g_state.cus * c.split));
+        break;
+    }
+    case K_RED_COL:
+        G.grid = std::max<int64_t>(1, std::min(ceil_div(p.cols * 64, c.block), cap));
+        break;
+    case K_RED_COLT:
+        G.grid = std::max<int64_t>(1, std::min(ceil_div(p.cols, c.block), cap));
+        break;
+    case K_RED_ROW: {
+        int64_t target = (int64_t)g_state.cus * 1024;
+        int64_t q = std::max<int64_t>(1, ceil_div(target, std::max<int64_t>(1, p.rows)));
+        q = std::min<int64_t>(q, std::min<int64_t>(std::max<int64_t>(1, p.cols), 65536));
+        G.splits = q;
+        G.grid = std::max<int64_t>(1, std::min(ceil_div(p.rows * q, c.block), cap));
+        if (q > 1) {
+            G.comb_grid = std::min<int64_t>(p.rows, (int64_t)g_state.cus * 16);
+            G.part_bytes = (size_t)(p.rows * q) * 16;
+        }
+        break;
+    }
+    }
+    if (p.kind == K_RED_FLAT || p.kind == K_RED_TILED) G.part_bytes = (size_t)G.grid * 16;
+    return G;
+}
+
+static void fill_reads(const Plan& p, const coot_operand* ops, coot_kargs& a)
+{
+    for (size_t j = 0; j < p.reads.size(); ++j) {
+        a.leaf[j] = ops[p.reads[j].slot].ptr;
+        a.ld[j] = p.reads[j].ld;
+    }
+}
+
+// One fused launch (two for split per-row reductions) of a plan.
+void run_plan(const Plan& p, const LaunchCfg& cfg_in, const coot_operand* ops, const coot_operand* out,
+              hipStream_t st)
+{
+    LaunchCfg c = normalise_config(p, cfg_in);
+    std::string name;
+    std::string src = kernel_source(p, c, &name, nullptr);
+    Kernel k = get_kernel(name, src, p.kind == K_RED_ROW);
+    Geometry G = geometry(p, c);
+    coot_kargs a;
+    std::memset(&a, 0, sizeof a);
+    fill_reads(p, ops, a);
+    a.rows = p.rows;
+    a.cols = p.cols;
+    a.n = p.n;
+    a.splits = G.splits;
+    if (p.red_op < 0) {
+        a.out = out->ptr;
+        a.ld_out = out->ld;
+        launch(k.fn, G.grid, G.block, a, st);
+        return;
+    }
+    const int64_t n_out = p.dim < 0 ? 1 : (p.dim == 0 ? p.cols : p.rows);
+    const bool host = (out->flags & COOT_OPERAND_HOST) != 0;
+    const size_t res_bytes = (size_t)n_out * 8;
+    Scratch& s = scratch_for(st, G.part_bytes, host ? res_bytes : 0, 1);
+    a.part = s.part;
+    a.counter = s.counters;
+    a.res = host ? s.res : out->ptr;
+    launch(k.fn, G.grid, G.block, a, st);
+    if (p.kind == K_RED_ROW && G.splits > 1) launch(k.fn2, G.comb_grid, 256, a, st);
+    if (host) {
+        hipchk(hipMemcpyAsync(out->ptr, s.res, res_bytes / 8 * (size_t)itemsize(out->dtype), hipMemcpyDeviceToHost, st),
+               "hipMemcpyAsync");
+        hipchk(hipStreamSynchronize(st), "hipStreamSynchronize");
+    }
+}
+
+// device temporaries for the unfused and materialising paths
+struct Temp {
+    void* p = nullptr;
+    hipStream_t st = nullptr;
+    Temp() = default;
+    Temp(const Temp&) = delete;
+    ~Temp()
+    {
+        if (p) (void)hipFreeAsync(p, st);
+    }
+    void alloc(size_t bytes, hipStream_t s)
+    {
+        st = s;
+        hipchk(hipMallocAsync(&p, std::max<size_t>(bytes, 16), s), "hipMallocAsync(temporary)");
+    }
+};
+
+static int do_eval(const coot_expr* expr, const coot_operand* ops, int n_ops, const coot_operand* out, hipStream_t st);
+static int do_reduce(int red_op, int dim, const coot_expr* expr, const coot_operand* ops, int n_ops,
+                     const coot_operand* out, hipStream_t st);
+
+// The paper's evaluation order: every node's apply() runs its own kernel and
+// writes a temporary (Section 7).  Used as the unfused baseline.
+static int run_unfused(int red_op, int dim, const coot_expr* expr, const coot_operand* ops, int n_ops,
+                       const coot_operand* out, hipStream_t st)
+{
+    const int nn = expr->n_nodes;
+    std::vector<coot_operand> val(nn);
+    std::vector<Temp> tmp(nn);
+    // shapes and precisions of the user's nodes
+    std::vector<int64_t> R(nn), C(nn);
+    std::vector<int> prec(nn);
+    for (int i = 0; i < nn; ++i) {
+        const coot_node& N = expr->nodes[i];
+        if (N.op == COOT_LEAF) {
+            val[i] = ops[N.a];
+            R[i] = ops[N.a].n_rows;
+            C[i] = ops[N.a].n_cols;
+            prec[i] = ops[N.a].dtype == COOT_F64 ? 64 : 32;
+            continue;
+        }
+        R[i] = N.op == COOT_TRANS ? C[N.a] : R[N.a];
+        C[i] = N.op == COOT_TRANS ? R[N.a] : C[N.a];
+        prec[i] = N.op == COOT_CONV ? (N.b == COOT_F64 ? 64 : 32) : prec[N.a];
+        bool last = i == nn - 1;
+        coot_node mini[3];
+        int m = 0, nops = 0;
+        coot_operand mops[2];
+        mini[m++] = coot_node{COOT_LEAF, 0, -1, 0, 0.0};
+        mops[nops++] = val[N.a];
+        int bidx = -1;
+        if (N.op >= COOT_PLUS && N.op <= COOT_DIV) {
+            mini[m++] = coot_node{COOT_LEAF, 1, -1, 0, 0.0};
+            mops[nops++] = val[N.b];
+            bidx = 1;
+        }
+        mini[m] = coot_node{N.op, 0, N.op == COOT_CONV ? N.b : bidx, 0, N.k};
+        m++;
+        coot_expr me{mini, m, 0, expr->cfg};
+        if (last && red_op < 0) return do_eval(&me, mops, nops, out, st);
+        int dt = prec[i] == 64 ? COOT_F64 : COOT_F32;
+        if (N.op == COOT_CONV && (N.b == COOT_F16 || N.b == COOT_BF16)) dt = N.b;
+        tmp[i].alloc((size_t)(R[i] * C[i]) * itemsize(dt), st);
+        val[i] = coot_operand{tmp[i].p, R[i], C[i], std::max<int64_t>(1, R[i]), dt, 0};
+        int rc = do_eval(&me, mops, nops, &val[i], st);
+        if (rc) return rc;
+    }
+    if (red_op < 0) {  // the root is a leaf: plain copy through a one-node kernel
+        coot_node one{COOT_LEAF, 0, -1, 0, 0.0};
+        coot_expr me{&one, 1, 0, expr->cfg};
+        return do_eval(&me, &val[nn - 1], 1, out, st);
+    }
+    int base = red_op & 0xff;
+    int flags = red_op & COOT_RED_PAIRWISE;
+    if (base == COOT_RED_DOT) base = COOT_RED_ACCU;
+    coot_node one{COOT_LEAF, 0, -1, 0, 0.0};
+    coot_expr me{&one, 1, 0, expr->cfg};
+    return do_reduce(base | flags, dim, &me, &val[nn - 1], 1, out, st);
+}
+
+static int do_eval(const coot_expr* expr, const coot_operand* ops, int n_ops, const coot_operand* out, hipStream_t st)
+{
+    Plan p = make_plan(-1, -1, expr, ops, n_ops, out);
+    ensure_init();
+    if (expr->flags & COOT_EXPR_UNFUSED) return run_unfused(-1, -1, expr, ops, n_ops, out, st);
+    if (p.n == 0) return COOT_OK;
+    run_plan(p, choose_config(p, expr->cfg), ops, out, st);
+    return COOT_OK;
+}
+
+static int do_reduce(int red_op, int dim, const coot_expr* expr, const coot_operand* ops, int n_ops,
+                     const coot_operand* out, hipStream_t st)
+{
+    Plan p = make_plan(red_op, dim, expr, ops, n_ops, out);
+    ensure_init();
+    if (expr->flags & COOT_EXPR_UNFUSED) return run_unfused(red_op, dim, expr, ops, n_ops, out, st);
+    const int64_t n_out = p.dim < 0 ? 1 : (p.dim == 0 ? p.cols : p.rows);
+    if (n_out == 0) return COOT_OK;
+    if (p.temp_needed) {
+        // per-dimension reduction of a tree that reads an operand transposed:
+        // materialise the value once, then reduce it
+        Temp t;
+        int dt = p.root_prec == 64 ? COOT_F64 : COOT_F32;
+        t.alloc((size_t)p.n * itemsize(dt), st);
+        coot_operand tv{t.p, p.rows, p.cols, std::max<int64_t>(1, p.rows), dt, 0};
+        coot_expr e2 = *expr;
+        e2.flags = 0;
+        int rc = do_eval(&e2, ops, n_ops, &tv, st);
+        if (rc) return rc;
+        coot_node one{COOT_LEAF, 0, -1, 0, 0.0};
+        coot_expr me{&one, 1, 0, expr->cfg};
+        return do_reduce(red_op == COOT_RED_DOT ? COOT_RED_ACCU : red_op, dim, &me, &tv, 1, out, st);
+    }
+    run_plan(p, choose_config(p, expr->cfg), ops, out, st);
+    return COOT_OK;
+}
+
+}  // namespace coot
+
+using namespace coot;
+
+extern "C" {
+
+int coot_init(int device, unsigned flags)
+{
+    return guard([&] {
+        init_device(device, flags);
+        return COOT_OK;
+    });
+}
+
+int coot_finalize(void)
+{
+    return guard([&] {
+        if (!g_state.init) return COOT_OK;
+        (void)hipDeviceSynchronize();
+        {
+            std::lock_guard<std::mutex> lk(g_state.mu);
+            for (auto& kv : g_state.scratch) {
+                if (kv.second.part) (void)hipFree(kv.second.part);
+                if (kv.second.res) (void)hipFree(kv.second.res);
+                if (kv.second.counters) (void)hipFree(kv.second.counters);
+            }
+            g_state.scratch.clear();
+        }
+        batch_destroy_all();
+        jit_unload_all();
+        g_state.init = false;
+        return COOT_OK;
+    });
+}
+
+int coot_eval(const coot_expr* expr, const coot_operand* ops, int n_ops, const coot_operand* out, void* stream)
+{
+    return guard([&] { return do_eval(expr, ops, n_ops, out, (hipStream_t)stream); });
+}
+
+int coot_reduce(int red_op, int dim, const coot_expr* expr, const coot_operand* ops, int n_ops,
+                const coot_operand* out, void* stream)
+{
+    return guard([&] {
+        if (red_op < 0) fail(COOT_ERR_ARG, "red_op must be a COOT_RED_* value");
+        return do_reduce(red_op, dim, expr, ops, n_ops, out, (hipStream_t)stream);
+    });
+}
+
+int coot_synchronise(void* stream)
+{
+    return guard([&] {
+        hipchk(hipStreamSynchronize((hipStream_t)stream), "hipStreamSynchronize");
+        return COOT_OK;
+    });
+}
+
+const char* coot_last_error(void) { return t_err.c_str(); }
+
+int coot_validate(int red_op, int dim, const coot_expr* expr, const coot_operand* ops, int n_ops,
+                  const coot_operand* out)
+{
+    return guard([&] {
+        make_plan(red_op, dim, expr, ops, n_ops, out);
+        return COOT_OK;
+    });
+}
+
+int64_t coot_kernel_source(int red_op, int dim, const coot_expr* expr, const coot_operand* ops, int n_ops,
+                           const coot_operand* out, char* buf, int64_t cap)
+{
+    int64_t result = 0;
+    int rc = guard([&] {
+        Plan p = make_plan(red_op, dim, expr, ops, n_ops, out);
+        LaunchCfg c = expr->cfg.ept ? LaunchCfg{expr->cfg.ept, expr->cfg.block, expr->cfg.split} : default_config(p);
+        std::string src = prelude_source() + "\n" + kernel_source(p, normalise_config(p, c), nullptr, nullptr);
+        if (buf && cap > 0) {
+            int64_t m = std::min<int64_t>(cap - 1, (int64_t)src.size());
+            std::memcpy(buf, src.data(), (size_t)m);
+            buf[m] = '\0';
+        }
+        result = (int64_t)src.size();
+        return COOT_OK;
+    });
+    return rc ? rc : result;
+}
+
+int coot_precompile(int red_op, int dim, const coot_expr* expr, const coot_operand* ops, int n_ops,
+                    const coot_operand* out)
+{
+    return guard([&] {
+        Plan p = make_plan(red_op, dim, expr, ops, n_ops, out);
+        LaunchCfg c = expr->cfg.ept ? LaunchCfg{expr->cfg.ept, expr->cfg.block, expr->cfg.split} : default_config(p);
+        std::string name;
+        std::string src = kernel_source(p, normalise_config(p, c), &name, nullptr);
+        return precompile_kernel(name, src);
+    });
+}
+
+int coot_get_stats(coot_stats* s)
+{
+    return guard([&] {
+        if (!s) fail(COOT_ERR_ARG, "stats is NULL");
+        s->launches = g_state.launches;
+        s->jit_compiles = g_jit_stats.compiles;
+        s->jit_disk_hits = g_jit_stats.disk_hits;
+        s->jit_mem_hits = g_jit_stats.mem_hits;
+        s->jit_seconds = g_jit_stats.seconds;
+        return COOT_OK;
+    });
+}
+
+int coot_config_of(int index, coot_config* cfg)
+{
+    return guard([&] {
+        if (index < 0 || index >= COOT_N_CONFIGS || !cfg) fail(COOT_ERR_ARG, "config index out of range");
+        LaunchCfg c = config_of(index);
+        *cfg = coot_config{c.ept, c.block, c.split, 0};
+        return COOT_OK;
+    });
+}
+
+}  // extern "C"

@@ -1,0 +1,469 @@
+// HIP source generation: one kernel per (tree signature, kind, configuration).
+//
+// The paper's library launches at least one kernel per node and keeps a
+// temporary between nodes (Section 7: each op_type::apply calls one or more
+// GPU kernels; generating code per expression is named as not yet possible).
+// Here the whole tree becomes the body of a single kernel: every distinct
+// operand is read once, the tree is evaluated in registers, and the result is
+// either stored once or folded into a reduction accumulator.
+#include <cmath>
+#include <cstdio>
+#include <sstream>
+
+#include "internal.h"
+
+extern "C" const char* coot_prelude_text;
+
+namespace coot {
+
+std::string prelude_source() { return coot_prelude_text; }
+
+static const char* ctype(int prec) { return prec == 64 ? "double" : "float"; }
+
+static const char* stype(int dt)
+{
+    switch (dt) {
+    case COOT_F32: return "float";
+    case COOT_F64: return "double";
+    default: return "u16";
+    }
+}
+
+static std::string widen(int dt, const std::string& e)
+{
+    if (dt == COOT_F16) return "widen_f16(" + e + ")";
+    if (dt == COOT_BF16) return "widen_bf16(" + e + ")";
+    return e;
+}
+
+// root value (compute precision prec) -> bits of the output storage type
+static std::string narrow(int out_dt, int prec, const std::string& e)
+{
+    switch (out_dt) {
+    case COOT_F32: return prec == 64 ? "(float)(" + e + ")" : e;
+    case COOT_F64: return "(double)(" + e + ")";
+    case COOT_F16: return (prec == 64 ? "bits_f16_d(" : "bits_f16(") + e + ")";
+    case COOT_BF16: return (prec == 64 ? "bits_bf16_d(" : "bits_bf16(") + e + ")";
+    }
+    return e;
+}
+
+static std::string lit(double k, int prec)
+{
+    char b[64];
+    if (prec == 32) {
+        if (std::isnan(k)) return "__builtin_nanf(\"\")";
+        if (std::isinf(k)) return k > 0 ? "__builtin_inff()" : "(-__builtin_inff())";
+        snprintf(b, sizeof b, "(%af)", (double)(float)k);
+    } else {
+        if (std::isnan(k)) return "__builtin_nan(\"\")";
+        if (std::isinf(k)) return k > 0 ? "__builtin_inf()" : "(-__builtin_inf())";
+        snprintf(b, sizeof b, "(%a)", k);
+    }
+    return b;
+}
+
+// The element function: arguments are the widened values of the reads.
+// pair = true emits x_pair(...) returning the two children of the root
+// product instead of the product itself (exact TwoProduct in the reduction).
+static std::string emit_eval(const Plan& p, bool pair)
+{
+    std::ostringstream s;
+    std::ostringstream args;
+    for (size_t j = 0; j < p.reads.size(); ++j) {
+        if (j) args << ", ";
+        args << ctype(p.reads[j].dtype == COOT_F64 ? 64 : 32) << " l" << j;
+    }
+    const int rp = p.nodes[p.root].prec;
+    if (pair)
+        s << "CD void x_pair(" << args.str() << (p.reads.empty() ? "" : ", ") << ctype(rp) << "& pa, " << ctype(rp)
+          << "& pb)\n{\n";
+    else
+        s << "CD " << ctype(rp) << " x_eval(" << args.str() << ")\n{\n";
+    for (size_t i = 0; i < p.nodes.size(); ++i) {
+        const PNode& n = p.nodes[i];
+        if (pair && (int)i == p.root) continue;
+        const char* T = ctype(n.prec);
+        const bool f = n.prec == 32;
+        std::string a = n.a >= 0 ? "t" + std::to_string(n.a) : "";
+        std::string b = n.b >= 0 ? "t" + std::to_string(n.b) : "";
+        std::string k = lit(n.k, n.prec);
+        std::string e;
+        switch (n.op) {
+        case COOT_LEAF: e = "l" + std::to_string(n.a); break;
+        case COOT_PLUS: e = a + " + " + b; break;
+        case COOT_MINUS: e = a + " - " + b; break;
+        case COOT_SCHUR: e = a + " * " + b; break;
+        case COOT_DIV: e = a + " / " + b; break;
+        case COOT_SCAL_PLUS: e = a + " + " + k; break;
+        case COOT_SCAL_MINUS_POST: e = a + " - " + k; break;
+        case COOT_SCAL_MINUS_PRE: e = k + " - " + a; break;
+        case COOT_SCAL_TIMES: e = a + " * " + k; break;
+        case COOT_SCAL_DIV_POST: e = a + " / " + k; break;
+        case COOT_SCAL_DIV_PRE: e = k + " / " + a; break;
+        case COOT_EXP: e = std::string(f ? "expf(" : "exp(") + a + ")"; break;
+        case COOT_LOG: e = std::string(f ? "logf(" : "log(") + a + ")"; break;
+        case COOT_SQRT: e = std::string(f ? "sqrtf(" : "sqrt(") + a + ")"; break;
+        case COOT_ABS: e = std::string(f ? "__builtin_fabsf(" : "__builtin_fabs(") + a + ")"; break;
+        case COOT_CONV: {
+            const int cp = p.nodes[n.a].prec;
+            switch (n.conv) {
+            case COOT_F32: e = cp == 64 ? "(float)" + a : a; break;
+            case COOT_F64: e = "(double)" + a; break;
+            case COOT_F16: e = (cp == 64 ? "rnd_f16_d(" : "rnd_f16(") + a + ")"; break;
+            case COOT_BF16: e = (cp == 64 ? "rnd_bf16_d(" : "rnd_bf16(") + a + ")"; break;
+            }
+            break;
+        }
+        }
+        s << "    const " << T << " t" << i << " = " << e << ";\n";
+    }
+    if (pair)
+        s << "    pa = t" << p.prod_a << ";\n    pb = t" << p.prod_b << ";\n}\n";
+    else
+        s << "    return t" << p.root << ";\n}\n";
+    return s.str();
+}
+
+// --- reduction helpers ------------------------------------------------------
+static bool red_is_sum(int r)
+{
+    return r == COOT_RED_ACCU || r == COOT_RED_SUM || r == COOT_RED_DOT || r == COOT_RED_NORM1 || r == COOT_RED_NORM2;
+}
+
+static bool red_is_max(int r) { return r == COOT_RED_MAX || r == COOT_RED_INDEX_MAX || r == COOT_RED_NORMINF; }
+
+static std::string acc_type(const Plan& p)
+{
+    const int rp = p.nodes[p.root].prec;
+    if (red_is_sum(p.red_op)) {
+        if (rp == 64) return "AccKD";
+        return p.pairwise ? "AccPF" : "AccKF";
+    }
+    return std::string("AccI<") + ctype(rp) + (red_is_max(p.red_op) ? ", true>" : ", false>");
+}
+
+// statement adding the tree's value at linear index `gi` to `acc`
+static std::string accumulate(const Plan& p, const std::string& args, const std::string& gi)
+{
+    const int rp = p.nodes[p.root].prec;
+    const std::string fab = rp == 64 ? "__builtin_fabs" : "__builtin_fabsf";
+    const std::string C = ctype(rp);
+    if (p.product_form)
+        return "{ " + C + " pa, pb; x_pair(" + args + (p.reads.empty() ? "" : ", ") + "pa, pb); acc.add_prod(pa, pb); }";
+    switch (p.red_op) {
+    case COOT_RED_ACCU:
+    case COOT_RED_SUM:
+    case COOT_RED_DOT: return "acc.add(x_eval(" + args + "));";
+    case COOT_RED_NORM1: return "acc.add(" + fab + "(x_eval(" + args + ")));";
+    case COOT_RED_NORM2: return "{ const " + C + " t = x_eval(" + args + "); acc.add_prod(t, t); }";
+    case COOT_RED_NORMINF:
+    case COOT_RED_NORMNEGINF: return "acc.add(" + fab + "(x_eval(" + args + ")), " + gi + ");";
+    default: return "acc.add(x_eval(" + args + "), " + gi + ");";
+    }
+}
+
+static std::string put_value(const Plan& p, const std::string& where, const std::string& v)
+{
+    return std::string(p.out_dtype == COOT_F64 ? "put_f64(" : "put_f32(") + "a.res, " + where + ", " + v + ");";
+}
+
+// statements writing result `j` straight from a per-thread/wave accumulator
+static std::string write_direct(const Plan& p, const std::string& j)
+{
+    if (red_is_sum(p.red_op)) {
+        std::string v = "(acc.hi() + acc.lo())";
+        if (p.red_op == COOT_RED_NORM2) v = "__builtin_sqrt" + v;
+        return put_value(p, j, v);
+    }
+    if (p.red_op == COOT_RED_INDEX_MIN || p.red_op == COOT_RED_INDEX_MAX) return "put_u64(a.res, " + j + ", acc.i);";
+    return put_value(p, j, "(acc.i < 0 ? __builtin_nan(\"\") : (double)acc.v)");
+}
+
+static std::string put_partial(const Plan& p, const std::string& slot)
+{
+    if (red_is_sum(p.red_op)) return "put_sum_partial((double*)a.part, " + slot + ", acc.hi(), acc.lo());";
+    return "put_idx_partial((double*)a.part, " + slot + ", (double)acc.v, acc.i);";
+}
+
+// statements combining `count` partials (first, stride) and writing result j (thread 0)
+static std::string combine_and_write(const Plan& p, const std::string& first, const std::string& count,
+                                     const std::string& stride, const std::string& j)
+{
+    std::ostringstream s;
+    if (red_is_sum(p.red_op)) {
+        s << "{ const double v = combine_sums((const double*)a.part, " << first << ", " << count << ", " << stride
+          << "); if (threadIdx.x == 0) "
+          << put_value(p, j, p.red_op == COOT_RED_NORM2 ? "__builtin_sqrt(v)" : "v") << " }";
+    } else {
+        s << "{ const AccI<double, " << (red_is_max(p.red_op) ? "true" : "false") << "> r = combine_idx<"
+          << (red_is_max(p.red_op) ? "true" : "false") << ">((const double*)a.part, " << first << ", " << count << ", "
+          << stride << "); if (threadIdx.x == 0) { ";
+        if (p.red_op == COOT_RED_INDEX_MIN || p.red_op == COOT_RED_INDEX_MAX)
+            s << "put_u64(a.res, " << j << ", r.i);";
+        else
+            s << put_value(p, j, "(r.i < 0 ? __builtin_nan(\"\") : r.v)");
+        s << " } }";
+    }
+    return s.str();
+}
+
+// --- common declarations ----------------------------------------------------
+static std::string decl_reads(const Plan& p, bool restrict_ok)
+{
+    std::ostringstream s;
+    for (size_t j = 0; j < p.reads.size(); ++j) {
+        const char* S = stype(p.reads[j].dtype);
+        s << "    const " << S << "* " << (restrict_ok ? "__restrict__ " : "") << "L" << j << " = (const " << S
+          << "*)a.leaf[" << j << "];\n";
+        s << "    const i64 ld" << j << " = a.ld[" << j << "];\n";
+    }
+    return s.str();
+}
+
+// argument list from per-read expressions
+template <class F>
+static std::string arglist(const Plan& p, F f)
+{
+    std::string s;
+    for (size_t j = 0; j < p.reads.size(); ++j) {
+        if (j) s += ", ";
+        s += widen(p.reads[j].dtype, f((int)j));
+    }
+    return s;
+}
+
+// --- flat kinds: linear index, VE-element vectors, grid-stride loop ----------
+static std::string emit_flat(const Plan& p, const LaunchCfg& c, const std::string& name)
+{
+    const bool ew = p.kind == K_EW_FLAT;
+    const int VE = p.ve, EPT = c.ept;
+    const std::string OS = ew ? stype(p.out_dtype) : "";
+    const int rp = p.nodes[p.root].prec;
+    std::ostringstream s;
+    s << "extern \"C\" __global__ void __launch_bounds__(512) " << name << "(const coot_kargs a)\n{\n";
+    s << decl_reads(p, !p.alias_out);
+    if (ew) s << "    " << OS << "* " << (p.alias_out ? "" : "__restrict__ ") << "O = (" << OS << "*)a.out;\n";
+    else s << "    " << acc_type(p) << " acc;\n    acc.init();\n";
+    s << "    const i64 nv = a.n / " << VE << ";\n";
+    s << "    const i64 bs = blockDim.x;\n";
+    s << "    const i64 step = (i64)gridDim.x * bs * " << EPT << ";\n";
+    s << "    for (i64 base = (i64)blockIdx.x * bs * " << EPT << " + threadIdx.x; base < nv; base += step) {\n";
+    for (size_t j = 0; j < p.reads.size(); ++j)
+        s << "        " << stype(p.reads[j].dtype) << " r" << j << "[" << EPT << "][" << VE << "];\n";
+    s << "#pragma unroll\n        for (int e = 0; e < " << EPT << "; ++e) {\n";
+    s << "            const i64 v = base + e * bs;\n            if (v < nv) {\n";
+    for (size_t j = 0; j < p.reads.size(); ++j)
+        s << "                ldv<" << stype(p.reads[j].dtype) << ", " << VE << ">(L" << j << ", v * " << VE << ", r" << j
+          << "[e]);\n";
+    s << "            }\n        }\n";
+    s << "#pragma unroll\n        for (int e = 0; e < " << EPT << "; ++e) {\n";
+    s << "            const i64 v = base + e * bs;\n            if (v < nv) {\n";
+    std::string args = arglist(p, [](int j) { return "r" + std::to_string(j) + "[e][k]"; });
+    if (ew) {
+        s << "                " << OS << " o[" << VE << "];\n";
+        s << "#pragma unroll\n                for (int k = 0; k < " << VE << "; ++k) o[k] = "
+          << narrow(p.out_dtype, rp, "x_eval(" + args + ")") << ";\n";
+        s << "                stv<" << OS << ", " << VE << ">(O, v * " << VE << ", o);\n";
+    } else {
+        s << "#pragma unroll\n                for (int k = 0; k < " << VE << "; ++k) { const i64 gi = v * " << VE
+          << " + k; (void)gi; " << accumulate(p, args, "gi") << " }\n";
+    }
+    s << "            }\n        }\n    }\n";
+    // tail elements that do not fill a vector
+    std::string targs = arglist(p, [](int j) { return "L" + std::to_string(j) + "[i]"; });
+    s << "    if (blockIdx.x == gridDim.x - 1)\n";
+    s << "        for (i64 i = nv * " << VE << " + threadIdx.x; i < a.n; i += bs) ";
+    if (ew) s << "O[i] = " << narrow(p.out_dtype, rp, "x_eval(" + targs + ")") << ";\n";
+    else s << "{ " << accumulate(p, targs, "i") << " }\n";
+    if (!ew) {
+        s << "    __shared__ " << acc_type(p) << " lds_acc[8];\n";
+        s << "    acc = block_reduce(acc, lds_acc);\n";
+        s << "    if (threadIdx.x == 0) " << put_partial(p, "blockIdx.x") << "\n";
+        s << "    if (arrive_last(a.counter, gridDim.x)) {\n        "
+          << combine_and_write(p, "0", "gridDim.x", "1", "0") << "\n        counter_reset(a.counter);\n    }\n";
+    }
+    s << "}\n";
+    return s.str();
+}
+
+// --- tiled kinds: 64x64 tiles, transposed reads staged through LDS ----------
+static std::string emit_tiled(const Plan& p, const std::string& name)
+{
+    const bool ew = p.kind == K_EW_TILED;
+    const int rp = p.nodes[p.root].prec;
+    std::ostringstream s;
+    // which transposed reads get an LDS tile (budget 96 KiB)
+    std::vector<bool> in_lds(p.reads.size(), false);
+    int budget = 96 * 1024;
+    bool any_lds = false;
+    for (size_t j = 0; j < p.reads.size(); ++j) {
+        if (!p.reads[j].trans) continue;
+        int bytes = 64 * 65 * (p.reads[j].dtype == COOT_F64 ? 8 : 4);
+        if (bytes <= budget) {
+            in_lds[j] = true;
+            budget -= bytes;
+            any_lds = true;
+        }
+    }
+    s << "extern \"C\" __global__ void __launch_bounds__(256) " << name << "(const coot_kargs a)\n{\n";
+    s << decl_reads(p, !p.alias_out);
+    for (size_t j = 0; j < p.reads.size(); ++j)
+        if (in_lds[j]) s << "    __shared__ " << ctype(p.reads[j].dtype == COOT_F64 ? 64 : 32) << " T" << j << "[64][65];\n";
+    if (ew) {
+        const char* OS = stype(p.out_dtype);
+        s << "    " << OS << "* " << (p.alias_out ? "" : "__restrict__ ") << "O = (" << OS << "*)a.out;\n";
+        s << "    const i64 ldo = a.ld_out;\n";
+    } else {
+        s << "    " << acc_type(p) << " acc;\n    acc.init();\n";
+    }
+    s << "    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;\n";
+    s << "    const i64 R = a.rows, Cn = a.cols;\n";
+    s << "    const i64 tr = (R + 63) >> 6, tc = (Cn + 63) >> 6, nt = tr * tc;\n";
+    s << "    for (i64 t = blockIdx.x; t < nt; t += gridDim.x) {\n";
+    s << "        const i64 i0 = (t % tr) << 6, j0 = (t / tr) << 6;\n";
+    if (any_lds) {
+        s << "        __syncthreads();\n#pragma unroll\n        for (int kk = 0; kk < 16; ++kk) {\n";
+        s << "            const int ii = w + 4 * kk;\n            const i64 ig = i0 + ii, jg = j0 + lane;\n";
+        s << "            if (ig < R && jg < Cn) {\n";
+        for (size_t j = 0; j < p.reads.size(); ++j)
+            if (in_lds[j])
+                s << "                T" << j << "[ii][lane] = " << widen(p.reads[j].dtype, "L" + std::to_string(j) + "[jg + ig * ld" + std::to_string(j) + "]") << ";\n";
+        s << "            }\n        }\n        __syncthreads();\n";
+    }
+    s << "        const i64 ig = i0 + lane;\n        if (ig < R) {\n#pragma unroll\n";
+    s << "            for (int kk = 0; kk < 16; ++kk) {\n";
+    s << "                const int jj = w + 4 * kk;\n                const i64 jg = j0 + jj;\n";
+    s << "                if (jg < Cn) {\n";
+    std::string args;
+    for (size_t j = 0; j < p.reads.size(); ++j) {
+        if (j) args += ", ";
+        std::string J = std::to_string(j);
+        if (in_lds[j])
+            args += "T" + J + "[lane][jj]";
+        else if (p.reads[j].trans)
+            args += widen(p.reads[j].dtype, "L" + J + "[jg + ig * ld" + J + "]");
+        else
+            args += widen(p.reads[j].dtype, "L" + J + "[ig + jg * ld" + J + "]");
+    }
+    if (ew)
+        s << "                    O[ig + jg * ldo] = " << narrow(p.out_dtype, rp, "x_eval(" + args + ")") << ";\n";
+    else
+        s << "                    " << accumulate(p, args, "(ig + jg * R)") << "\n";
+    s << "                }\n            }\n        }\n    }\n";
+    if (!ew) {
+        s << "    __shared__ " << acc_type(p) << " lds_acc[4];\n";
+        s << "    acc = block_reduce(acc, lds_acc);\n";
+        s << "    if (threadIdx.x == 0) " << put_partial(p, "blockIdx.x") << "\n";
+        s << "    if (arrive_last(a.counter, gridDim.x)) {\n        "
+          << combine_and_write(p, "0", "gridDim.x", "1", "0") << "\n        counter_reset(a.counter);\n    }\n";
+    }
+    s << "}\n";
+    return s.str();
+}
+
+// --- per-column reductions (dim 0): one wave per column ----------------------
+static std::string emit_col(const Plan& p, const LaunchCfg& c, const std::string& name)
+{
+    const int VE = p.ve, EPT = c.ept;
+    std::ostringstream s;
+    s << "extern \"C\" __global__ void __launch_bounds__(512) " << name << "(const coot_kargs a)\n{\n";
+    s << decl_reads(p, true);
+    s << "    const int lane = threadIdx.x & 63;\n";
+    s << "    const i64 wv = ((i64)blockIdx.x * blockDim.x + threadIdx.x) >> 6;\n";
+    s << "    const i64 nw = ((i64)gridDim.x * blockDim.x) >> 6;\n";
+    s << "    const i64 nvr = a.rows / " << VE << ";\n";
+    s << "    for (i64 j = wv; j < a.cols; j += nw) {\n";
+    s << "        " << acc_type(p) << " acc;\n        acc.init();\n";
+    for (size_t j = 0; j < p.reads.size(); ++j)
+        s << "        const " << stype(p.reads[j].dtype) << "* C" << j << " = L" << j << " + j * ld" << j << ";\n";
+    s << "        for (i64 base = lane; base < nvr; base += 64 * " << EPT << ") {\n";
+    for (size_t j = 0; j < p.reads.size(); ++j)
+        s << "            " << stype(p.reads[j].dtype) << " r" << j << "[" << EPT << "][" << VE << "];\n";
+    s << "#pragma unroll\n            for (int e = 0; e < " << EPT << "; ++e) {\n";
+    s << "                const i64 v = base + e * 64;\n                if (v < nvr) {\n";
+    for (size_t j = 0; j < p.reads.size(); ++j)
+        s << "                    ldv<" << stype(p.reads[j].dtype) << ", " << VE << ">(C" << j << ", v * " << VE << ", r"
+          << j << "[e]);\n";
+    s << "                }\n            }\n";
+    s << "#pragma unroll\n            for (int e = 0; e < " << EPT << "; ++e) {\n";
+    s << "                const i64 v = base + e * 64;\n                if (v < nvr) {\n";
+    std::string args = arglist(p, [](int j) { return "r" + std::to_string(j) + "[e][k]"; });
+    s << "#pragma unroll\n                    for (int k = 0; k < " << VE << "; ++k) { const i64 gi = v * " << VE
+      << " + k; (void)gi; " << accumulate(p, args, "gi") << " }\n";
+    s << "                }\n            }\n        }\n";
+    std::string targs = arglist(p, [](int j) { return "C" + std::to_string(j) + "[r]"; });
+    s << "        for (i64 r = nvr * " << VE << " + lane; r < a.rows; r += 64) { " << accumulate(p, targs, "r") << " }\n";
+    s << "        wave_reduce(acc);\n";
+    s << "        if (lane == 0) { " << write_direct(p, "j") << " }\n";
+    s << "    }\n}\n";
+    return s.str();
+}
+
+// --- per-column reductions of short columns: one thread per column -----------
+static std::string emit_colt(const Plan& p, const std::string& name)
+{
+    std::ostringstream s;
+    s << "extern \"C\" __global__ void __launch_bounds__(512) " << name << "(const coot_kargs a)\n{\n";
+    s << decl_reads(p, true);
+    s << "    for (i64 j = (i64)blockIdx.x * blockDim.x + threadIdx.x; j < a.cols; j += (i64)gridDim.x * blockDim.x) {\n";
+    s << "        " << acc_type(p) << " acc;\n        acc.init();\n";
+    std::string args = arglist(p, [](int j) { return "L" + std::to_string(j) + "[r + j * ld" + std::to_string(j) + "]"; });
+    s << "        for (i64 r = 0; r < a.rows; ++r) { " << accumulate(p, args, "r") << " }\n";
+    s << "        " << write_direct(p, "j") << "\n    }\n}\n";
+    return s.str();
+}
+
+// --- per-row reductions (dim 1): thread per (row, column subset) -------------
+static std::string emit_row(const Plan& p, const std::string& name)
+{
+    std::ostringstream s;
+    s << "extern \"C\" __global__ void __launch_bounds__(512) " << name << "(const coot_kargs a)\n{\n";
+    s << decl_reads(p, true);
+    s << "    const i64 total = a.rows * a.splits;\n";
+    s << "    for (i64 w = (i64)blockIdx.x * blockDim.x + threadIdx.x; w < total; w += (i64)gridDim.x * blockDim.x) {\n";
+    s << "        const i64 r = w % a.rows, q = w / a.rows;\n";
+    s << "        " << acc_type(p) << " acc;\n        acc.init();\n";
+    std::string args = arglist(p, [](int j) { return "L" + std::to_string(j) + "[r + c * ld" + std::to_string(j) + "]"; });
+    s << "#pragma unroll 4\n        for (i64 c = q; c < a.cols; c += a.splits) { " << accumulate(p, args, "c") << " }\n";
+    s << "        if (a.splits == 1) { " << write_direct(p, "r") << " } else { " << put_partial(p, "q * a.rows + r")
+      << " }\n";
+    s << "    }\n}\n";
+    // combine: one block per row, splits in order
+    s << "extern \"C\" __global__ void __launch_bounds__(256) " << name << "_comb(const coot_kargs a)\n{\n";
+    s << "    for (i64 r = blockIdx.x; r < a.rows; r += gridDim.x) {\n        "
+      << combine_and_write(p, "r", "a.splits", "a.rows", "r") << "\n    }\n}\n";
+    return s.str();
+}
+
+std::string kernel_source(const Plan& p, const LaunchCfg& cfg, std::string* name_out, std::string* sig_out)
+{
+    std::ostringstream body;
+    const bool need_eval = !p.product_form;
+    body << "// tree: " << p.body_sig << "\n";
+    if (need_eval || p.red_op < 0) body << emit_eval(p, false);
+    if (p.product_form) body << emit_eval(p, true);
+    static const char* kname[] = {"ewf", "ewt", "redf", "redt", "col", "colt", "row"};
+    std::string placeholder = "COOT_KERNEL_NAME";
+    switch (p.kind) {
+    case K_EW_FLAT:
+    case K_RED_FLAT: body << emit_flat(p, cfg, placeholder); break;
+    case K_EW_TILED:
+    case K_RED_TILED: body << emit_tiled(p, placeholder); break;
+    case K_RED_COL: body << emit_col(p, cfg, placeholder); break;
+    case K_RED_COLT: body << emit_colt(p, placeholder); break;
+    case K_RED_ROW: body << emit_row(p, placeholder); break;
+    }
+    std::ostringstream key;
+    key << "kind" << p.kind << "|ve" << p.ve << "|ept" << cfg.ept << "|out" << p.out_dtype << "|red" << p.red_op
+        << "|pw" << p.pairwise << "|" << body.str();
+    std::string sig = key.str();
+    std::string name = std::string("coot_") + kname[p.kind] + "_" + hex64(fnv1a(sig));
+    std::string b = body.str();
+    for (size_t pos; (pos = b.find(placeholder)) != std::string::npos;) b.replace(pos, placeholder.size(), name);
+    if (name_out) *name_out = name;
+    if (sig_out) *sig_out = sig;
+    return b;
+}
+
+}  // namespace coot

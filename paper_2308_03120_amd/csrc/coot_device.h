@@ -1,0 +1,337 @@
+/*
+ * Device building blocks shared by every run-time compiled kernel (gfx950,
+ * wave64).  This text is prepended to each generated kernel source; the
+ * generator adds the tree's element function and the kernel bodies.
+ *
+ * Floating-point rules: no contraction (a*b+c stays two rounded operations
+ * unless fmaf/fma is written on purpose), IEEE divide and square root
+ * (correctly rounded), denormals kept, no fast-math.
+ */
+#pragma clang fp contract(off)
+
+typedef unsigned short u16;
+typedef unsigned int u32;
+typedef unsigned long long u64;
+typedef long long i64;
+typedef u32 u32x4 __attribute__((ext_vector_type(4)));
+typedef u32 u32x2 __attribute__((ext_vector_type(2)));
+
+#define CD __device__ __forceinline__
+
+/* ------------------------------------------------------------------ */
+/* storage <-> compute conversions                                     */
+/* ------------------------------------------------------------------ */
+/* 16-bit storage widens exactly to FP32. */
+CD float widen_bf16(u16 b) { return __builtin_bit_cast(float, (u32)b << 16); }
+CD float widen_f16(u16 b) { return (float)__builtin_bit_cast(_Float16, b); }
+
+/* FP32 -> bfloat16 bits, round to nearest even; NaN stays a quiet NaN. */
+CD u16 bits_bf16(float f)
+{
+    u32 u = __builtin_bit_cast(u32, f);
+    if ((u & 0x7fffffffu) > 0x7f800000u) return (u16)((u >> 16) | 0x40u);
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return (u16)(u >> 16);
+}
+/* FP32 -> binary16 bits: the hardware conversion rounds to nearest even. */
+CD u16 bits_f16(float f) { return __builtin_bit_cast(u16, (_Float16)f); }
+
+/* FP64 -> FP32 rounded to odd (truncate, then set the last bit if inexact).
+ * Rounding to odd into a format with at least two more bits than the final
+ * 16-bit format makes the following round-to-nearest-even exact
+ * (Boldo and Melquiond, "Emulation of FMA and correctly rounded sums: proved
+ * algorithms using rounding to odd", IEEE Trans. Computers 57(4), 2008). */
+CD float f32_round_odd(double d)
+{
+    float f = (float)d;
+    if ((double)f != d && d == d) {
+        u32 u = __builtin_bit_cast(u32, f);
+        if (__builtin_fabs((double)f) > __builtin_fabs(d)) u -= 1u;  /* step toward zero */
+        u |= 1u;
+        f = __builtin_bit_cast(float, u);
+    }
+    return f;
+}
+CD u16 bits_bf16_d(double d) { return bits_bf16(f32_round_odd(d)); }
+CD u16 bits_f16_d(double d) { return bits_f16(f32_round_odd(d)); }
+
+/* value of a number after rounding to a 16-bit type (used by conv nodes) */
+CD float rnd_bf16(float f) { return widen_bf16(bits_bf16(f)); }
+CD float rnd_f16(float f) { return widen_f16(bits_f16(f)); }
+CD float rnd_bf16_d(double d) { return widen_bf16(bits_bf16_d(d)); }
+CD float rnd_f16_d(double d) { return widen_f16(bits_f16_d(d)); }
+
+/* ------------------------------------------------------------------ */
+/* vector loads / stores of VE consecutive elements                     */
+/* ------------------------------------------------------------------ */
+template <int BYTES> struct rawvec;
+template <> struct rawvec<16> { typedef u32x4 T; };
+template <> struct rawvec<8> { typedef u32x2 T; };
+template <> struct rawvec<4> { typedef u32 T; };
+template <> struct rawvec<2> { typedef u16 T; };
+
+#ifndef COOT_NT_LOADS
+#define COOT_NT_LOADS 0
+#endif
+
+template <class S, int VE>
+CD void ldv(const S* __restrict__ p, i64 e0, S (&o)[VE])
+{
+    constexpr int B = (int)sizeof(S) * VE;
+    if constexpr (B <= 16) {
+        typedef typename rawvec<B>::T R;
+#if COOT_NT_LOADS
+        R r = __builtin_nontemporal_load((const R*)(p + e0));
+#else
+        R r = *(const R*)(p + e0);
+#endif
+        __builtin_memcpy(o, &r, B);
+    } else {
+        ldv<S, VE / 2>(p, e0, *(S(*)[VE / 2])o);
+        ldv<S, VE / 2>(p, e0 + VE / 2, *(S(*)[VE / 2])(o + VE / 2));
+    }
+}
+
+template <class S, int VE>
+CD void stv(S* p, i64 e0, const S (&o)[VE])
+{
+    constexpr int B = (int)sizeof(S) * VE;
+    if constexpr (B <= 16) {
+        typedef typename rawvec<B>::T R;
+        R r;
+        __builtin_memcpy(&r, o, B);
+        *(R*)(p + e0) = r;
+    } else {
+        stv<S, VE / 2>(p, e0, *(const S(*)[VE / 2])o);
+        stv<S, VE / 2>(p, e0 + VE / 2, *(const S(*)[VE / 2])(o + VE / 2));
+    }
+}
+
+/* ------------------------------------------------------------------ */
+/* accumulators                                                         */
+/* ------------------------------------------------------------------ */
+/* Compensated FP32 sum: (s, c) with every step an exact TwoSum (Knuth) and
+ * products split exactly with TwoProduct (fmaf).  The value is s + c. */
+struct AccKF {
+    float s, c;
+    CD void init() { s = 0.0f; c = 0.0f; }
+    CD void add(float x)
+    {
+        float t = s + x;
+        float z = t - s;
+        c += (s - (t - z)) + (x - z);
+        s = t;
+    }
+    CD void add_prod(float a, float b)
+    {
+        float p = a * b;
+        float e = __builtin_fmaf(a, b, -p);
+        add(p);
+        c += e;
+    }
+    CD void merge(const AccKF& o)
+    {
+        float t = s + o.s;
+        float z = t - s;
+        float e = (s - (t - z)) + (o.s - z);
+        s = t;
+        c = (c + o.c) + e;
+    }
+    CD void shfl(int off)
+    {
+        AccKF o;
+        o.s = __shfl_xor(s, off, 64);
+        o.c = __shfl_xor(c, off, 64);
+        merge(o);
+    }
+    CD double hi() const { return (double)s; }
+    CD double lo() const { return (double)c; }
+};
+
+/* Plain FP32 sum (the "pairwise only" variant: per-thread running sum, then
+ * the same binary trees with no compensation). */
+struct AccPF {
+    float s;
+    CD void init() { s = 0.0f; }
+    CD void add(float x) { s += x; }
+    CD void add_prod(float a, float b) { s += a * b; }
+    CD void merge(const AccPF& o) { s = s + o.s; }
+    CD void shfl(int off)
+    {
+        AccPF o;
+        o.s = __shfl_xor(s, off, 64);
+        merge(o);
+    }
+    CD double hi() const { return (double)s; }
+    CD double lo() const { return 0.0; }
+};
+
+/* Compensated FP64 sum (F64 data, and the cross-block combine). */
+struct AccKD {
+    double s, c;
+    CD void init() { s = 0.0; c = 0.0; }
+    CD void add(double x)
+    {
+        double t = s + x;
+        double z = t - s;
+        c += (s - (t - z)) + (x - z);
+        s = t;
+    }
+    CD void add_prod(double a, double b)
+    {
+        double p = a * b;
+        double e = __builtin_fma(a, b, -p);
+        add(p);
+        c += e;
+    }
+    CD void merge(const AccKD& o)
+    {
+        double t = s + o.s;
+        double z = t - s;
+        double e = (s - (t - z)) + (o.s - z);
+        s = t;
+        c = (c + o.c) + e;
+    }
+    CD void shfl(int off)
+    {
+        AccKD o;
+        o.s = __shfl_xor(s, off, 64);
+        o.c = __shfl_xor(c, off, 64);
+        merge(o);
+    }
+    CD double hi() const { return s; }
+    CD double lo() const { return c; }
+};
+
+/* Extremum with its index: NaN skipped, ties to the lowest index, i < 0
+ * means "nothing seen yet". */
+template <class C, bool MAX>
+struct AccI {
+    C v;
+    i64 i;
+    CD void init() { v = (C)0; i = -1; }
+    CD bool better(C x, i64 j) const
+    {
+        if (i < 0) return true;
+        if (MAX ? (x > v) : (x < v)) return true;
+        return x == v && j < i;
+    }
+    CD void add(C x, i64 j)
+    {
+        if (x == x && better(x, j)) { v = x; i = j; }
+    }
+    CD void merge(const AccI& o)
+    {
+        if (o.i >= 0 && better(o.v, o.i)) { v = o.v; i = o.i; }
+    }
+    CD void shfl(int off)
+    {
+        AccI o;
+        o.v = __shfl_xor(v, off, 64);
+        o.i = __shfl_xor(i, off, 64);
+        merge(o);
+    }
+};
+
+/* ------------------------------------------------------------------ */
+/* wave64 and block reductions (fixed order: deterministic)             */
+/* ------------------------------------------------------------------ */
+template <class A>
+CD void wave_reduce(A& a)
+{
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) a.shfl(off);
+}
+
+/* Result valid in thread 0.  lds must hold blockDim.x/64 entries. */
+template <class A>
+CD A block_reduce(A a, A* lds)
+{
+    wave_reduce(a);
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63, nw = blockDim.x >> 6;
+    __syncthreads();
+    if (lane == 0) lds[w] = a;
+    __syncthreads();
+    if (w == 0) {
+        A b;
+        if (lane < nw) b = lds[lane];
+        else b.init();
+        wave_reduce(b);
+        a = b;
+    }
+    return a;
+}
+
+/* ------------------------------------------------------------------ */
+/* two-pass combine inside one launch: every block publishes one        */
+/* partial, the last block to arrive combines them all in block order.  */
+/* ------------------------------------------------------------------ */
+CD bool arrive_last(unsigned* counter, unsigned total)
+{
+    __shared__ unsigned s_last;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        unsigned t = __hip_atomic_fetch_add(counter, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+        s_last = (t == total - 1u) ? 1u : 0u;
+    }
+    __syncthreads();
+    bool last = s_last != 0u;
+    if (last) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    return last;
+}
+
+CD void counter_reset(unsigned* counter)
+{
+    if (threadIdx.x == 0) __hip_atomic_store(counter, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+/* partial slots are 16 bytes: sums (hi, lo) as two doubles; extrema
+ * (value as double, index). */
+CD void put_sum_partial(double* part, i64 slot, double hi, double lo)
+{
+    part[2 * slot] = hi;
+    part[2 * slot + 1] = lo;
+}
+
+CD void put_idx_partial(double* part, i64 slot, double v, i64 i)
+{
+    part[2 * slot] = v;
+    part[2 * slot + 1] = __builtin_bit_cast(double, i);
+}
+
+/* FP64 compensated combine of `count` sum partials starting at `first`,
+ * with `stride` doubles-pairs between them; result in thread 0. */
+CD double combine_sums(const double* part, i64 first, i64 count, i64 stride)
+{
+    __shared__ AccKD lds_kd[16];
+    AccKD a;
+    a.init();
+    for (i64 t = threadIdx.x; t < count; t += blockDim.x) {
+        const double* p = part + 2 * (first + t * stride);
+        a.add(p[0]);
+        a.add(p[1]);
+    }
+    a = block_reduce(a, lds_kd);
+    return a.s + a.c;
+}
+
+template <bool MAX>
+CD AccI<double, MAX> combine_idx(const double* part, i64 first, i64 count, i64 stride)
+{
+    __shared__ AccI<double, MAX> lds_id[16];
+    AccI<double, MAX> a;
+    a.init();
+    for (i64 t = threadIdx.x; t < count; t += blockDim.x) {
+        const double* p = part + 2 * (first + t * stride);
+        AccI<double, MAX> o;
+        o.v = p[0];
+        o.i = __builtin_bit_cast(i64, p[1]);
+        a.merge(o);
+    }
+    return block_reduce(a, lds_id);
+}
+
+/* write a reduction value / index to the output buffer */
+CD void put_f32(void* out, i64 j, double v) { ((float*)out)[j] = (float)v; }
+CD void put_f64(void* out, i64 j, double v) { ((double*)out)[j] = v; }
+CD void put_u64(void* out, i64 j, i64 i) { ((u64*)out)[j] = (u64)(i < 0 ? 0 : i); }

@@ -1,0 +1,96 @@
+// Host-side internals of libcoot_mi355x.so.
+#pragma once
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "coot.h"
+#include "coot_kargs.h"
+
+namespace coot {
+
+struct Error {
+    int code;
+    std::string msg;
+};
+
+[[noreturn]] void fail(int code, const std::string& msg);
+void set_error(int code, const std::string& msg);
+
+int itemsize(int dtype);
+bool is_value_dtype(int dtype);  // F32, F64, F16, BF16
+const char* dtype_name(int dtype);
+
+// ----------------------------------------------------------------- planning
+enum Kind {
+    K_EW_FLAT = 0,     // element-wise, contiguous operands, linear index
+    K_EW_TILED = 1,    // element-wise, 64x64 tiles (transposed reads / ld views)
+    K_RED_FLAT = 2,    // reduction over all elements, contiguous
+    K_RED_TILED = 3,   // reduction over all elements, tiled
+    K_RED_COL = 4,     // per-column reduction, one wave per column
+    K_RED_COLT = 5,    // per-column reduction, one thread per column (short columns)
+    K_RED_ROW = 6,     // per-row reduction, one thread per row, column splits
+};
+
+struct Read {
+    int slot;
+    bool trans;       // read element (r, c) of the value as operand (c, r)
+    int dtype;
+    int64_t ld;       // effective leading dimension
+};
+
+struct PNode {
+    int op;           // COOT_* opcode (never COOT_TRANS after planning)
+    int a, b;         // children (plan node indices); LEAF: a = read index
+    double k;         // scalar (already rounded to the node's precision)
+    int prec;         // 32 or 64
+    int conv;         // COOT_CONV target dtype
+    int64_t rows, cols;
+};
+
+struct Plan {
+    std::vector<PNode> nodes;
+    std::vector<Read> reads;
+    int root;                 // index of the root node
+    int root_prec;
+    int64_t rows, cols, n;    // shape of the tree's value
+    int red_op;               // -1 for element-wise
+    int dim;
+    bool pairwise;
+    bool product_form;        // sum over a product root: kernel splits it (TwoProduct)
+    int prod_a, prod_b;
+    int kind;
+    int ve;                   // elements per vector access (flat kinds)
+    int out_dtype;
+    bool alias_out;
+    bool temp_needed;         // dim reduction of a tiled tree: materialise first
+    std::string body_sig;     // canonical description of the element function
+};
+
+// Validate and plan.  Throws Error.
+Plan make_plan(int red_op, int dim, const coot_expr* expr, const coot_operand* ops, int n_ops,
+               const coot_operand* out);
+
+struct LaunchCfg {
+    int ept, block, split;
+};
+
+// Kernel source for a plan and configuration; `name` receives the entry point.
+std::string kernel_source(const Plan& p, const LaunchCfg& cfg, std::string* name, std::string* sig);
+std::string prelude_source();
+
+// 64-entry configuration space
+LaunchCfg config_of(int index);
+int config_index(const LaunchCfg& c);
+LaunchCfg default_config(const Plan& p);
+LaunchCfg normalise_config(const Plan& p, LaunchCfg c);
+
+// features of a plan (cost model input)
+void plan_features(const Plan& p, float* f);
+
+// hash
+uint64_t fnv1a(const std::string& s);
+std::string hex64(uint64_t v);
+
+}  // namespace coot

@@ -1,0 +1,414 @@
+// Validation, exact rewrites and kernel choice for one coot_eval / coot_reduce
+// call.  Host only: nothing here touches the device.
+//
+// Semantics (Bandicoot paper, arXiv:2308.03120): column-major operands
+// (Section 2, Table 1); element-wise operators (Table 2) and functions
+// (Table 7); reductions (Tables 5 and 6).  Rewrites follow the paper's idea of
+// restructuring an expression into an equivalent, cheaper form while it is
+// built (Section 7, e.g. trans(diagmat(X)) -> diagmat(X)); only rewrites that
+// leave every rounded result unchanged are applied:
+//   * trans is moved down to the operands (trans(a + b) = trans(a) + trans(b),
+//     trans(f(a)) = f(trans(a)), trans(trans(a)) = a), so the generated kernel
+//     reads an operand transposed instead of materialising a transpose;
+//   * repeated operand reads and repeated identical subtrees are merged.
+// No reassociation and no constant folding is done (both change rounding).
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <functional>
+#include <map>
+#include <sstream>
+#include <tuple>
+
+#include "internal.h"
+
+namespace coot {
+
+int itemsize(int dt)
+{
+    switch (dt) {
+    case COOT_F32: return 4;
+    case COOT_F64: return 8;
+    case COOT_F16: return 2;
+    case COOT_BF16: return 2;
+    case COOT_U64: return 8;
+    }
+    return 0;
+}
+
+bool is_value_dtype(int dt) { return dt == COOT_F32 || dt == COOT_F64 || dt == COOT_F16 || dt == COOT_BF16; }
+
+const char* dtype_name(int dt)
+{
+    switch (dt) {
+    case COOT_F32: return "f32";
+    case COOT_F64: return "f64";
+    case COOT_F16: return "f16";
+    case COOT_BF16: return "bf16";
+    case COOT_U64: return "u64";
+    }
+    return "?";
+}
+
+static bool is_binary(int op) { return op >= COOT_PLUS && op <= COOT_DIV; }
+static bool is_scalar(int op) { return op >= COOT_SCAL_PLUS && op <= COOT_SCAL_DIV_PRE; }
+static bool is_unary(int op) { return op == COOT_EXP || op == COOT_LOG || op == COOT_SQRT || op == COOT_ABS; }
+static bool is_sum_like(int r)
+{
+    return r == COOT_RED_ACCU || r == COOT_RED_SUM || r == COOT_RED_DOT || r == COOT_RED_NORM1 || r == COOT_RED_NORM2;
+}
+
+uint64_t fnv1a(const std::string& s)
+{
+    uint64_t h = 1469598103934665603ull;
+    for (unsigned char c : s) {
+        h ^= c;
+        h *= 1099511628211ull;
+    }
+    return h;
+}
+
+std::string hex64(uint64_t v)
+{
+    char b[17];
+    snprintf(b, sizeof b, "%016llx", (unsigned long long)v);
+    return b;
+}
+
+static std::string shape_str(int64_t r, int64_t c)
+{
+    std::ostringstream o;
+    o << r << "x" << c;
+    return o.str();
+}
+
+static bool contiguous(const coot_operand& o) { return o.n_cols <= 1 || o.ld == o.n_rows; }
+
+// byte extent [lo, hi) of an operand's storage
+static void extent(const coot_operand& o, int dt, uint64_t* lo, uint64_t* hi)
+{
+    uint64_t base = (uint64_t)(uintptr_t)o.ptr;
+    int64_t n = o.n_rows * o.n_cols;
+    if (n == 0) {
+        *lo = *hi = base;
+        return;
+    }
+    uint64_t last = (uint64_t)(o.ld * (o.n_cols - 1) + o.n_rows);
+    *lo = base;
+    *hi = base + last * (uint64_t)itemsize(dt);
+}
+
+static void check_operand(const coot_operand& o, const char* what, bool output)
+{
+    if (o.n_rows < 0 || o.n_cols < 0) fail(COOT_ERR_ARG, std::string(what) + ": negative dimension");
+    if (o.n_rows > 0 && o.n_cols > (int64_t)(INT64_MAX / 16) / o.n_rows)
+        fail(COOT_ERR_ARG, std::string(what) + ": too many elements");
+    if (o.ld < 1 || o.ld < o.n_rows) fail(COOT_ERR_ARG, std::string(what) + ": ld must be >= max(1, n_rows)");
+    if (o.n_cols > 1 && o.ld > (int64_t)(INT64_MAX / 16) / o.n_cols) fail(COOT_ERR_ARG, std::string(what) + ": ld too large");
+    int64_t n = o.n_rows * o.n_cols;
+    if (n > 0 && o.ptr == nullptr) fail(COOT_ERR_ARG, std::string(what) + ": NULL pointer with elements");
+    if (!output && o.flags != 0) fail(COOT_ERR_ARG, std::string(what) + ": flags must be 0 for an input");
+    if (output && (o.flags & ~COOT_OPERAND_HOST)) fail(COOT_ERR_ARG, std::string(what) + ": unknown flags");
+}
+
+static void check_config(const coot_config& c)
+{
+    if (c.reserved != 0) fail(COOT_ERR_ARG, "cfg.reserved must be 0");
+    bool zero = c.ept == 0 && c.block == 0 && c.split == 0;
+    if (zero) return;
+    auto pow2in = [](int v, int lo, int hi) { return v >= lo && v <= hi && (v & (v - 1)) == 0; };
+    if (!pow2in(c.ept, 1, 8) || !pow2in(c.block, 64, 512) || !pow2in(c.split, 1, 8))
+        fail(COOT_ERR_ARG, "cfg: ept in {1,2,4,8}, block in {64,...,512}, split in {1,2,4,8}, or all zero");
+}
+
+struct Info {
+    int64_t rows, cols;
+    int prec;
+};
+
+Plan make_plan(int red_op_in, int dim, const coot_expr* expr, const coot_operand* ops, int n_ops,
+               const coot_operand* out)
+{
+    if (!expr) fail(COOT_ERR_ARG, "expr is NULL");
+    if (!expr->nodes) fail(COOT_ERR_ARG, "expr->nodes is NULL");
+    const int nn = expr->n_nodes;
+    if (nn < 1 || nn > 4096) fail(COOT_ERR_BAD_TREE, "n_nodes must be in [1, 4096]");
+    if (n_ops < 0 || (n_ops > 0 && !ops)) fail(COOT_ERR_ARG, "operands: bad count or NULL array");
+    if (expr->flags & ~COOT_EXPR_UNFUSED) fail(COOT_ERR_ARG, "unknown expr flags");
+    check_config(expr->cfg);
+    if (!out) fail(COOT_ERR_ARG, "out is NULL");
+
+    Plan P;
+    P.red_op = -1;
+    P.dim = -1;
+    P.pairwise = false;
+    if (red_op_in >= 0) {
+        if (red_op_in & ~(0xff | COOT_RED_PAIRWISE)) fail(COOT_ERR_ARG, "unknown reduction flags");
+        P.red_op = red_op_in & 0xff;
+        P.pairwise = (red_op_in & COOT_RED_PAIRWISE) != 0;
+        if (P.red_op > COOT_RED_INDEX_MAX) fail(COOT_ERR_ARG, "unknown reduction");
+        if (dim < -1 || dim > 1) fail(COOT_ERR_ARG, "dim must be -1, 0 or 1");
+        P.dim = dim;
+        bool scalar_only = P.red_op == COOT_RED_ACCU || P.red_op == COOT_RED_DOT || P.red_op == COOT_RED_NORM1 ||
+                           P.red_op == COOT_RED_NORM2 || P.red_op == COOT_RED_NORMINF || P.red_op == COOT_RED_NORMNEGINF;
+        if (scalar_only && dim != -1) fail(COOT_ERR_ARG, "accu, dot and norm reduce over all elements (dim = -1)");
+    } else if (red_op_in != -1) {
+        fail(COOT_ERR_ARG, "red_op must be -1 for element-wise evaluation");
+    }
+
+    // --- structure, operands, shapes and precisions of the user's tree
+    std::vector<Info> info(nn);
+    std::vector<char> slot_checked(n_ops > 0 ? n_ops : 1, 0);
+    for (int i = 0; i < nn; ++i) {
+        const coot_node& N = expr->nodes[i];
+        std::string at = "node " + std::to_string(i);
+        if (N.reserved != 0) fail(COOT_ERR_BAD_TREE, at + ": reserved must be 0");
+        if (N.op == COOT_LEAF) {
+            if (N.a < 0 || N.a >= n_ops) fail(COOT_ERR_BAD_TREE, at + ": operand slot out of range");
+            const coot_operand& o = ops[N.a];
+            if (!slot_checked[N.a]) {
+                std::string w = "operand " + std::to_string(N.a);
+                check_operand(o, w.c_str(), false);
+                if (!is_value_dtype(o.dtype)) fail(COOT_ERR_DTYPE, w + ": dtype must be f32, f64, f16 or bf16");
+                slot_checked[N.a] = 1;
+            }
+            info[i] = {o.n_rows, o.n_cols, o.dtype == COOT_F64 ? 64 : 32};
+            continue;
+        }
+        bool bin = is_binary(N.op), sc = is_scalar(N.op), un = is_unary(N.op);
+        if (!bin && !sc && !un && N.op != COOT_TRANS && N.op != COOT_CONV) fail(COOT_ERR_BAD_TREE, at + ": unknown opcode");
+        if (N.a < 0 || N.a >= i) fail(COOT_ERR_BAD_TREE, at + ": child a must be an earlier node");
+        Info A = info[N.a];
+        if (bin) {
+            if (N.b < 0 || N.b >= i) fail(COOT_ERR_BAD_TREE, at + ": child b must be an earlier node");
+            Info B = info[N.b];
+            if (A.rows != B.rows || A.cols != B.cols)
+                fail(COOT_ERR_SHAPE, at + ": operand shapes " + shape_str(A.rows, A.cols) + " and " +
+                                         shape_str(B.rows, B.cols) + " differ");
+            if (A.prec != B.prec) fail(COOT_ERR_DTYPE, at + ": mixed FP32/FP64 operands need an explicit conversion");
+            info[i] = A;
+        } else if (N.op == COOT_CONV) {
+            if (!is_value_dtype(N.b)) fail(COOT_ERR_BAD_TREE, at + ": conversion target must be a value dtype");
+            info[i] = {A.rows, A.cols, N.b == COOT_F64 ? 64 : 32};
+        } else {
+            if (N.b != -1) fail(COOT_ERR_BAD_TREE, at + ": b must be -1 for a unary or scalar node");
+            if (N.op == COOT_TRANS)
+                info[i] = {A.cols, A.rows, A.prec};
+            else
+                info[i] = A;
+        }
+    }
+    const Info R = info[nn - 1];
+    P.rows = R.rows;
+    P.cols = R.cols;
+    P.n = R.rows * R.cols;
+    P.root_prec = R.prec;
+
+    // --- output
+    check_operand(*out, "out", true);
+    if (P.red_op < 0) {
+        if (out->flags & COOT_OPERAND_HOST) fail(COOT_ERR_ARG, "out: element-wise results must be device memory");
+        if (!is_value_dtype(out->dtype)) fail(COOT_ERR_DTYPE, "out: dtype must be f32, f64, f16 or bf16");
+        if (out->n_rows != P.rows || out->n_cols != P.cols)
+            fail(COOT_ERR_SHAPE, "out is " + shape_str(out->n_rows, out->n_cols) + ", the expression is " +
+                                     shape_str(P.rows, P.cols));
+        P.out_dtype = out->dtype;
+    } else {
+        bool sel = !is_sum_like(P.red_op);
+        if (sel && P.n == 0) fail(COOT_ERR_EMPTY, "min/max/index of an empty object");
+        if (P.red_op == COOT_RED_DOT && expr->nodes[nn - 1].op != COOT_SCHUR)
+            fail(COOT_ERR_BAD_TREE, "dot: the root must be an element-wise product of the two operands");
+        int64_t n_out = P.dim < 0 ? 1 : (P.dim == 0 ? P.cols : P.rows);
+        if (out->n_rows * out->n_cols != n_out || (out->n_rows != 1 && out->n_cols != 1))
+            fail(COOT_ERR_SHAPE, "out must be a vector of " + std::to_string(n_out) + " elements");
+        if (out->n_cols > 1 && out->ld != 1) fail(COOT_ERR_ARG, "out: a row vector result must have ld = 1");
+        bool idx = P.red_op == COOT_RED_INDEX_MIN || P.red_op == COOT_RED_INDEX_MAX;
+        if (idx && out->dtype != COOT_U64) fail(COOT_ERR_DTYPE, "out: index results are u64");
+        if (!idx && out->dtype != COOT_F32 && out->dtype != COOT_F64) fail(COOT_ERR_DTYPE, "out: values are f32 or f64");
+        P.out_dtype = out->dtype;
+    }
+
+    // --- exact rewrites: trans pushed to the operands, reads and subtrees merged
+    std::map<std::pair<int, bool>, int> read_of;
+    std::map<std::tuple<int, int, int, uint64_t, int>, int> cse;
+    std::map<std::pair<int, bool>, int> memo;
+    std::function<int(int, bool)> rebuild = [&](int i, bool t) -> int {
+        auto mk = memo.find({i, t});
+        if (mk != memo.end()) return mk->second;
+        const coot_node& N = expr->nodes[i];
+        int res;
+        if (N.op == COOT_TRANS) {
+            res = rebuild(N.a, !t);
+        } else {
+            PNode pn;
+            pn.op = N.op;
+            pn.a = pn.b = -1;
+            pn.k = 0.0;
+            pn.conv = -1;
+            pn.prec = info[i].prec;
+            pn.rows = t ? info[i].cols : info[i].rows;
+            pn.cols = t ? info[i].rows : info[i].cols;
+            if (N.op == COOT_LEAF) {
+                const coot_operand& o = ops[N.a];
+                bool tt = t;
+                int64_t ld = o.ld;
+                bool vec = o.n_rows == 1 || o.n_cols == 1;
+                if (tt && vec && contiguous(o) && (o.n_rows == 1 ? o.ld == 1 : true)) {
+                    // a contiguous vector has the same linear order either way
+                    tt = false;
+                    ld = pn.rows > 0 ? pn.rows : 1;
+                }
+                auto key = std::make_pair(N.a, tt);
+                auto it = read_of.find(key);
+                int r;
+                if (it == read_of.end()) {
+                    r = (int)P.reads.size();
+                    P.reads.push_back({N.a, tt, o.dtype, ld});
+                    read_of[key] = r;
+                } else {
+                    r = it->second;
+                }
+                pn.a = r;
+            } else {
+                pn.a = rebuild(N.a, t);
+                if (is_binary(N.op)) pn.b = rebuild(N.b, t);
+                if (N.op == COOT_CONV) pn.conv = N.b;
+                if (is_scalar(N.op)) pn.k = pn.prec == 32 ? (double)(float)N.k : N.k;
+            }
+            uint64_t kb;
+            std::memcpy(&kb, &pn.k, 8);
+            auto key = std::make_tuple(pn.op, pn.a, pn.b, kb, pn.conv);
+            auto it = cse.find(key);
+            if (it != cse.end()) {
+                res = it->second;
+            } else {
+                res = (int)P.nodes.size();
+                P.nodes.push_back(pn);
+                cse[key] = res;
+            }
+        }
+        memo[{i, t}] = res;
+        return res;
+    };
+    P.root = rebuild(nn - 1, false);
+    if ((int)P.reads.size() > COOT_MAX_READS)
+        fail(COOT_ERR_UNSUPPORTED, "more than " + std::to_string(COOT_MAX_READS) + " distinct operand reads");
+
+    // --- aliasing of the output with the operands
+    {
+        uint64_t olo, ohi;
+        extent(*out, out->dtype, &olo, &ohi);
+        P.alias_out = false;
+        if (!(out->flags & COOT_OPERAND_HOST) && ohi > olo) {
+            for (int s = 0; s < n_ops; ++s) {
+                if (!slot_checked[s]) continue;
+                const coot_operand& o = ops[s];
+                uint64_t lo, hi;
+                extent(o, o.dtype, &lo, &hi);
+                if (hi <= lo || hi <= olo || ohi <= lo) continue;
+                bool same = P.red_op < 0 && o.ptr == out->ptr && o.ld == out->ld && o.dtype == out->dtype &&
+                            o.n_rows == out->n_rows && o.n_cols == out->n_cols;
+                for (const Read& r : P.reads)
+                    if (r.slot == s && r.trans) same = false;
+                if (!same) fail(COOT_ERR_ALIAS, "out overlaps operand " + std::to_string(s));
+                P.alias_out = true;
+            }
+        }
+    }
+
+    // --- kernel kind
+    bool any_trans = false, all_contig = true;
+    for (const Read& r : P.reads) {
+        if (r.trans) any_trans = true;
+        const coot_operand& o = ops[r.slot];
+        if (!r.trans && !(o.n_cols <= 1 || r.ld == P.rows || P.cols <= 1)) all_contig = false;
+    }
+    if (P.red_op < 0 && !(P.cols <= 1 || out->ld == P.rows)) all_contig = false;
+    P.temp_needed = false;
+    P.product_form = false;
+    P.prod_a = P.prod_b = -1;
+    if (P.red_op < 0) {
+        P.kind = (any_trans || !all_contig) ? K_EW_TILED : K_EW_FLAT;
+    } else if (P.dim < 0) {
+        P.kind = (any_trans || !all_contig) ? K_RED_TILED : K_RED_FLAT;
+    } else {
+        if (any_trans) P.temp_needed = true;
+        if (P.dim == 0)
+            P.kind = P.rows >= 64 ? K_RED_COL : K_RED_COLT;
+        else
+            P.kind = K_RED_ROW;
+    }
+    if (P.red_op >= 0 && (P.red_op == COOT_RED_ACCU || P.red_op == COOT_RED_SUM || P.red_op == COOT_RED_DOT) &&
+        P.nodes[P.root].op == COOT_SCHUR) {
+        P.product_form = true;
+        P.prod_a = P.nodes[P.root].a;
+        P.prod_b = P.nodes[P.root].b;
+    }
+
+    // --- vector width of the flat and per-column kinds
+    P.ve = 1;
+    if (P.kind == K_EW_FLAT || P.kind == K_RED_FLAT || P.kind == K_RED_COL) {
+        int maxsz = 1;
+        for (const Read& r : P.reads) maxsz = std::max(maxsz, itemsize(r.dtype));
+        if (P.red_op < 0) maxsz = std::max(maxsz, itemsize(out->dtype));
+        int ve = 16 / maxsz;
+        bool ok = true;
+        for (const Read& r : P.reads) {
+            uintptr_t p = (uintptr_t)ops[r.slot].ptr;
+            if (p % (uintptr_t)(ve * itemsize(r.dtype))) ok = false;
+            if (P.kind == K_RED_COL && (r.ld % ve)) ok = false;
+        }
+        if (P.red_op < 0 && ((uintptr_t)out->ptr % (uintptr_t)(ve * itemsize(out->dtype)))) ok = false;
+        P.ve = ok ? ve : 1;
+    }
+
+    // --- canonical text of the element function (part of the kernel key)
+    std::ostringstream s;
+    for (const Read& r : P.reads) s << "r" << dtype_name(r.dtype) << (r.trans ? "T" : "S") << ";";
+    for (const PNode& n : P.nodes) {
+        uint64_t kb;
+        std::memcpy(&kb, &n.k, 8);
+        s << n.op << "," << n.a << "," << n.b << "," << n.prec << "," << n.conv << "," << hex64(kb) << ";";
+    }
+    s << "root" << P.root;
+    P.body_sig = s.str();
+    return P;
+}
+
+// ----------------------------------------------------------- configurations
+LaunchCfg config_of(int index)
+{
+    LaunchCfg c;
+    c.ept = 1 << ((index >> 4) & 3);
+    c.block = 64 << ((index >> 2) & 3);
+    c.split = 1 << (index & 3);
+    return c;
+}
+
+int config_index(const LaunchCfg& c)
+{
+    auto lg = [](int v) {
+        int l = 0;
+        while ((1 << l) < v) ++l;
+        return l;
+    };
+    return lg(c.ept) * 16 + lg(c.block / 64) * 4 + lg(c.split);
+}
+
+LaunchCfg default_config(const Plan& p)
+{
+    LaunchCfg c;
+    c.ept = 4;
+    c.block = 256;
+    c.split = 4;
+    if (p.kind == K_RED_COL) c.ept = 2;
+    return c;
+}
+
+LaunchCfg normalise_config(const Plan& p, LaunchCfg c)
+{
+    if (p.kind == K_EW_TILED || p.kind == K_RED_TILED) c.block = 256;  // fixed 64x64 tile shape
+    return c;
+}
+
+}  // namespace coot

@@ -1,0 +1,150 @@
+"""Host-only checks of the C ABI: the library loads without a GPU, exports every
+entry point of include/coot.h, validates arguments before touching a device,
+and generates kernels that compile for gfx950 under strict floating-point
+rules."""
+import os
+import re
+import subprocess
+
+import numpy as np
+import pytest
+
+import synth
+from synth import abs_, exp, leaf, leaves, sqrt, trans, conv
+
+from paper_2308_03120_amd import coot
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+F = coot.fake_operand
+G = 1 << 40
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _lib():
+    from paper_2308_03120_amd import build
+
+    if not os.path.exists(coot.LIB_PATH):
+        build.build()
+    coot.lib()
+
+
+def header_functions():
+    with open(os.path.join(ROOT, "include", "coot.h")) as f:
+        text = f.read()
+    return sorted(set(re.findall(r"^\s*(?:int|int64_t|const char\*)\s+(coot_\w+)\s*\(", text, re.M)))
+
+
+def test_every_declared_function_is_exported():
+    out = subprocess.check_output(["nm", "-D", "--defined-only", coot.LIB_PATH], text=True)
+    syms = {line.split()[-1] for line in out.splitlines() if line.strip()}
+    declared = header_functions()
+    assert len(declared) >= 20
+    missing = [f for f in declared if f not in syms]
+    assert not missing, missing
+    assert set(coot.EXPORTS) <= set(declared)
+
+
+def code(fn):
+    try:
+        fn()
+    except coot.CootError as e:
+        return e.code
+    return 0
+
+
+def test_validation_errors():
+    A = F(10, 20, ptr=G)
+    B = F(20, 10, ptr=2 * G)
+    O = F(10, 20, ptr=3 * G)
+    x, y = leaves(2)
+    assert code(lambda: coot.validate(None, -1, x + y, [A, A], O)) == 0
+    assert code(lambda: coot.validate(None, -1, x + y, [A, B], O)) == -2          # shape
+    assert code(lambda: coot.validate(None, -1, trans(y) + x, [A, B], O)) == 0
+    assert code(lambda: coot.validate(None, -1, x + y, [A], O)) == -1             # slot out of range
+    assert code(lambda: coot.validate(None, -1, [("plus", 0, 1, 0)], [A], O)) == -1  # child not earlier
+    assert code(lambda: coot.validate(None, -1, [("leaf", 0, -1, 0), (99, 0, -1, 0)], [A], O)) == -1
+    assert code(lambda: coot.validate(None, -1, x + y, [A, F(10, 20, "f64", ptr=4 * G)], O)) == -3  # mixed precision
+    assert code(lambda: coot.validate(None, -1, x, [A], F(20, 10, ptr=3 * G))) == -2  # out shape
+    assert code(lambda: coot.validate(None, -1, x, [F(10, 20, ld=5, ptr=G)], O)) == -10  # ld < rows
+    assert code(lambda: coot.validate(None, -1, x, [F(10, 20, ptr=0)], O)) == -10      # NULL with elements
+    assert code(lambda: coot.validate(None, -1, x, [A], F(10, 20, "u64", ptr=3 * G))) == -3
+    # aliasing: exact in-place is fine, a transposed read of the output is not
+    assert code(lambda: coot.validate(None, -1, x + y, [A, O], O)) == 0
+    S = F(10, 10, ptr=5 * G)
+    assert code(lambda: coot.validate(None, -1, trans(x) + x, [S], S)) == -4
+    assert code(lambda: coot.validate(None, -1, x + 1.0, [F(10, 20, ptr=3 * G + 4)], O)) == -4  # shifted overlap
+    # reductions
+    assert code(lambda: coot.validate("accu", -1, x, [A], F(1, 1, ptr=3 * G))) == 0
+    assert code(lambda: coot.validate("accu", 0, x, [A], F(1, 20, ld=1, ptr=3 * G))) == -10
+    assert code(lambda: coot.validate("sum", 0, x, [A], F(1, 20, ld=1, ptr=3 * G))) == 0
+    assert code(lambda: coot.validate("sum", 1, x, [A], F(10, 1, ptr=3 * G))) == 0
+    assert code(lambda: coot.validate("sum", 1, x, [A], F(20, 1, ptr=3 * G))) == -2
+    assert code(lambda: coot.validate("dot", -1, x + y, [A, A], F(1, 1, ptr=3 * G))) == -1
+    assert code(lambda: coot.validate("index_max", -1, x, [A], F(1, 1, ptr=3 * G))) == -3
+    assert code(lambda: coot.validate("index_max", -1, x, [A], F(1, 1, "u64", ptr=3 * G))) == 0
+    assert code(lambda: coot.validate("max", -1, x, [F(0, 5, ptr=0)], F(1, 1, ptr=3 * G))) == -5
+    assert code(lambda: coot.validate("accu", -1, x, [F(0, 5, ptr=0)], F(1, 1, ptr=3 * G))) == 0
+    assert code(lambda: coot.validate("accu", -1, x, [A], F(1, 1, ptr=G + 8))) == -4  # result inside an operand
+
+
+def test_bad_config_rejected():
+    A = F(10, 20, ptr=G)
+    O = F(10, 20, ptr=3 * G)
+    e = coot.expr(leaf(0) + 1.0, cfg=(3, 256, 1))
+    import ctypes as C
+    arr, n = coot._ops([A])
+    assert coot.lib().coot_validate(-1, -1, C.byref(e), arr, n, C.byref(O)) == -10
+    assert coot.config_of(0) == (1, 64, 1) and coot.config_of(63) == (8, 512, 8)
+
+
+def test_generated_source_is_strict_ieee():
+    x, y = leaves(2)
+    src = coot.kernel_source(None, -1, sqrt(abs_(x)) % y - x / (1 + abs_(y)),
+                             [F(1 << 20, 1, ptr=G), F(1 << 20, 1, ptr=2 * G)], F(1 << 20, 1, ptr=3 * G))
+    assert "#pragma clang fp contract(off)" in src
+    body = src[src.find("CD float x_eval"):]
+    body = body[: body.find("}")]
+    assert "fma" not in body and "__f" not in body.replace("__builtin_fabsf", "")
+    assert "sqrtf(" in body and " / " in body
+
+
+def test_rewrites_move_trans_to_operands_and_merge_reads():
+    x, y = leaves(2)
+    A = F(30, 40, ptr=G)
+    B = F(40, 30, ptr=2 * G)
+    src = coot.kernel_source(None, -1, trans(trans(x) + y) - x, [A, B], F(30, 40, ptr=3 * G))
+    tree = [l for l in src.splitlines() if l.startswith("// tree:")][0]
+    reads = re.findall(r"r(f32|f64|f16|bf16)(S|T)", tree)
+    assert reads == [("f32", "S"), ("f32", "T")]   # x read once, y read transposed
+    assert ",30," not in tree                       # no transpose node left
+    s2 = coot.kernel_source(None, -1, x % x + x, [A], F(30, 40, ptr=3 * G))
+    assert len(re.findall(r"r(f32)(S)", [l for l in s2.splitlines() if l.startswith("// tree:")][0])) == 1
+
+
+def test_features_shape_and_content():
+    x, y = leaves(2)
+    f = coot.features(None, -1, exp(x) + y % y, [F(1024, 64, ptr=G), F(1024, 64, ptr=2 * G)], F(1024, 64, ptr=3 * G))
+    assert f.shape == (32,)
+    assert f[0] == pytest.approx(np.log2(65536 + 1))
+    assert f[5] == 2 and f[18] == 1 and f[15] == 1 and f[14] == 1 and f[23] == 0
+    fr = coot.features("sum", 1, x, [F(1024, 64, ptr=G)], F(1024, 1, ptr=3 * G))
+    assert fr[23] == 1 and fr[24] == 1 and fr[27] == 1
+
+
+@pytest.mark.parametrize("red,dim,tree,ops,out", [
+    (None, -1, "Y", [(1000, 1000)] * 4, (1000, 1000)),
+    ("accu", -1, "AB", [(1000, 1000)] * 4, (1, 1)),
+    ("sum", 0, "A", [(1000, 1000)] * 4, (1, 1000)),
+    ("sum", 1, "A", [(1000, 1000)] * 4, (1000, 1)),
+    ("index_max", -1, "absB", [(1000, 1000)] * 4, (1, 1)),
+    (None, -1, "T", [(37, 211), (211, 37)], (211, 37)),
+    ("accu", -1, "T", [(37, 211), (211, 37)], (1, 1)),
+])
+def test_generated_kernels_compile_for_gfx950(tmp_path, monkeypatch, red, dim, tree, ops, out):
+    monkeypatch.setenv("COOT_CACHE_DIR", str(tmp_path))
+    A, B, C, D = leaves(4)
+    trees = {"Y": 2.5 * A + B % C - exp(D), "AB": A % B, "A": A, "absB": abs_(B), "T": trans(A) + 0.5 * B}
+    opnds = [F(r, c, ptr=(i + 1) * G) for i, (r, c) in enumerate(ops)]
+    odt = "u64" if red == "index_max" else "f32"
+    o = F(out[0], out[1], odt, ld=1 if out[0] == 1 else out[0], ptr=9 * G)
+    assert coot.precompile(red, dim, trees[tree], opnds, o) in (0, 1)

@@ -1,0 +1,209 @@
+"""GPU parity of fused element-wise trees against the CPU oracle.
+
+Gates: arithmetic-only FP32/FP64 trees must equal the oracle's per-node
+rounded evaluation (EMU) bit for bit, and stay within 2e-7 (FP32) of the exact
+FP64 value in the running-error scale S; trees with exp/log within 1e-6.
+Shapes are ragged against the 16-byte vectors, the blocks and the 64x64 tiles.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from synth import abs_, conv, exp, leaf, leaves, log, sqrt, trans
+
+from gpu_util import dev, empty, host, same, scaled_err, mismatch_report, need_gpu, classes_match, torch
+
+pytestmark = pytest.mark.gpu
+
+from paper_2308_03120_amd import coot  # noqa: E402
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    need_gpu()
+    coot.init(0)
+
+
+def mats_like(g, shapes, dt, lo=-2.0, hi=2.0):
+    return [synth.Mat(synth.store(np.asfortranarray(g.uniform(lo, hi, s)), dt), dt) for s in shapes]
+
+
+def run_eval(tree, mats, out_dt=None, out_shape=None, **kw):
+    r, c, p = oracle.shape(tree.postfix(), mats)
+    out_dt = out_dt or ("f64" if p == 64 else "f32")
+    Y = empty(r, c, out_dt)
+    coot.eval(tree, [dev(m) for m in mats], Y, **kw)
+    torch.cuda.synchronize()
+    return host(Y)
+
+
+def check_tree(tree, mats, arithmetic=True, out_dt=None, tol=None, **kw):
+    g = run_eval(tree, mats, out_dt, **kw)
+    _, _, p = oracle.shape(tree.postfix(), mats)
+    em = oracle.evaluate(tree.postfix(), mats, "emu")
+    ex, S = oracle.evaluate(tree.postfix(), mats, "exact", scale=True)
+    odt = out_dt or ("f64" if p == 64 else "f32")
+    if odt != "f64":
+        em = oracle.round_to(odt, em.reshape(-1, order="F")).reshape(em.shape, order="F")
+    if arithmetic:
+        assert same(g, em), mismatch_report(g, em)
+    assert classes_match(g, em)
+    if odt in ("f32", "f64"):
+        t = tol if tol is not None else ((2e-7 if arithmetic else 1e-6) if p == 32 else (1e-15 if arithmetic else 1e-14))
+        e = scaled_err(g, ex, S)
+        assert e <= t, f"scaled error {e} > {t}"
+    return g
+
+
+@pytest.fixture(scope="module")
+def g():
+    return np.random.default_rng(2024)
+
+
+BIN = ["plus", "minus", "schur", "div"]
+SCAL = ["scal_plus", "scal_minus_post", "scal_minus_pre", "scal_times", "scal_div_post", "scal_div_pre"]
+
+
+@pytest.mark.parametrize("dt", ["f32", "f64"])
+@pytest.mark.parametrize("op", BIN)
+def test_binary_ops(g, dt, op):
+    ms = mats_like(g, [(517, 263), (517, 263)], dt)
+    check_tree(synth.E(op, (leaf(0), leaf(1))), ms)
+
+
+@pytest.mark.parametrize("dt", ["f32", "f64"])
+@pytest.mark.parametrize("op", SCAL)
+def test_scalar_ops(g, dt, op):
+    ms = mats_like(g, [(1001, 3)], dt)
+    check_tree(synth.E(op, (leaf(0),), 0.3), ms)
+
+
+@pytest.mark.parametrize("dt", ["f32", "f64"])
+def test_unary_ops(g, dt):
+    ms = mats_like(g, [(777, 41)], dt, 0.01, 30.0)
+    check_tree(sqrt(leaf(0)), ms)
+    check_tree(abs_(0.0 - leaf(0)), ms)
+    check_tree(exp(leaf(0) * 0.5), ms, arithmetic=False)
+    check_tree(log(leaf(0)), ms, arithmetic=False)
+    check_tree(exp(log(leaf(0))) - leaf(0), ms, arithmetic=False,
+               tol=2e-6 if dt == "f32" else 1e-14)
+
+
+def test_cfg1_tree_small_ragged():
+    ms = synth.cfg1_inputs(67, 45)
+    check_tree(synth.cfg1_trees()["Y"], [ms[k] for k in "ABCD"], arithmetic=False)
+
+
+@pytest.mark.parametrize("dt", ["f32", "f64"])
+def test_cfg2_trees_small(dt):
+    d = synth.cfg2_inputs(dt, n=(1 << 16) + 3, n_ties=4)
+    x, y = d["x"], d["y"]
+    t = synth.cfg2_trees()
+    check_tree(t["z"], [x, y])
+    check_tree(t["axpy"], [x, y])
+
+
+@pytest.mark.parametrize("dt", ["f32", "f64"])
+def test_axpy_in_place(dt):
+    d = synth.cfg2_inputs(dt, n=100_003, n_ties=0)
+    X, Y = dev(d["x"]), dev(d["y"])
+    coot.eval(synth.cfg2_trees()["axpy"], [X, Y], Y)  # y = y + 0.75*x, out aliases y
+    torch.cuda.synchronize()
+    em = oracle.evaluate(synth.cfg2_trees()["axpy"].postfix(), [d["x"], d["y"]], "emu")[:, 0]
+    assert same(host(Y), em)
+
+
+def test_transposed_reads(g):
+    for (r, c) in [(37, 211), (64, 64), (65, 130), (1000, 777), (1, 300), (300, 1)]:
+        A, B = mats_like(g, [(r, c), (c, r)], "f32")
+        x, y = leaves(2)
+        check_tree(trans(x) + 0.5 * y, [A, B])
+        check_tree(trans(trans(x) % y) - x, [A, B])
+
+
+def test_transposed_reads_f64_and_16bit(g):
+    A, B = mats_like(g, [(130, 70), (70, 130)], "f64")
+    check_tree(trans(leaf(0)) / (1.0 + abs_(leaf(1))), [A, B])
+    for dt in ("bf16", "f16"):
+        A, B = mats_like(g, [(130, 70), (70, 130)], dt)
+        check_tree(trans(leaf(0)) + leaf(1) % leaf(1), [A, B])
+
+
+def test_submatrix_views_and_misalignment(g):
+    A, B = mats_like(g, [(301, 97), (301, 97)], "f32")
+    x, y = leaves(2)
+    t = x % y - 2.5
+    em = oracle.evaluate(t.postfix(), [A, B], "emu")
+    for ldA, ldB, ldO, off in [(301, 301, 301, 1), (320, 301, 310, 0), (512, 333, 301, 3)]:
+        dA, dB = dev(A, ld=ldA, offset=off), dev(B, ld=ldB)
+        O = empty(301, 97, "f32", ld=ldO, offset=off)
+        coot.eval(t, [dA, dB], O)
+        torch.cuda.synchronize()
+        assert same(host(O), em), (ldA, ldB, ldO, off)
+
+
+@pytest.mark.parametrize("dt", ["bf16", "f16"])
+def test_sixteen_bit_storage(g, dt):
+    A, B = mats_like(g, [(1003, 65), (1003, 65)], dt, -100, 100)
+    x, y = leaves(2)
+    check_tree(x % y + 0.1, [A, B])                 # FP32 out
+    check_tree(x % y + 0.1, [A, B], out_dt=dt)      # rounded to the 16-bit type on store
+    check_tree(conv(x % y, dt) - y, [A, B])         # explicit conversion node
+
+
+def test_f64_to_16bit_rounding(g):
+    # values near half-way points of the 16-bit grids: a double rounding would show
+    base = g.uniform(1, 2, (4099, 1))
+    for dt, fb in (("f16", 10), ("bf16", 7)):
+        q = 2.0 ** -fb
+        vals = np.floor(base / q) * q + q / 2 + (g.integers(-1, 2, base.shape) * 2.0 ** -40)
+        M = synth.Mat(np.asfortranarray(vals), "f64")
+        check_tree(leaf(0) * 1.0, [M], out_dt=dt)
+        check_tree(conv(leaf(0), dt) + 0.0, [M])
+
+
+def test_mixed_precision_conversion(g):
+    A = mats_like(g, [(500, 9)], "f32")[0]
+    Bd = mats_like(g, [(500, 9)], "f64")[0]
+    check_tree(conv(leaf(0), "f64") % leaf(1), [A, Bd])
+    check_tree(conv(leaf(1), "f32") + leaf(0), [A, Bd])
+
+
+def test_empty_and_single(g):
+    E0 = synth.Mat(np.zeros((0, 5), np.float32, order="F"), "f32")
+    Y = empty(0, 5)
+    coot.eval(leaf(0) + 1.0, [dev(E0)], Y)
+    one = mats_like(g, [(1, 1)], "f32")
+    check_tree(sqrt(abs_(leaf(0))) * 3.0, one)
+
+
+def test_special_values():
+    v = np.array([0.0, -0.0, np.inf, -np.inf, np.nan, 1e-45, -1e-45, 3.4e38, -3.4e38, 1.0], np.float32)
+    A = synth.Mat(np.asfortranarray(v.reshape(-1, 1)), "f32")
+    B = synth.Mat(np.asfortranarray(v[::-1].copy().reshape(-1, 1)), "f32")
+    x, y = leaves(2)
+    for t in (x + y, x - y, x % y, x / y, sqrt(x), abs_(x), x * 2.0, 1.0 / x):
+        g = run_eval(t, [A, B])
+        em = oracle.evaluate(t.postfix(), [A, B], "emu")
+        assert same(g, em), (t.op, mismatch_report(g, em))
+
+
+def test_unfused_equals_fused(g):
+    ms = mats_like(g, [(333, 77)] * 3, "f32")
+    a, b, c = leaves(3)
+    t = sqrt(abs_(a)) % b - a / (1.0 + abs_(b)) + exp(c * 0.25)
+    f = run_eval(t, ms)
+    u = run_eval(t, ms, unfused=True)
+    assert same(f, u)
+    ms2 = mats_like(g, [(80, 50), (50, 80)], "f32")
+    t2 = trans(a) * 3.0 + b
+    assert same(run_eval(t2, ms2), run_eval(t2, ms2, unfused=True))
+
+
+@pytest.mark.parametrize("cfg", [0, 5, 21, 42, 63])
+def test_every_config_gives_same_bits(g, cfg):
+    ms = mats_like(g, [(100_001, 1)] * 2, "f32")
+    t = leaf(0) % leaf(1) + 0.75
+    em = oracle.evaluate(t.postfix(), ms, "emu")
+    assert same(run_eval(t, ms, cfg=cfg), em)
