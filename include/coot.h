@@ -121,10 +121,14 @@ typedef struct coot_node {
 } coot_node;
 
 /* Launch configuration.  ept = 16-byte vectors per thread per step
- * {1,2,4,8}; block = threads per block {64,128,256,512}; split = occupancy
- * level {1,2,4,8}: the grid is capped at 256 CUs x (4*split waves per CU).
- * All zero = let the library choose (default heuristic, tuned cache or the
- * learned cost model, see coot_set_tuning). */
+ * {1,2,4,8}; block = threads per block {64,128,256,512}; split = grid level
+ * {1,2,4,8}: 1, 2, 4 give a persistent grid-stride launch of
+ * split * (1024 / block) blocks per CU (for reductions: that many partial
+ * results), 8 gives one pass with as many blocks as the work needs (at most
+ * 16384 partial results for a reduction).  Tiled kernels (transposed reads)
+ * have a fixed 256-thread 64x64 tile and use only split.  All zero = let the
+ * library choose (default heuristic, tuned cache or the learned cost model,
+ * see coot_set_tuning). */
 typedef struct coot_config {
     int32_t ept;
     int32_t block;

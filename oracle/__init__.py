@@ -177,9 +177,18 @@ def evaluate_at(tree, mats, lin: np.ndarray, mode: str = "exact") -> np.ndarray:
     return out[: lin.size]
 
 
-def reduce(op: str, tree, mats, dim: int = -1, mode: str = "emu"):
+SUM_LIKE = ("accu", "sum", "dot", "norm1", "norm2")
+
+
+def reduce(op: str, tree, mats, dim: int = -1, mode: str = None):
     """Reduction of a tree.  Returns (values, indices, abs_sums) as 1-D arrays
-    (length 1 for dim=-1, n_cols for dim=0, n_rows for dim=1)."""
+    (length 1 for dim=-1, n_cols for dim=0, n_rows for dim=1).
+
+    ``mode`` is how the tree is evaluated before reducing: "exact" (FP64 at
+    every node) or "emu" (rounded at every node to the compute precision).
+    Default: exact for sums, emu for selections (min/max/index)."""
+    if mode is None:
+        mode = "exact" if op in SUM_LIKE else "emu"
     r, c, _ = shape(tree, mats)
     n_out = 1 if dim < 0 else (c if dim == 0 else r)
     vals = np.empty(max(1, n_out), np.float64)

@@ -410,12 +410,15 @@ double oracle_dot2(const double* x, const double* y, int64_t n)
  *   dim = -1 : over all elements (column-major linear order);
  *   dim =  0 : one result per column (output 1 x n_cols);
  *   dim =  1 : one result per row    (output n_rows x 1).
- * Sum-like results (accu, sum, dot, norm1, norm2/fro) use EXACT values of the
- * tree and Sum2/Dot2.  For a tree whose root is an element-wise product the
- * sum is a dot product of the two children (Dot2), so no rounding of the
- * products enters the reference.  Selections (min, max, the norms "inf" and
- * "-inf", index_min, index_max) use the tree values in `mode` and keep the
- * lowest column-major index among equal values; NaN values are skipped; if
+ * The tree is evaluated in `mode`: EXACT gives the reference value of the
+ * expression; EMU gives the values the method itself produces per element
+ * (rounded at every node), whose accurate sum isolates the error of the
+ * summation from the error of the element-wise tree.  Sums (accu, sum, dot,
+ * norm1, norm2/fro) use Sum2/Dot2.  For a tree whose root is an element-wise
+ * product the sum is a dot product of the two children (Dot2), so no rounding
+ * of the products enters the reference.  Selections (min, max, the norms
+ * "inf" and "-inf", index_min, index_max) keep the lowest column-major index
+ * among equal values; NaN values are skipped; if
  * every value is NaN the value is NaN and the index 0.  Empty input: sums
  * give 0, selections return E_EMPTY.
  *
@@ -448,13 +451,13 @@ int oracle_reduce(int rop, int dim, const or_node* nd, int nn, const or_leaf* lv
         va = (double*)malloc((size_t)(n > 0 ? n : 1) * sizeof(double));
         vb = (double*)malloc((size_t)(n > 0 ? n : 1) * sizeof(double));
         if (!va || !vb) { free(va); free(vb); return E_NOMEM; }
-        rc = oracle_eval(nd, nd[root].a + 1, lv, nl, MODE_EXACT, va, NULL, &r2, &c2);
+        rc = oracle_eval(nd, nd[root].a + 1, lv, nl, mode, va, NULL, &r2, &c2);
         /* the prefix ending at a child is a tree whose root is that child */
-        if (rc == OK) rc = oracle_eval(nd, nd[root].b + 1, lv, nl, MODE_EXACT, vb, NULL, &r2, &c2);
+        if (rc == OK) rc = oracle_eval(nd, nd[root].b + 1, lv, nl, mode, vb, NULL, &r2, &c2);
     } else {
         va = (double*)malloc((size_t)(n > 0 ? n : 1) * sizeof(double));
         if (!va) return E_NOMEM;
-        rc = oracle_eval(nd, nn, lv, nl, is_sum_like(rop) ? MODE_EXACT : mode, va, NULL, NULL, NULL);
+        rc = oracle_eval(nd, nn, lv, nl, mode, va, NULL, NULL, NULL);
     }
     if (rc != OK) { free(va); free(vb); return rc; }
 

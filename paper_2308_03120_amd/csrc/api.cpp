@@ -132,7 +132,13 @@ Scratch& scratch_for(hipStream_t st, size_t part_bytes, size_t res_bytes, size_t
 
 static int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
 
-int64_t grid_cap(const LaunchCfg& c) { return (int64_t)g_state.cus * std::max(1, (256 * c.split) / c.block); }
+// split 1, 2, 4: split * (1024 / block) blocks per CU (a persistent, grid-stride
+// launch); split 8: one pass, as many blocks as the work needs.
+int64_t grid_cap(const LaunchCfg& c)
+{
+    if (c.split >= 8) return INT64_C(1) << 40;
+    return (int64_t)g_state.cus * c.split * std::max(1, 1024 / c.block);
+}
 
 void launch(hipFunction_t f, int64_t grid, int block, coot_kargs& a, hipStream_t st)
 {
@@ -185,14 +191,14 @@ static Geometry geometry(const Plan& p, const LaunchCfg& c)
     case K_RED_FLAT: {
         int64_t nv = p.n / p.ve;
         G.grid = std::max<int64_t>(1, std::min(ceil_div(nv, (int64_t)c.block * c.ept), cap));
-        if (p.kind == K_RED_FLAT) G.grid = std::min<int64_t>(G.grid, 8192);
+        if (p.kind == K_RED_FLAT) G.grid = std::min<int64_t>(G.grid, 16384);
         break;
     }
     case K_EW_TILED:
     case K_RED_TILED: {
         int64_t nt = ceil_div(p.rows, 64) * ceil_div(p.cols, 64);
         G.block = 256;
-        G.grid = std::max<int64_t>(1, std::min(nt, (int64_t)g_state.cus * c.split));
+        G.grid = std::max<int64_t>(1, std::min(nt, c.split >= 8 ? nt : (int64_t)g_state.cus * c.split * 2));
         break;
     }
     case K_RED_COL:

@@ -196,13 +196,13 @@ static std::string combine_and_write(const Plan& p, const std::string& first, co
           << "); if (threadIdx.x == 0) "
           << put_value(p, j, p.red_op == COOT_RED_NORM2 ? "__builtin_sqrt(v)" : "v") << " }";
     } else {
-        s << "{ const AccI<double, " << (red_is_max(p.red_op) ? "true" : "false") << "> r = combine_idx<"
+        s << "{ const AccI<double, " << (red_is_max(p.red_op) ? "true" : "false") << "> cr = combine_idx<"
           << (red_is_max(p.red_op) ? "true" : "false") << ">((const double*)a.part, " << first << ", " << count << ", "
           << stride << "); if (threadIdx.x == 0) { ";
         if (p.red_op == COOT_RED_INDEX_MIN || p.red_op == COOT_RED_INDEX_MAX)
-            s << "put_u64(a.res, " << j << ", r.i);";
+            s << "put_u64(a.res, " << j << ", cr.i);";
         else
-            s << put_value(p, j, "(r.i < 0 ? __builtin_nan(\"\") : r.v)");
+            s << put_value(p, j, "(cr.i < 0 ? __builtin_nan(\"\") : cr.v)");
         s << " } }";
     }
     return s.str();
@@ -271,10 +271,10 @@ static std::string emit_flat(const Plan& p, const LaunchCfg& c, const std::strin
     }
     s << "            }\n        }\n    }\n";
     // tail elements that do not fill a vector
-    std::string targs = arglist(p, [](int j) { return "L" + std::to_string(j) + "[i]"; });
+    std::string targs = arglist(p, [](int j) { return "ldnt(L" + std::to_string(j) + " + i)"; });
     s << "    if (blockIdx.x == gridDim.x - 1)\n";
     s << "        for (i64 i = nv * " << VE << " + threadIdx.x; i < a.n; i += bs) ";
-    if (ew) s << "O[i] = " << narrow(p.out_dtype, rp, "x_eval(" + targs + ")") << ";\n";
+    if (ew) s << "stnt(O + i, (" << OS << ")(" << narrow(p.out_dtype, rp, "x_eval(" + targs + ")") << "));\n";
     else s << "{ " << accumulate(p, targs, "i") << " }\n";
     if (!ew) {
         s << "    __shared__ " << acc_type(p) << " lds_acc[8];\n";
@@ -328,7 +328,7 @@ static std::string emit_tiled(const Plan& p, const std::string& name)
         s << "            if (ig < R && jg < Cn) {\n";
         for (size_t j = 0; j < p.reads.size(); ++j)
             if (in_lds[j])
-                s << "                T" << j << "[ii][lane] = " << widen(p.reads[j].dtype, "L" + std::to_string(j) + "[jg + ig * ld" + std::to_string(j) + "]") << ";\n";
+                s << "                T" << j << "[ii][lane] = " << widen(p.reads[j].dtype, "ldnt(L" + std::to_string(j) + " + jg + ig * ld" + std::to_string(j) + ")") << ";\n";
         s << "            }\n        }\n        __syncthreads();\n";
     }
     s << "        const i64 ig = i0 + lane;\n        if (ig < R) {\n#pragma unroll\n";
@@ -342,12 +342,12 @@ static std::string emit_tiled(const Plan& p, const std::string& name)
         if (in_lds[j])
             args += "T" + J + "[lane][jj]";
         else if (p.reads[j].trans)
-            args += widen(p.reads[j].dtype, "L" + J + "[jg + ig * ld" + J + "]");
+            args += widen(p.reads[j].dtype, "ldnt(L" + J + " + jg + ig * ld" + J + ")");
         else
-            args += widen(p.reads[j].dtype, "L" + J + "[ig + jg * ld" + J + "]");
+            args += widen(p.reads[j].dtype, "ldnt(L" + J + " + ig + jg * ld" + J + ")");
     }
     if (ew)
-        s << "                    O[ig + jg * ldo] = " << narrow(p.out_dtype, rp, "x_eval(" + args + ")") << ";\n";
+        s << "                    stnt(O + ig + jg * ldo, (" << stype(p.out_dtype) << ")(" << narrow(p.out_dtype, rp, "x_eval(" + args + ")") << "));\n";
     else
         s << "                    " << accumulate(p, args, "(ig + jg * R)") << "\n";
     s << "                }\n            }\n        }\n    }\n";
@@ -392,7 +392,7 @@ static std::string emit_col(const Plan& p, const LaunchCfg& c, const std::string
     s << "#pragma unroll\n                    for (int k = 0; k < " << VE << "; ++k) { const i64 gi = v * " << VE
       << " + k; (void)gi; " << accumulate(p, args, "gi") << " }\n";
     s << "                }\n            }\n        }\n";
-    std::string targs = arglist(p, [](int j) { return "C" + std::to_string(j) + "[r]"; });
+    std::string targs = arglist(p, [](int j) { return "ldnt(C" + std::to_string(j) + " + r)"; });
     s << "        for (i64 r = nvr * " << VE << " + lane; r < a.rows; r += 64) { " << accumulate(p, targs, "r") << " }\n";
     s << "        wave_reduce(acc);\n";
     s << "        if (lane == 0) { " << write_direct(p, "j") << " }\n";
@@ -408,7 +408,7 @@ static std::string emit_colt(const Plan& p, const std::string& name)
     s << decl_reads(p, true);
     s << "    for (i64 j = (i64)blockIdx.x * blockDim.x + threadIdx.x; j < a.cols; j += (i64)gridDim.x * blockDim.x) {\n";
     s << "        " << acc_type(p) << " acc;\n        acc.init();\n";
-    std::string args = arglist(p, [](int j) { return "L" + std::to_string(j) + "[r + j * ld" + std::to_string(j) + "]"; });
+    std::string args = arglist(p, [](int j) { return "ldnt(L" + std::to_string(j) + " + r + j * ld" + std::to_string(j) + ")"; });
     s << "        for (i64 r = 0; r < a.rows; ++r) { " << accumulate(p, args, "r") << " }\n";
     s << "        " << write_direct(p, "j") << "\n    }\n}\n";
     return s.str();
@@ -424,7 +424,7 @@ static std::string emit_row(const Plan& p, const std::string& name)
     s << "    for (i64 w = (i64)blockIdx.x * blockDim.x + threadIdx.x; w < total; w += (i64)gridDim.x * blockDim.x) {\n";
     s << "        const i64 r = w % a.rows, q = w / a.rows;\n";
     s << "        " << acc_type(p) << " acc;\n        acc.init();\n";
-    std::string args = arglist(p, [](int j) { return "L" + std::to_string(j) + "[r + c * ld" + std::to_string(j) + "]"; });
+    std::string args = arglist(p, [](int j) { return "ldnt(L" + std::to_string(j) + " + r + c * ld" + std::to_string(j) + ")"; });
     s << "#pragma unroll 4\n        for (i64 c = q; c < a.cols; c += a.splits) { " << accumulate(p, args, "c") << " }\n";
     s << "        if (a.splits == 1) { " << write_direct(p, "r") << " } else { " << put_partial(p, "q * a.rows + r")
       << " }\n";
@@ -458,7 +458,10 @@ std::string kernel_source(const Plan& p, const LaunchCfg& cfg, std::string* name
     key << "kind" << p.kind << "|ve" << p.ve << "|ept" << cfg.ept << "|out" << p.out_dtype << "|red" << p.red_op
         << "|pw" << p.pairwise << "|" << body.str();
     std::string sig = key.str();
-    std::string name = std::string("coot_") + kname[p.kind] + "_" + hex64(fnv1a(sig));
+    // the name hashes the whole kernel text (prelude included): any change to
+    // the generated code gives the kernel a new name
+    static const uint64_t prelude_hash = fnv1a(prelude_source());
+    std::string name = std::string("coot_") + kname[p.kind] + "_" + hex64(fnv1a(sig) ^ (prelude_hash * 0x9e3779b97f4a7c15ull));
     std::string b = body.str();
     for (size_t pos; (pos = b.find(placeholder)) != std::string::npos;) b.replace(pos, placeholder.size(), name);
     if (name_out) *name_out = name;

@@ -70,8 +70,11 @@ template <> struct rawvec<8> { typedef u32x2 T; };
 template <> struct rawvec<4> { typedef u32 T; };
 template <> struct rawvec<2> { typedef u16 T; };
 
-#ifndef COOT_NT_LOADS
-#define COOT_NT_LOADS 0
+/* Streaming data is touched once: loads and stores carry the nontemporal
+ * hint, which measurably raises HBM throughput on gfx950 for streams larger
+ * than the caches. */
+#ifndef COOT_NT
+#define COOT_NT 1
 #endif
 
 template <class S, int VE>
@@ -80,7 +83,7 @@ CD void ldv(const S* __restrict__ p, i64 e0, S (&o)[VE])
     constexpr int B = (int)sizeof(S) * VE;
     if constexpr (B <= 16) {
         typedef typename rawvec<B>::T R;
-#if COOT_NT_LOADS
+#if COOT_NT
         R r = __builtin_nontemporal_load((const R*)(p + e0));
 #else
         R r = *(const R*)(p + e0);
@@ -100,11 +103,36 @@ CD void stv(S* p, i64 e0, const S (&o)[VE])
         typedef typename rawvec<B>::T R;
         R r;
         __builtin_memcpy(&r, o, B);
+#if COOT_NT
+        __builtin_nontemporal_store(r, (R*)(p + e0));
+#else
         *(R*)(p + e0) = r;
+#endif
     } else {
         stv<S, VE / 2>(p, e0, *(const S(*)[VE / 2])o);
         stv<S, VE / 2>(p, e0 + VE / 2, *(const S(*)[VE / 2])(o + VE / 2));
     }
+}
+
+/* single-element streaming load / store */
+template <class S>
+CD S ldnt(const S* p)
+{
+#if COOT_NT
+    return __builtin_nontemporal_load(p);
+#else
+    return *p;
+#endif
+}
+
+template <class S>
+CD void stnt(S* p, S v)
+{
+#if COOT_NT
+    __builtin_nontemporal_store(v, p);
+#else
+    *p = v;
+#endif
 }
 
 /* ------------------------------------------------------------------ */

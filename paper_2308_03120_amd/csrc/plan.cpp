@@ -395,13 +395,21 @@ int config_index(const LaunchCfg& c)
     return lg(c.ept) * 16 + lg(c.block / 64) * 4 + lg(c.split);
 }
 
+// Defaults from streaming measurements on MI355X: element-wise kernels (reads
+// plus a write) run best as one pass of 256-thread blocks with 4 vectors per
+// thread; read-only reductions best as a persistent grid of 512-thread blocks
+// (2 per CU) with 8 vectors in flight per thread.
 LaunchCfg default_config(const Plan& p)
 {
     LaunchCfg c;
-    c.ept = 4;
-    c.block = 256;
-    c.split = 4;
-    if (p.kind == K_RED_COL) c.ept = 2;
+    switch (p.kind) {
+    case K_EW_FLAT: c = {4, 256, 8}; break;
+    case K_RED_FLAT: c = {8, 512, 1}; break;
+    case K_RED_COL: c = {2, 256, 8}; break;
+    case K_EW_TILED:
+    case K_RED_TILED: c = {1, 256, 4}; break;
+    default: c = {4, 256, 8}; break;
+    }
     return c;
 }
 

@@ -195,3 +195,15 @@ def test_sum2_dot2_alone(g):
     exact = sum(Fraction(p) * Fraction(q) for p, q in zip(x[:2000], y[:2000]))
     assert abs(Fraction(oracle.dot2(x[:2000], y[:2000])) - exact) <= Fraction(np.spacing(abs(float(exact))))
     assert np.isfinite(d)
+
+
+def test_emu_sum_is_exact_sum_of_single_precision_tree_values(g):
+    a = g.uniform(-1, 1, 20_000).astype(np.float32)
+    b = g.uniform(-1, 1, 20_000).astype(np.float32)
+    vals = (a * a - np.float32(0.25)).astype(np.float64)   # IEEE single per node (numpy)
+    s, _, asum = oracle.reduce("accu", (leaf(0) % leaf(0) - 0.25).postfix(), [M(a)], mode="emu")
+    assert abs(s[0] - math.fsum(vals)) <= np.spacing(abs(math.fsum(vals)))
+    # product root in EMU mode: exact sum of products of the single-precision children
+    ch = (a + np.float32(1.0)).astype(np.float64) * b.astype(np.float64)
+    d, _, _ = oracle.reduce("dot", ((leaf(0) + 1.0) % leaf(1)).postfix(), [M(a), M(b)], mode="emu")
+    assert abs(d[0] - math.fsum(ch)) <= np.spacing(abs(math.fsum(ch)))
