@@ -20,6 +20,7 @@ from __future__ import annotations
 import argparse
 import json
 import os
+import re
 import sys
 import time
 
@@ -101,7 +102,14 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--unfused-steps", type=int, default=5)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--traffic-from", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
+                    help="write profiles/traffic.json from two rocprofv3 --pmc counter files and exit")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="first run the library's plain 1 GiB copy kernel 3 times (counter calibration)")
     args = ap.parse_args()
+    if args.traffic_from:
+        traffic_from(args.traffic_from[0], args.traffic_from[1], os.path.join(ROOT, "profiles", "traffic.json"))
+        return
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
               f"(asked for --gpus {args.gpus})", file=sys.stderr)
@@ -115,6 +123,13 @@ def main():
 
     torch.cuda.set_device(0)
     coot.init(0)
+    if args.calibrate_copy:
+        src = torch.zeros(1 << 28, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            coot.copy(dst, src)
+        torch.cuda.synchronize()
+        del src, dst
     steps = []
     bufs = []
     for dt in ("f32", "f64"):
@@ -129,29 +144,43 @@ def main():
         del d
     step_bytes = sum(b for _, b, _ in steps)
 
-    # warm-up (compiles / loads kernels)
-    for _ in range(max(1, args.warmup)):
-        for _, _, fn in steps:
-            fn()
+    # warm-up: compiles / loads kernels, then a breakdown pass with HIP events
+    # between the calls (on the stream the kernels are launched on)
+    for _, _, fn in steps:
+        fn()
     torch.cuda.synchronize()
-
-    # timed region: K steps, events between calls on the launch stream
-    K = args.steps
-    ev = [[torch.cuda.Event(enable_timing=True) for _ in range(len(steps) + 1)] for _ in range(K)]
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for k in range(K):
+    W = max(1, args.warmup)
+    ev = [[torch.cuda.Event(enable_timing=True) for _ in range(len(steps) + 1)] for _ in range(W)]
+    for k in range(W):
         ev[k][0].record()
         for i, (_, _, fn) in enumerate(steps):
             fn()
             ev[k][i + 1].record()
     torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
     per = {}
     for i, (name, nbytes, _) in enumerate(steps):
-        ts = [ev[k][i].elapsed_time(ev[k][i + 1]) for k in range(K)]
+        ts = [ev[k][i].elapsed_time(ev[k][i + 1]) for k in range(W)]
         avg = sum(ts) / len(ts)
         per[name] = {"us": round(avg * 1e3, 2), "GBps": round(nbytes / (avg * 1e-3) / 1e9, 1)}
+    dom = max(per, key=lambda k: per[k]["us"])
+    dom_i = [n for n, _, _ in steps].index(dom)
+
+    # timed region: K steps; events bracket only the dominant kernel
+    K = args.steps
+    evd = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(K)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(K):
+        for i, (_, _, fn) in enumerate(steps):
+            if i == dom_i:
+                evd[k][0].record()
+                fn()
+                evd[k][1].record()
+            else:
+                fn()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    dom_us = sum(a.elapsed_time(b) for a, b in evd) / K * 1e3
     ms_step = wall / K * 1e3
     value = step_bytes * K / wall / 1e9
 
@@ -171,22 +200,17 @@ def main():
     ms_unfused = (time.perf_counter() - t1) / Ku * 1e3
 
     # roofline of the dominant kernel (largest share of the step)
-    dom = max(per, key=lambda k: per[k]["us"])
     dom_bytes = dict((n, b) for n, b, _ in steps)[dom]
-    achieved = dom_bytes / (per[dom]["us"] * 1e-6) / 1e9
+    achieved = dom_bytes / (dom_us * 1e-6) / 1e9
     traffic = None
     tpath = os.path.join(ROOT, "profiles", "traffic.json")
     if os.path.exists(tpath):
-        try:
-            with open(tpath) as f:
-                tj = json.load(f)
-            # the counters only count while the kernel they were taken on is unchanged
-            from paper_2308_03120_amd import coot as _c  # noqa: F401
-            entry = tj.get(dom)
-            if entry and entry.get("kernel") == kernel_name_of(coot, synth, torch, bufs, dom):
-                traffic = entry.get("bytes")
-        except Exception as e:  # a stale or unreadable file means "not measured"
-            log("traffic.json ignored:", e)
+        with open(tpath) as f:
+            tj = json.load(f)
+        entry = tj.get("calls", {}).get(dom)
+        # the counters count only while the kernel they were taken on is unchanged
+        if entry and entry.get("kernel") == kernel_names(coot, synth).get(dom):
+            traffic = entry.get("bytes")
 
     cpu = None
     if not args.no_cpu:
@@ -215,33 +239,73 @@ def main():
         "unfused_ms_per_step": round(ms_unfused, 3),
         "speedup_vs_unfused": round(ms_unfused / ms_step, 3),
         "per_call": per,
-        "roofline": {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": PEAK_GBS,
+        "roofline": {"bound": "hbm", "kernel": dom, "kernel_us": round(dom_us, 2), "achieved": round(achieved, 1),
+                     "peak": PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / PEAK_GBS, 4), "traffic": traffic},
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)
 
 
-def kernel_name_of(coot, synth, torch, bufs, call):
-    """Name of the generated kernel behind a benchmark call (its text hash)."""
-    name, dt = call.rsplit("_", 1)
-    for d, X, Y, Yw, Z in bufs:
-        if d != dt:
-            continue
+def kernel_names(coot, synth):
+    """Generated kernel behind every benchmark call (the name hashes the kernel
+    text).  Host only: operand descriptors without memory, 256-byte aligned
+    like the device buffers."""
+    G = 1 << 40
+    names = {}
+    for dt in ("f32", "f64"):
+        X = coot.fake_operand(N, 1, dt, ptr=G)
+        Y = coot.fake_operand(N, 1, dt, ptr=2 * G)
+        Z = coot.fake_operand(N, 1, dt, ptr=3 * G)
         for nm, kind, tree, _ in ops_of(synth):
-            if nm != name:
-                continue
             if kind == "eval":
-                ops, out, red = ([X, Yw], Yw, None) if nm == "axpy" else ([X, Y], Z, None)
+                ops, out, red = ([X, Y], Y, None) if nm == "axpy" else ([X, Y], Z, None)
             else:
                 ops = [X, Y] if kind == "dot" else [X]
-                out = torch.empty(1, dtype=torch.int64 if kind == "index_max" else X.dtype, device="cuda")
+                out = coot.fake_operand(1, 1, "u64" if kind == "index_max" else dt, ptr=4 * G)
                 red = kind
             src = coot.kernel_source(red, -1, tree, ops, out)
-            for line in src.splitlines():
-                if 'extern "C" __global__' in line:
-                    return line.split("(")[0].split()[-1]
-    return None
+            m = re.search(r'extern "C" __global__ void __launch_bounds__\(\d+\) (coot_[a-z]+_[0-9a-f]{16})\(', src)
+            names[f"{nm}_{dt}"] = m.group(1) if m else None
+    return names
+
+
+def traffic_from(fetch_csv, write_csv, out_path):
+    """HBM bytes per launch of every benchmark kernel from two rocprofv3 --pmc
+    runs (FETCH_SIZE, WRITE_SIZE; KiB per dispatch), each scaled by what the
+    same counter reads for the library's plain copy of a known size."""
+    import csv
+    from collections import defaultdict
+
+    import synth
+    from paper_2308_03120_amd import coot
+
+    def load(p, counter):
+        agg = defaultdict(list)
+        for r in csv.DictReader(open(p)):
+            if r["Counter_Name"] == counter:
+                agg[r["Kernel_Name"]].append(float(r["Counter_Value"]))
+        return agg
+
+    f, w = load(fetch_csv, "FETCH_SIZE"), load(write_csv, "WRITE_SIZE")
+    copy = [k for k in f if "coot_copy16" in k]
+    assert copy, "the counter runs need --calibrate-copy"
+    copy_kib = (1 << 30) / 1024.0   # 1 GiB read and 1 GiB written per copy
+    f_scale = copy_kib / (sum(f[copy[0]]) / len(f[copy[0]]))
+    w_scale = copy_kib / (sum(w[copy[0]]) / len(w[copy[0]]))
+    names = kernel_names(coot, synth)
+    calls = {}
+    for call, kname in names.items():
+        if kname in f and kname in w:
+            fk = sum(f[kname]) / len(f[kname]) * f_scale
+            wk = sum(w[kname]) / len(w[kname]) * w_scale
+            calls[call] = {"kernel": kname, "fetch_bytes": round(fk * 1024), "write_bytes": round(wk * 1024),
+                           "bytes": round((fk + wk) * 1024)}
+    out = {"fetch_scale": f_scale, "write_scale": w_scale, "calls": calls,
+           "source": [os.path.basename(fetch_csv), os.path.basename(write_csv)]}
+    with open(out_path, "w") as fo:
+        json.dump(out, fo, indent=1, sort_keys=True)
+    print(json.dumps(out, indent=1))
 
 
 if __name__ == "__main__":

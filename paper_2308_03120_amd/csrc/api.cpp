@@ -75,6 +75,14 @@ static void init_device(int device, unsigned flags)
     g_state.arch = prop.gcnArchName;
     g_state.hbm = prop.totalGlobalMem;
     g_state.clock_khz = prop.clockRate;
+    // temporaries of the unfused and materialising paths come from the
+    // stream-ordered pool; keep freed blocks in it instead of unmapping them
+    hipMemPool_t pool;
+    if (hipDeviceGetDefaultMemPool(&pool, device) == hipSuccess) {
+        uint64_t keep = UINT64_MAX;
+        (void)hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &keep);
+    }
+    (void)hipGetLastError();
     g_state.init = true;
     if (flags & COOT_PRINT_INFO) {
         printf("coot: device %d: %s (%s), %d CUs, %.0f MHz, %.1f GiB HBM, kernel cache %s\n", device, prop.name,

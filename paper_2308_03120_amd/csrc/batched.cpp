@@ -1,17 +1,350 @@
-// Batched evaluation of many matrices' expressions in one persistent launch.
+// Batched evaluation: the expressions (and per-matrix reductions) of many
+// matrices of different shapes in one persistent launch, replayed through a
+// hipGraph.  The paper names collections of matrices (Cube) as roadmap work
+// and notes that small matrices use a GPU poorly (Sections 3 and 6); one
+// launch over the tiles of all matrices is this library's answer to both.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstring>
+#include <mutex>
+#include <set>
+#include <vector>
+
 #include "internal.h"
+#include "jit.h"
 #include "runtime.h"
 
+using namespace coot;
+
+struct coot_batch_plan {
+    Kernel k{};
+    coot_batch_item_d* d_items = nullptr;
+    int* d_tile_item = nullptr;
+    int* d_zero_tiles = nullptr;
+    double* d_part = nullptr;
+    unsigned* d_counters = nullptr;
+    int64_t n_tiles = 0, n_items = 0, max_item_tiles = 1;
+    int64_t grid = 1;
+    coot_bargs args{};
+    uint32_t flags = 0;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    // what the baselines need
+    std::vector<coot_batch_item_d> h_items;
+    std::vector<coot_node> nodes, red_nodes;
+    std::vector<int32_t> slot_dtypes;
+    int32_t n_slots = 0, out_dtype = COOT_F32, red_op = COOT_RED_ACCU, red_dtype = COOT_F32;
+    bool has_out = false, has_red = false;
+    void* red_out = nullptr;
+    int y_prec = 32;
+};
+
+namespace {
+
+std::mutex g_plans_mu;
+std::set<coot_batch_plan*> g_plans;
+
+template <class F>
+int guard3(F&& f)
+{
+    try {
+        return f();
+    } catch (const Error& e) {
+        set_error(e.code, e.msg);
+        return e.code;
+    } catch (const std::bad_alloc&) {
+        set_error(COOT_ERR_NOMEM, "out of host memory");
+        return COOT_ERR_NOMEM;
+    } catch (const std::exception& e) {
+        set_error(COOT_ERR_ARG, e.what());
+        return COOT_ERR_ARG;
+    }
+}
+
+void launch_b(hipFunction_t f, int64_t grid, coot_bargs& a, hipStream_t st)
+{
+    void* params[] = {&a};
+    hipchk(hipModuleLaunchKernel(f, (unsigned)std::max<int64_t>(1, grid), 1, 1, 256, 1, 1, 0, st, params, nullptr),
+           "hipModuleLaunchKernel(batch)");
+    g_state.launches++;
+}
+
+void free_plan(coot_batch_plan* p)
+{
+    if (p->exec) (void)hipGraphExecDestroy(p->exec);
+    if (p->graph) (void)hipGraphDestroy(p->graph);
+    (void)hipFree(p->d_items);
+    (void)hipFree(p->d_tile_item);
+    (void)hipFree(p->d_zero_tiles);
+    (void)hipFree(p->d_part);
+    (void)hipFree(p->d_counters);
+    delete p;
+}
+
+// trans parity of every leaf slot (bit 0: read straight, bit 1: read transposed)
+std::vector<int> slot_parities(const coot_expr* e, int n_slots)
+{
+    const int nn = e->n_nodes;
+    std::vector<int> mask(nn, 0), slot(n_slots, 0);
+    mask[nn - 1] = 1;
+    for (int i = nn - 1; i >= 0; --i) {
+        const coot_node& N = e->nodes[i];
+        if (!mask[i]) continue;
+        if (N.op == COOT_LEAF) {
+            if (N.a >= 0 && N.a < n_slots) slot[N.a] |= mask[i];
+            continue;
+        }
+        int m = mask[i];
+        if (N.op == COOT_TRANS) m = ((m & 1) << 1) | ((m >> 1) & 1);
+        if (N.a >= 0 && N.a < i) mask[N.a] |= m;
+        if (N.op >= COOT_PLUS && N.op <= COOT_DIV && N.b >= 0 && N.b < i) mask[N.b] |= m;
+    }
+    return slot;
+}
+
+}  // namespace
+
 namespace coot {
-void batch_destroy_all() {}
+void batch_destroy_all()
+{
+    std::lock_guard<std::mutex> lk(g_plans_mu);
+    for (auto* p : g_plans) free_plan(p);
+    g_plans.clear();
+}
 }  // namespace coot
 
 extern "C" {
-int coot_batch_create(const coot_batch*, void*, coot_batch_plan**)
+
+int coot_batch_create(const coot_batch* b, void* stream, coot_batch_plan** out_plan)
 {
-    coot::set_error(COOT_ERR_UNSUPPORTED, "batched evaluation not built yet");
-    return COOT_ERR_UNSUPPORTED;
+    return guard3([&] {
+        if (!b || !out_plan) fail(COOT_ERR_ARG, "NULL batch or plan pointer");
+        *out_plan = nullptr;
+        if (!b->expr || !b->expr->nodes || b->expr->n_nodes < 1) fail(COOT_ERR_BAD_TREE, "batch: empty expression");
+        if (b->n_slots < 1 || b->n_slots > 6) fail(COOT_ERR_UNSUPPORTED, "batch: 1 to 6 operand slots");
+        if (b->n_items < 0) fail(COOT_ERR_ARG, "batch: negative item count");
+        if (!b->slot_dtypes || !b->shapes || (b->n_items > 0 && !b->leaf_ptrs)) fail(COOT_ERR_ARG, "batch: NULL table");
+        if (b->flags & ~(COOT_BATCH_NO_GRAPH | COOT_BATCH_PER_ITEM | COOT_BATCH_UNFUSED))
+            fail(COOT_ERR_ARG, "batch: unknown flags");
+        const bool has_out = b->out_ptrs != nullptr;
+        const bool has_red = b->red_expr != nullptr;
+        if (!has_out && !has_red) fail(COOT_ERR_ARG, "batch: neither outputs nor a reduction requested");
+        for (int s = 0; s < b->n_slots; ++s)
+            if (!is_value_dtype(b->slot_dtypes[s])) fail(COOT_ERR_DTYPE, "batch: slot dtype");
+        if (has_out && !is_value_dtype(b->out_dtype)) fail(COOT_ERR_DTYPE, "batch: out dtype");
+        if (has_red) {
+            const int base = b->red_op & 0xff;
+            if ((b->red_op & ~(0xff | COOT_RED_PAIRWISE)) ||
+                (base != COOT_RED_ACCU && base != COOT_RED_SUM && base != COOT_RED_DOT && base != COOT_RED_NORM1 &&
+                 base != COOT_RED_NORM2))
+                fail(COOT_ERR_UNSUPPORTED, "batch: only accu, sum, dot, norm1 and norm2 per item");
+            if (b->red_dtype != COOT_F32 && b->red_dtype != COOT_F64) fail(COOT_ERR_DTYPE, "batch: reduction dtype");
+            if (!b->red_out && b->n_items > 0) fail(COOT_ERR_ARG, "batch: NULL red_out");
+        }
+        if (b->expr->flags != 0 || (has_red && b->red_expr->flags != 0)) fail(COOT_ERR_ARG, "batch: expression flags");
+        ensure_init();
+
+        // per-slot transposition and the shape rule it implies
+        std::vector<int> par = slot_parities(b->expr, b->n_slots);
+        bool need_square = false;
+        for (int s = 0; s < b->n_slots; ++s) need_square = need_square || par[s] == 3;
+        for (int i = 0; i < b->n_items; ++i) {
+            int64_t r = b->shapes[2 * i], c = b->shapes[2 * i + 1];
+            if (r < 0 || c < 0 || r > (1 << 30) || c > (1 << 30)) fail(COOT_ERR_SHAPE, "batch: item shape out of range");
+            if (need_square && r != c) fail(COOT_ERR_SHAPE, "batch: a slot read both straight and transposed needs square items");
+        }
+        // plan the element function on canonical shapes (never vectors)
+        const int64_t cr = need_square ? 3 : 2, cc = 3;
+        const uintptr_t G = uintptr_t(1) << 40;
+        std::vector<coot_operand> fake(b->n_slots);
+        for (int s = 0; s < b->n_slots; ++s) {
+            bool t = par[s] == 2;
+            fake[s] = coot_operand{(void*)(G * (s + 1)), t ? cc : cr, t ? cr : cc, t ? cc : cr, b->slot_dtypes[s], 0};
+        }
+        coot_operand fout{(void*)(G * 9), cr, cc, cr, has_out ? b->out_dtype : COOT_F32, 0};
+        coot_expr ey = *b->expr;
+        ey.cfg = coot_config{0, 0, 0, 0};
+        Plan py = make_plan(-1, -1, &ey, fake.data(), b->n_slots, &fout);
+        const int y_prec = py.nodes[py.root].prec;
+        Plan pr;
+        if (has_red) {
+            int ydt = has_out ? b->out_dtype : (y_prec == 64 ? COOT_F64 : COOT_F32);
+            coot_operand fy{(void*)(G * 10), cr, cc, cr, ydt, 0};
+            coot_operand fr{(void*)(G * 11), 1, 1, 1, b->red_dtype, 0};
+            coot_expr er = *b->red_expr;
+            er.cfg = coot_config{0, 0, 0, 0};
+            pr = make_plan(b->red_op, -1, &er, &fy, 1, &fr);
+            for (const Read& r : pr.reads)
+                if (r.trans) fail(COOT_ERR_UNSUPPORTED, "batch: the reduction tree cannot transpose Y");
+        }
+        std::vector<int> read_slot;
+        for (const Read& r : py.reads) read_slot.push_back(r.slot);
+
+        auto* P = new coot_batch_plan();
+        try {
+            P->flags = b->flags;
+            P->has_out = has_out;
+            P->has_red = has_red;
+            P->out_dtype = b->out_dtype;
+            P->red_op = b->red_op;
+            P->red_dtype = b->red_dtype;
+            P->red_out = b->red_out;
+            P->n_slots = b->n_slots;
+            P->y_prec = y_prec;
+            P->nodes.assign(b->expr->nodes, b->expr->nodes + b->expr->n_nodes);
+            if (has_red) P->red_nodes.assign(b->red_expr->nodes, b->red_expr->nodes + b->red_expr->n_nodes);
+            P->slot_dtypes.assign(b->slot_dtypes, b->slot_dtypes + b->n_slots);
+            // tiles and descriptors
+            P->n_items = b->n_items;
+            P->h_items.resize((size_t)b->n_items);
+            std::vector<int> tile_item;
+            int64_t t0 = 0;
+            for (int i = 0; i < b->n_items; ++i) {
+                coot_batch_item_d& d = P->h_items[(size_t)i];
+                std::memset(&d, 0, sizeof d);
+                d.rows = b->shapes[2 * i];
+                d.cols = b->shapes[2 * i + 1];
+                int64_t nt = ((d.rows + 63) / 64) * ((d.cols + 63) / 64);
+                if (nt == 0) nt = 1;  // an empty item still has one (empty) tile so that its r_i is written
+                d.tile0 = t0;
+                d.ntiles = nt;
+                t0 += nt;
+                P->max_item_tiles = std::max(P->max_item_tiles, nt);
+                for (int s = 0; s < b->n_slots; ++s) {
+                    d.leaf[s] = b->leaf_ptrs[(size_t)i * b->n_slots + s];
+                    if (!d.leaf[s] && d.rows * d.cols > 0) fail(COOT_ERR_ARG, "batch: NULL operand pointer");
+                }
+                if (has_out) {
+                    d.out = b->out_ptrs[i];
+                    if (!d.out && d.rows * d.cols > 0) fail(COOT_ERR_ARG, "batch: NULL output pointer");
+                }
+                for (int64_t q = 0; q < nt; ++q) tile_item.push_back(i);
+            }
+            if (t0 > INT32_MAX) fail(COOT_ERR_UNSUPPORTED, "batch: too many tiles");
+            P->n_tiles = t0;
+            // device tables
+            auto up = [](void** dst, const void* src, size_t bytes) {
+                hipchk(hipMalloc(dst, std::max<size_t>(bytes, 16)), "hipMalloc(batch table)");
+                if (bytes) hipchk(hipMemcpy(*dst, src, bytes, hipMemcpyHostToDevice), "hipMemcpy(batch table)");
+            };
+            up((void**)&P->d_items, P->h_items.data(), P->h_items.size() * sizeof(coot_batch_item_d));
+            up((void**)&P->d_tile_item, tile_item.data(), tile_item.size() * sizeof(int));
+            std::vector<int> zeros((size_t)P->max_item_tiles, 0);
+            up((void**)&P->d_zero_tiles, zeros.data(), zeros.size() * sizeof(int));
+            hipchk(hipMalloc((void**)&P->d_part, (size_t)std::max<int64_t>(1, P->n_tiles) * 16), "hipMalloc(batch partials)");
+            hipchk(hipMalloc((void**)&P->d_counters, (size_t)std::max<int64_t>(1, P->n_items) * 4), "hipMalloc(batch counters)");
+            hipchk(hipMemset(P->d_counters, 0, (size_t)std::max<int64_t>(1, P->n_items) * 4), "hipMemset(batch counters)");
+            // kernel
+            std::string name;
+            std::string src = batch_kernel_source(py, has_red ? &pr : nullptr, has_out, b->out_dtype, b->red_dtype,
+                                                  read_slot, &name);
+            P->k = get_kernel(name, src, false);
+            P->grid = std::max<int64_t>(1, std::min<int64_t>(P->n_tiles, (int64_t)g_state.cus * 8));
+            P->args = coot_bargs{P->d_items, P->d_tile_item, P->n_tiles, 0, P->d_part, P->d_counters, b->red_out};
+            // one launch captured in a graph
+            if (!(b->flags & (COOT_BATCH_NO_GRAPH | COOT_BATCH_PER_ITEM | COOT_BATCH_UNFUSED)) && P->n_items > 0) {
+                hipStream_t cap;
+                hipchk(hipStreamCreateWithFlags(&cap, hipStreamNonBlocking), "hipStreamCreate(capture)");
+                hipError_t e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
+                if (e == hipSuccess) {
+                    void* params[] = {&P->args};
+                    e = hipModuleLaunchKernel(P->k.fn, (unsigned)P->grid, 1, 1, 256, 1, 1, 0, cap, params, nullptr);
+                    hipGraph_t g = nullptr;
+                    hipError_t e2 = hipStreamEndCapture(cap, &g);
+                    if (e == hipSuccess) e = e2;
+                    P->graph = g;
+                }
+                if (e == hipSuccess) e = hipGraphInstantiate(&P->exec, P->graph, nullptr, nullptr, 0);
+                (void)hipStreamDestroy(cap);
+                hipchk(e, "graph capture of the batched launch");
+            }
+            (void)stream;
+        } catch (...) {
+            free_plan(P);
+            throw;
+        }
+        {
+            std::lock_guard<std::mutex> lk(g_plans_mu);
+            g_plans.insert(P);
+        }
+        *out_plan = P;
+        return COOT_OK;
+    });
 }
-int coot_batch_run(coot_batch_plan*, void*) { return COOT_ERR_UNSUPPORTED; }
-int coot_batch_destroy(coot_batch_plan*) { return COOT_OK; }
+
+int coot_batch_run(coot_batch_plan* P, void* stream)
+{
+    return guard3([&] {
+        {
+            std::lock_guard<std::mutex> lk(g_plans_mu);
+            if (!P || !g_plans.count(P)) fail(COOT_ERR_ARG, "unknown batch plan");
+        }
+        hipStream_t st = (hipStream_t)stream;
+        if (P->n_items == 0) return COOT_OK;
+        if (P->flags & COOT_BATCH_UNFUSED) {
+            // one kernel per node and item, temporaries in between
+            for (int64_t i = 0; i < P->n_items; ++i) {
+                const coot_batch_item_d& d = P->h_items[(size_t)i];
+                std::vector<coot_operand> ops(P->n_slots);
+                coot_expr e{P->nodes.data(), (int32_t)P->nodes.size(), COOT_EXPR_UNFUSED, {0, 0, 0, 0}};
+                std::vector<int> sp = slot_parities(&e, P->n_slots);
+                for (int s = 0; s < P->n_slots; ++s) {
+                    bool t = sp[s] == 2;
+                    int64_t r = t ? d.cols : d.rows, c = t ? d.rows : d.cols;
+                    ops[s] = coot_operand{(void*)d.leaf[s], r, c, std::max<int64_t>(1, r), P->slot_dtypes[s], 0};
+                }
+                int ydt = P->has_out ? P->out_dtype : (P->y_prec == 64 ? COOT_F64 : COOT_F32);
+                void* ybuf = d.out;
+                if (!P->has_out) hipchk(hipMallocAsync(&ybuf, (size_t)std::max<int64_t>(1, d.rows * d.cols) * itemsize(ydt), st),
+                                        "hipMallocAsync(Y)");
+                coot_operand y{ybuf, d.rows, d.cols, std::max<int64_t>(1, d.rows), ydt, 0};
+                int rc = coot_eval(&e, ops.data(), P->n_slots, &y, stream);
+                if (rc == COOT_OK && P->has_red) {
+                    coot_expr er{P->red_nodes.data(), (int32_t)P->red_nodes.size(), COOT_EXPR_UNFUSED, {0, 0, 0, 0}};
+                    coot_operand ro{(char*)P->red_out + i * itemsize(P->red_dtype), 1, 1, 1, P->red_dtype, 0};
+                    rc = coot_reduce(P->red_op, -1, &er, &y, 1, &ro, stream);
+                }
+                if (!P->has_out) (void)hipFreeAsync(ybuf, st);
+                if (rc) fail(rc, coot_last_error());
+            }
+            return COOT_OK;
+        }
+        if (P->flags & COOT_BATCH_PER_ITEM) {
+            // the same fused kernel, launched once per item
+            for (int64_t i = 0; i < P->n_items; ++i) {
+                const coot_batch_item_d& d = P->h_items[(size_t)i];
+                coot_bargs a = P->args;
+                a.items = P->d_items + i;
+                a.tile_item = P->d_zero_tiles;
+                a.n_tiles = d.ntiles;
+                a.tile_base = d.tile0;
+                a.counters = P->d_counters + i;
+                a.red_out = P->red_out ? (void*)((char*)P->red_out + i * itemsize(P->red_dtype)) : nullptr;
+                launch_b(P->k.fn, d.ntiles, a, st);
+            }
+            return COOT_OK;
+        }
+        if (P->exec) {
+            hipchk(hipGraphLaunch(P->exec, st), "hipGraphLaunch");
+            g_state.launches++;
+        } else {
+            launch_b(P->k.fn, P->grid, P->args, st);
+        }
+        return COOT_OK;
+    });
 }
+
+int coot_batch_destroy(coot_batch_plan* P)
+{
+    return guard3([&] {
+        if (!P) return COOT_OK;
+        std::lock_guard<std::mutex> lk(g_plans_mu);
+        if (!g_plans.count(P)) fail(COOT_ERR_ARG, "unknown batch plan");
+        g_plans.erase(P);
+        free_plan(P);
+        return COOT_OK;
+    });
+}
+
+}  // extern "C"

@@ -66,7 +66,7 @@ static std::string lit(double k, int prec)
 // The element function: arguments are the widened values of the reads.
 // pair = true emits x_pair(...) returning the two children of the root
 // product instead of the product itself (exact TwoProduct in the reduction).
-static std::string emit_eval(const Plan& p, bool pair)
+static std::string emit_eval(const Plan& p, bool pair, const std::string& pfx = "x")
 {
     std::ostringstream s;
     std::ostringstream args;
@@ -76,10 +76,10 @@ static std::string emit_eval(const Plan& p, bool pair)
     }
     const int rp = p.nodes[p.root].prec;
     if (pair)
-        s << "CD void x_pair(" << args.str() << (p.reads.empty() ? "" : ", ") << ctype(rp) << "& pa, " << ctype(rp)
-          << "& pb)\n{\n";
+        s << "CD void " << pfx << "_pair(" << args.str() << (p.reads.empty() ? "" : ", ") << ctype(rp) << "& pa, "
+          << ctype(rp) << "& pb)\n{\n";
     else
-        s << "CD " << ctype(rp) << " x_eval(" << args.str() << ")\n{\n";
+        s << "CD " << ctype(rp) << " " << pfx << "_eval(" << args.str() << ")\n{\n";
     for (size_t i = 0; i < p.nodes.size(); ++i) {
         const PNode& n = p.nodes[i];
         if (pair && (int)i == p.root) continue;
@@ -143,8 +143,19 @@ static std::string acc_type(const Plan& p)
     return std::string("AccI<") + ctype(rp) + (red_is_max(p.red_op) ? ", true>" : ", false>");
 }
 
+static std::string accumulate_into(const Plan& p, const std::string& args, const std::string& gi);
+
 // statement adding the tree's value at linear index `gi` to `acc`
-static std::string accumulate(const Plan& p, const std::string& args, const std::string& gi)
+static std::string accumulate(const Plan& p, const std::string& args, const std::string& gi,
+                              const std::string& acc = "acc")
+{
+    std::string s = accumulate_into(p, args, gi);
+    if (acc == "acc") return s;
+    for (size_t pos; (pos = s.find("acc.")) != std::string::npos;) s.replace(pos, 4, acc + ".");
+    return s;
+}
+
+static std::string accumulate_into(const Plan& p, const std::string& args, const std::string& gi)
 {
     const int rp = p.nodes[p.root].prec;
     const std::string fab = rp == 64 ? "__builtin_fabs" : "__builtin_fabsf";
@@ -244,7 +255,7 @@ static std::string emit_flat(const Plan& p, const LaunchCfg& c, const std::strin
     s << "extern \"C\" __global__ void __launch_bounds__(512) " << name << "(const coot_kargs a)\n{\n";
     s << decl_reads(p, !p.alias_out);
     if (ew) s << "    " << OS << "* " << (p.alias_out ? "" : "__restrict__ ") << "O = (" << OS << "*)a.out;\n";
-    else s << "    " << acc_type(p) << " acc;\n    acc.init();\n";
+    else s << "    " << acc_type(p) << " acc, acc2;\n    acc.init();\n    acc2.init();\n";
     s << "    const i64 nv = a.n / " << VE << ";\n";
     s << "    const i64 bs = blockDim.x;\n";
     s << "    const i64 step = (i64)gridDim.x * bs * " << EPT << ";\n";
@@ -267,9 +278,11 @@ static std::string emit_flat(const Plan& p, const LaunchCfg& c, const std::strin
         s << "                stv<" << OS << ", " << VE << ">(O, v * " << VE << ", o);\n";
     } else {
         s << "#pragma unroll\n                for (int k = 0; k < " << VE << "; ++k) { const i64 gi = v * " << VE
-          << " + k; (void)gi; " << accumulate(p, args, "gi") << " }\n";
+          << " + k; (void)gi; if (e & 1) " << accumulate(p, args, "gi", "acc2") << " else " << accumulate(p, args, "gi")
+          << " }\n";
     }
     s << "            }\n        }\n    }\n";
+    if (!ew) s << "    acc.merge(acc2);\n";
     // tail elements that do not fill a vector
     std::string targs = arglist(p, [](int j) { return "ldnt(L" + std::to_string(j) + " + i)"; });
     s << "    if (blockIdx.x == gridDim.x - 1)\n";
@@ -434,6 +447,133 @@ static std::string emit_row(const Plan& p, const std::string& name)
     s << "    for (i64 r = blockIdx.x; r < a.rows; r += gridDim.x) {\n        "
       << combine_and_write(p, "r", "a.splits", "a.rows", "r") << "\n    }\n}\n";
     return s.str();
+}
+
+// --- batched kernel: one persistent launch over the 64x64 tiles of many items --
+// Every item has its own shape and operand pointers (a descriptor table).  A
+// block takes tiles in grid-stride order; per tile it evaluates the tree (reads
+// transposed through LDS), stores Y, and folds the reduction tree of Y into a
+// compensated partial.  The block that finishes an item's last tile (counted
+// with a per-item atomic) adds that item's tile partials in tile order in FP64,
+// so r_i does not depend on timing.
+std::string batch_kernel_source(const Plan& py, const Plan* pr, bool has_out, int out_dtype, int red_dtype,
+                                const std::vector<int>& read_slot, std::string* name_out)
+{
+    std::ostringstream s;
+    const int rp = py.nodes[py.root].prec;
+    s << "// batch tree: " << py.body_sig << "\n";
+    s << emit_eval(py, false, "x");
+    if (pr) {
+        s << "// reduction tree over Y: " << pr->body_sig << "\n";
+        s << emit_eval(*pr, pr->product_form, "r");
+    }
+    std::vector<bool> in_lds(py.reads.size(), false);
+    int budget = 96 * 1024;
+    for (size_t j = 0; j < py.reads.size(); ++j) {
+        if (!py.reads[j].trans) continue;
+        int bytes = 64 * 65 * (py.reads[j].dtype == COOT_F64 ? 8 : 4);
+        if (bytes <= budget) {
+            in_lds[j] = true;
+            budget -= bytes;
+        }
+    }
+    bool any_lds = false;
+    for (bool b : in_lds) any_lds = any_lds || b;
+    const std::string ACC = pr ? (pr->nodes[pr->root].prec == 64 ? "AccKD" : (pr->pairwise ? "AccPF" : "AccKF")) : "";
+    s << "extern \"C\" __global__ void __launch_bounds__(256) COOT_KERNEL_NAME(const coot_bargs b)\n{\n";
+    for (size_t j = 0; j < py.reads.size(); ++j)
+        if (in_lds[j]) s << "    __shared__ " << ctype(py.reads[j].dtype == COOT_F64 ? 64 : 32) << " T" << j << "[64][65];\n";
+    if (pr) s << "    __shared__ " << ACC << " lds_acc[4];\n";
+    s << "    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;\n";
+    s << "    for (i64 t = blockIdx.x; t < b.n_tiles; t += gridDim.x) {\n";
+    s << "        const int it = b.tile_item[t];\n";
+    s << "        const coot_batch_item_d* I = b.items + it;\n";
+    s << "        const i64 R = I->rows, Cn = I->cols;\n";
+    s << "        const i64 gt = t + b.tile_base;\n";
+    s << "        const i64 tl = gt - I->tile0;\n";
+    s << "        const i64 tr = (R + 63) >> 6;\n";
+    s << "        const i64 i0 = (tl % tr) << 6, j0 = (tl / tr) << 6;\n";
+    for (size_t j = 0; j < py.reads.size(); ++j) {
+        const char* S = stype(py.reads[j].dtype);
+        s << "        const " << S << "* L" << j << " = (const " << S << "*)I->leaf[" << read_slot[j] << "];\n";
+        // a straight read has the item's shape (ld = R); a transposed one is Cn x R (ld = Cn)
+        s << "        const i64 ld" << j << " = " << (py.reads[j].trans ? "Cn" : "R") << ";\n";
+    }
+    if (has_out) s << "        " << stype(out_dtype) << "* O = (" << stype(out_dtype) << "*)I->out;\n";
+    if (pr) s << "        " << ACC << " acc;\n        acc.init();\n";
+    if (any_lds) {
+        s << "        __syncthreads();\n#pragma unroll\n        for (int kk = 0; kk < 16; ++kk) {\n";
+        s << "            const int ii = w + 4 * kk;\n            const i64 ig = i0 + ii, jg = j0 + lane;\n";
+        s << "            if (ig < R && jg < Cn) {\n";
+        for (size_t j = 0; j < py.reads.size(); ++j)
+            if (in_lds[j])
+                s << "                T" << j << "[ii][lane] = "
+                  << widen(py.reads[j].dtype, "ldnt(L" + std::to_string(j) + " + jg + ig * ld" + std::to_string(j) + ")")
+                  << ";\n";
+        s << "            }\n        }\n        __syncthreads();\n";
+    }
+    s << "        const i64 ig = i0 + lane;\n        if (ig < R) {\n#pragma unroll\n";
+    s << "            for (int kk = 0; kk < 16; ++kk) {\n";
+    s << "                const int jj = w + 4 * kk;\n                const i64 jg = j0 + jj;\n";
+    s << "                if (jg < Cn) {\n";
+    std::string args;
+    for (size_t j = 0; j < py.reads.size(); ++j) {
+        if (j) args += ", ";
+        std::string J = std::to_string(j);
+        if (in_lds[j])
+            args += "T" + J + "[lane][jj]";
+        else if (py.reads[j].trans)
+            args += widen(py.reads[j].dtype, "ldnt(L" + J + " + jg + ig * ld" + J + ")");
+        else
+            args += widen(py.reads[j].dtype, "ldnt(L" + J + " + ig + jg * ld" + J + ")");
+    }
+    s << "                    const " << ctype(rp) << " y = x_eval(" << args << ");\n";
+    std::string yv = "y";
+    if (has_out) {
+        s << "                    const " << stype(out_dtype) << " yo = " << narrow(out_dtype, rp, "y") << ";\n";
+        s << "                    stnt(O + ig + jg * R, yo);\n";
+        if (out_dtype == COOT_F16) yv = "widen_f16(yo)";
+        else if (out_dtype == COOT_BF16) yv = "widen_bf16(yo)";
+        else yv = "yo";
+    }
+    if (pr) {
+        const int pp = pr->nodes[pr->root].prec;
+        if (pr->product_form)
+            s << "                    { " << ctype(pp) << " pa, pb; r_pair(" << yv << ", pa, pb); acc.add_prod(pa, pb); }\n";
+        else if (pr->red_op == COOT_RED_NORM2)
+            s << "                    { const " << ctype(pp) << " u = r_eval(" << yv << "); acc.add_prod(u, u); }\n";
+        else if (pr->red_op == COOT_RED_NORM1)
+            s << "                    acc.add(" << (pp == 64 ? "__builtin_fabs" : "__builtin_fabsf") << "(r_eval(" << yv
+              << ")));\n";
+        else
+            s << "                    acc.add(r_eval(" << yv << "));\n";
+    }
+    s << "                }\n            }\n        }\n";
+    if (pr) {
+        s << "        acc = block_reduce(acc, lds_acc);\n";
+        s << "        if (threadIdx.x == 0) {\n";
+        s << "            put_sum_partial((double*)b.part, gt, acc.hi(), acc.lo());\n";
+        s << "            const unsigned done = __hip_atomic_fetch_add(b.counters + it, 1u, __ATOMIC_RELEASE, "
+             "__HIP_MEMORY_SCOPE_AGENT);\n";
+        s << "            if (done == (unsigned)(I->ntiles - 1)) {\n";
+        s << "                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, \"agent\");\n";
+        s << "                AccKD f;\n                f.init();\n";
+        s << "                const double* P = (const double*)b.part + 2 * I->tile0;\n";
+        s << "                for (i64 q = 0; q < I->ntiles; ++q) { f.add(P[2 * q]); f.add(P[2 * q + 1]); }\n";
+        std::string v = pr->red_op == COOT_RED_NORM2 ? "__builtin_sqrt(f.s + f.c)" : "(f.s + f.c)";
+        s << "                " << (red_dtype == COOT_F64 ? "put_f64" : "put_f32") << "(b.red_out, it, " << v << ");\n";
+        s << "                __hip_atomic_store(b.counters + it, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);\n";
+        s << "            }\n        }\n";
+    }
+    s << "    }\n}\n";
+    std::string body = s.str();
+    static const uint64_t prelude_hash = fnv1a(prelude_source());
+    std::string name = "coot_batch_" + hex64(fnv1a(body + (has_out ? "o" : "") + std::to_string(out_dtype) + "|" +
+                                                   std::to_string(red_dtype)) ^ (prelude_hash * 0x9e3779b97f4a7c15ull));
+    const std::string ph = "COOT_KERNEL_NAME";
+    for (size_t pos; (pos = body.find(ph)) != std::string::npos;) body.replace(pos, ph.size(), name);
+    if (name_out) *name_out = name;
+    return body;
 }
 
 std::string kernel_source(const Plan& p, const LaunchCfg& cfg, std::string* name_out, std::string* sig_out)

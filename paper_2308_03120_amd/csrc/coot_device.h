@@ -299,7 +299,9 @@ CD bool arrive_last(unsigned* counter, unsigned total)
     __shared__ unsigned s_last;
     __syncthreads();
     if (threadIdx.x == 0) {
-        unsigned t = __hip_atomic_fetch_add(counter, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+        /* release: this block's partial is visible before the count moves;
+         * only the last block acquires, below */
+        unsigned t = __hip_atomic_fetch_add(counter, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
         s_last = (t == total - 1u) ? 1u : 0u;
     }
     __syncthreads();

@@ -34,9 +34,9 @@ typedef struct coot_batch_item_d {
 
 typedef struct coot_bargs {
     const coot_batch_item_d* items;
-    const int* tile_item;              /* item of every tile */
+    const int* tile_item;              /* item (index into items) of every tile */
     long long n_tiles;
-    long long n_items;
+    long long tile_base;               /* global index of tile 0 of this launch */
     void* part;                        /* per-tile partials */
     unsigned int* counters;            /* per-item tiles-done counters */
     void* red_out;

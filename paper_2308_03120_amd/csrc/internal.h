@@ -79,6 +79,8 @@ struct LaunchCfg {
 // Kernel source for a plan and configuration; `name` receives the entry point.
 std::string kernel_source(const Plan& p, const LaunchCfg& cfg, std::string* name, std::string* sig);
 std::string prelude_source();
+std::string batch_kernel_source(const Plan& py, const Plan* pr, bool has_out, int out_dtype, int red_dtype,
+                                const std::vector<int>& read_slot, std::string* name_out);
 
 // 64-entry configuration space
 LaunchCfg config_of(int index);

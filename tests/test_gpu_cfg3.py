@@ -1,0 +1,99 @@
+"""Precision extension at full size: BF16 and FP16 storage of 16384 x 16384
+matrices with log-normal magnitudes (|x| = exp(3 z), z ~ N(0,1) clipped so
+|x| stays in [1e-4, 1e4]) and random signs.  Column sums, accu and dot
+accumulate in FP32, plain ("pairwise") and compensated ("pairwise+Kahan"),
+each combined across blocks in FP64; every result is compared with the FP64
+oracle.  The compensated variant is gated at 1e-6 relative (per column,
+falling back to 1e-6 of the sum of |terms| where a column cancels); the plain
+variant is reported, not gated.  A JSON report of all errors is written when
+COOT_REPORT_DIR is set."""
+import json
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+
+from gpu_util import TORCH_DT, need_gpu, torch
+
+pytestmark = pytest.mark.gpu
+
+from paper_2308_03120_amd import coot  # noqa: E402
+
+R = C = 16384
+REPORT = {}
+
+
+def to_dev(m):
+    t = torch.from_numpy(np.ascontiguousarray(m.data.T).view(np.int16)).view(TORCH_DT[m.dtype])
+    return t.cuda().t()
+
+
+@pytest.fixture(scope="module", params=["bf16", "f16"])
+def data(request):
+    need_gpu()
+    coot.init(0)
+    dt = request.param
+    d = synth.cfg3_inputs(dt, R, C)
+    A, B = d["A"], d["B"]
+    yield dt, A, B, to_dev(A), to_dev(B)
+    torch.cuda.empty_cache()
+
+
+def _report(key, val):
+    REPORT[key] = val
+    rd = os.environ.get("COOT_REPORT_DIR")
+    if rd:
+        os.makedirs(rd, exist_ok=True)
+        with open(os.path.join(rd, "precision_errors.json"), "w") as f:
+            json.dump(REPORT, f, indent=1, sort_keys=True)
+
+
+@pytest.mark.parametrize("pairwise", [False, True])
+def test_column_sums(data, pairwise):
+    dt, A, B, dA, dB = data
+    got = coot.reduce("sum", synth.leaf(0), [dA], dim=0, pairwise=pairwise).double().cpu().numpy()
+    o, _, asum = oracle.reduce("sum", [synth.Node("leaf", 0)], [A], dim=0)
+    err = np.abs(got - o)
+    relerr = err / np.abs(o)
+    normwise = err / asum
+    _report(f"{dt}_colsum_{'pairwise' if pairwise else 'kahan'}",
+            {"max_rel": float(np.max(relerr)), "median_rel": float(np.median(relerr)),
+             "max_normwise": float(np.max(normwise)), "columns": int(o.size)})
+    if not pairwise:
+        assert np.all((relerr <= 1e-6) | (normwise <= 1e-6)), float(np.max(np.minimum(relerr, normwise)))
+
+
+@pytest.mark.parametrize("pairwise", [False, True])
+def test_accu(data, pairwise):
+    dt, A, B, dA, dB = data
+    got = coot.reduce("accu", synth.leaf(0), [dA], pairwise=pairwise).double().item()
+    o, _, asum = oracle.reduce("accu", [synth.Node("leaf", 0)], [A])
+    rel = abs(got - o[0]) / abs(o[0])
+    _report(f"{dt}_accu_{'pairwise' if pairwise else 'kahan'}",
+            {"rel": rel, "normwise": abs(got - o[0]) / asum[0], "value": got, "oracle": float(o[0])})
+    if not pairwise:
+        assert rel <= 1e-6 or abs(got - o[0]) <= 1e-6 * asum[0], (got, o[0])
+
+
+@pytest.mark.parametrize("pairwise", [False, True])
+def test_dot(data, pairwise):
+    dt, A, B, dA, dB = data
+    t = synth.leaf(0) % synth.leaf(1)
+    got = coot.reduce("dot", t, [dA, dB], pairwise=pairwise).double().item()
+    o, _, asum = oracle.reduce("dot", t.postfix(), [A, B])
+    rel = abs(got - o[0]) / abs(o[0])
+    _report(f"{dt}_dot_{'pairwise' if pairwise else 'kahan'}",
+            {"rel": rel, "normwise": abs(got - o[0]) / asum[0], "value": got, "oracle": float(o[0])})
+    if not pairwise:
+        assert rel <= 1e-6 or abs(got - o[0]) <= 1e-6 * asum[0], (got, o[0])
+
+
+def test_inputs_are_finite_and_in_range(data):
+    dt, A, B, dA, dB = data
+    w = oracle.widen16(dt, A.data.reshape(-1, order="F")[:1 << 22])
+    assert np.all(np.isfinite(w))
+    a = np.abs(w)
+    assert a.min() >= 0.9e-4 and a.max() <= 1.01e4
