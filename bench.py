@@ -102,6 +102,13 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--unfused-steps", type=int, default=5)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--workload", default="scale", choices=["scale", "costmodel", "batched", "precision"],
+                    help="scale (default): the 2^28-element FP32/FP64 calls; costmodel: learned launch "
+                         "configuration over 6,000 random trees; batched: 10,000 matrices in one launch; "
+                         "precision: 16384^2 BF16/FP16 sums and dots")
+    ap.add_argument("--out-dir", default=os.path.join(ROOT, "gpurun_out"),
+                    help="where the cost-model workload writes its corpus table and weights")
+    ap.add_argument("--trees", type=int, default=6000)
     ap.add_argument("--traffic-from", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
                     help="write profiles/traffic.json from two rocprofv3 --pmc counter files and exit")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -123,6 +130,12 @@ def main():
 
     torch.cuda.set_device(0)
     coot.init(0)
+    if args.workload == "costmodel":
+        return costmodel_workload(args, np, torch, synth, coot)
+    if args.workload == "batched":
+        return batched_workload(args, np, torch, synth, coot)
+    if args.workload == "precision":
+        return precision_workload(args, np, torch, synth, coot)
     if args.calibrate_copy:
         src = torch.zeros(1 << 28, dtype=torch.float32, device="cuda")
         dst = torch.empty_like(src)
@@ -244,6 +257,172 @@ def main():
                      "unit": "GB/s", "frac": round(achieved / PEAK_GBS, 4), "traffic": traffic},
         "cpu_baseline": cpu,
     }
+    print(json.dumps(out), flush=True)
+
+
+def costmodel_workload(args, np, torch, synth, coot):
+    """Learned launch configuration: exhaustive autotuning of the random-tree
+    corpus, training of the MLP on the GPU, regret on the held-out trees."""
+    from paper_2308_03120_amd import costmodel as cm
+
+    os.makedirs(args.out_dir, exist_ok=True)
+    trees = synth.cfg5_trees(args.trees)
+    tr_idx, te_idx = synth.cfg5_split(len(trees), int(round(len(trees) * 5 / 6)))
+    t0 = time.perf_counter()
+    n = cm.precompile_corpus(trees, per_module=64, workers=16)
+    t_compile = time.perf_counter() - t0
+    log(f"compiled {n} kernels in {t_compile:.0f} s")
+    t0 = time.perf_counter()
+    times, feats, default = cm.time_corpus(trees, reps=3, log=log)
+    t_tune = time.perf_counter() - t0
+    np.savez_compressed(os.path.join(args.out_dir, "costmodel_corpus.npz"), times=times, feats=feats,
+                        default=default, train=tr_idx, test=te_idx)
+    t0 = time.perf_counter()
+    params, mean, std, hist = cm.train(feats[tr_idx], cm.targets(times[tr_idx]), log=log)
+    t_train = time.perf_counter() - t0
+    cm.save_model(os.path.join(args.out_dir, "costmodel_weights.bin"), params, mean, std)
+    pred = cm.predict(params, mean, std, feats[te_idx])
+    picks = pred.argmin(axis=1)
+    held = cm.summarize(times[te_idx], default[te_idx], picks)
+    fit = cm.summarize(times[tr_idx], default[tr_idx], cm.predict(params, mean, std, feats[tr_idx]).argmin(axis=1))
+    # the model inside the library (GPU inference at plan time) against fused default and unfused
+    coot.model_set(params, mean, std)
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(7)
+    sample = te_idx[:200]
+    t_def = t_mod = t_unf = 0.0
+    agree = 0
+    for i in sample:
+        rt = trees[i]
+        red, dim, ops, out = cm.allocate(rt, torch, gen)
+        agree += int(coot.model_choose(red, dim, rt.expr, ops, out) == picks[list(te_idx).index(i)])
+
+        def run(cfg=None, unfused=False):
+            if red is None:
+                coot.eval(rt.expr, ops, out, cfg=cfg, unfused=unfused)
+            else:
+                coot.reduce(red, rt.expr, ops, out=out, dim=dim, cfg=cfg, unfused=unfused)
+
+        def med(fn, reps=3):
+            fn()
+            ts = []
+            for _ in range(reps):
+                a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                a.record()
+                fn()
+                b.record()
+                torch.cuda.synchronize()
+                ts.append(a.elapsed_time(b))
+            return sorted(ts)[reps // 2]
+
+        coot.set_tuning(coot.TUNE_DEFAULT)
+        t_def += med(lambda: run())
+        coot.set_tuning(coot.TUNE_MODEL)
+        t_mod += med(lambda: run())
+        coot.set_tuning(coot.TUNE_DEFAULT)
+        t_unf += med(lambda: run(unfused=True))
+        del ops, out
+    out = {
+        "metric": "learned launch configuration: regret vs exhaustive autotune on held-out trees",
+        "value": round(held["regret_model_mean"], 5), "unit": "mean regret (t_pick/t_best - 1)",
+        "higher_is_better": False, "n_gpus": 1, "data": "synthetic: 6,000 seeded random expression trees",
+        "config": {"workload": "random trees, depth 1-6, 2^10-2^26 elements, F64/F32/F16/BF16; MLP 32-64-64",
+                   "trees": len(trees), "train": int(len(tr_idx)), "held_out": int(len(te_idx)),
+                   "configs": 64},
+        "held_out": held, "train_fit": fit, "loss_history": hist,
+        "end_to_end_sample": {"trees": int(len(sample)), "model_picks_match_library_inference": agree,
+                              "ms_default": round(t_def, 3), "ms_model": round(t_mod, 3), "ms_unfused": round(t_unf, 3),
+                              "model_speedup_over_default": round(t_def / t_mod, 4),
+                              "model_speedup_over_unfused": round(t_unf / t_mod, 4)},
+        "seconds": {"compile": round(t_compile, 1), "autotune": round(t_tune, 1), "train": round(t_train, 2)},
+    }
+    print(json.dumps(out), flush=True)
+
+
+def batched_workload(args, np, torch, synth, coot):
+    """10,000 matrices: one graph-replayed launch vs per-matrix fused launches vs unfused per-node launches."""
+    d = synth.cfg4_inputs()
+    shapes, offs = d["shapes"], d["offsets"]
+    dA, dB = torch.from_numpy(d["A"]).cuda(), torch.from_numpy(d["Bp"]).cuda()
+    dY = torch.zeros(d["total"], device="cuda")
+    red = torch.zeros(len(shapes), device="cuda")
+    es = 4
+    ptrs = [[dA.data_ptr() + int(o) * es, dB.data_ptr() + int(o) * es] for o in offs]
+    outs = [dY.data_ptr() + int(o) * es for o in offs]
+    yshape = [[int(c), int(r)] for r, c in shapes]
+    elems = int((shapes[:, 0] * shapes[:, 1]).sum())
+    nbytes = 12 * elems
+    Ytree, Rtree = synth.cfg4_tree(), synth.leaf(0) % synth.leaf(0)
+
+    def plan(flags):
+        return coot.BatchPlan(Ytree, [coot.F32, coot.F32], ptrs, yshape, out_ptrs=outs, red_tree=Rtree,
+                              red_op="accu", red_out=red, flags=flags)
+
+    def timed(p, reps):
+        p.run()
+        torch.cuda.synchronize()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        t0 = time.perf_counter()
+        a.record()
+        for _ in range(reps):
+            p.run()
+        b.record()
+        torch.cuda.synchronize()
+        return a.elapsed_time(b) / reps, (time.perf_counter() - t0) / reps * 1e3
+
+    one = plan(0)
+    t_one, w_one = timed(one, max(10, args.steps))
+    nog = plan(coot.BATCH_NO_GRAPH)
+    t_nog, _ = timed(nog, max(10, args.steps))
+    per = plan(coot.BATCH_PER_ITEM)
+    t_per, w_per = timed(per, 3)
+    unf = plan(coot.BATCH_UNFUSED)
+    t_unf, w_unf = timed(unf, 1)
+    out = {
+        "metric": "batched fused evaluation effective GB/s (one graph-replayed launch)",
+        "value": round(nbytes / (t_one * 1e-3) / 1e9, 1), "unit": "GB/s", "n_gpus": 1, "higher_is_better": True,
+        "dtype": "f32", "data": "synthetic: seeded U[-1,1], 10,000 matrices, rows/cols log-uniform in [8, 512]",
+        "config": {"workload": "Y_i = trans(A_i) + 0.5*B_i', r_i = accu(Y_i % Y_i) for 10,000 matrices",
+                   "elements": elems, "algorithmic_bytes": nbytes},
+        "ms_one_launch_graph": round(t_one, 4), "ms_one_launch_direct": round(t_nog, 4),
+        "ms_per_matrix_launches": round(t_per, 3), "ms_unfused_per_node": round(t_unf, 3),
+        "speedup_vs_per_matrix": round(t_per / t_one, 2), "speedup_vs_unfused": round(t_unf / t_one, 2),
+        "frac_of_peak": round(nbytes / (t_one * 1e-3) / 1e9 / PEAK_GBS, 4),
+    }
+    for p in (one, nog, per, unf):
+        p.close()
+    print(json.dumps(out), flush=True)
+
+
+def precision_workload(args, np, torch, synth, coot):
+    """16384 x 16384 BF16/FP16: column sums, accu, dot, plain vs compensated FP32 accumulation."""
+    res = {}
+    for dt, tdt in (("bf16", torch.bfloat16), ("f16", torch.float16)):
+        d = synth.cfg3_inputs(dt)
+        A = torch.from_numpy(np.ascontiguousarray(d["A"].data.T).view(np.int16)).view(tdt).cuda().t()
+        B = torch.from_numpy(np.ascontiguousarray(d["B"].data.T).view(np.int16)).view(tdt).cuda().t()
+        x, y = synth.leaves(2)
+        for name, fn, nb in (("colsum", lambda pw: coot.reduce("sum", x, [A], dim=0, pairwise=pw), 2),
+                             ("accu", lambda pw: coot.reduce("accu", x, [A], pairwise=pw), 2),
+                             ("dot", lambda pw: coot.reduce("dot", x % y, [A, B], pairwise=pw), 4)):
+            for pw in (False, True):
+                fn(pw)
+                torch.cuda.synchronize()
+                a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                a.record()
+                for _ in range(20):
+                    fn(pw)
+                b.record()
+                torch.cuda.synchronize()
+                us = a.elapsed_time(b) / 20 * 1e3
+                res[f"{name}_{dt}_{'pairwise' if pw else 'kahan'}"] = {
+                    "us": round(us, 2), "GBps": round(nb * A.numel() / (us * 1e-6) / 1e9, 1)}
+        del A, B
+    gb = [v["GBps"] for k, v in res.items() if "kahan" in k]
+    out = {"metric": "compensated FP32 reductions of 16-bit storage, effective GB/s", "value": min(gb),
+           "unit": "GB/s (slowest compensated call)", "n_gpus": 1, "higher_is_better": True, "dtype": "bf16,f16",
+           "data": "synthetic: |x| = exp(3z), z~N(0,1) clipped to [1e-4, 1e4], random signs, 16384^2",
+           "per_call": res}
     print(json.dumps(out), flush=True)
 
 

@@ -237,6 +237,14 @@ int64_t coot_kernel_source(int red_op, int dim, const coot_expr* expr, const coo
 int coot_precompile(int red_op, int dim, const coot_expr* expr, const coot_operand* ops,
                     int n_ops, const coot_operand* out);
 
+/* Grouped precompilation: between coot_precompile_begin and
+ * coot_precompile_end, coot_precompile only records the kernels a call needs;
+ * coot_precompile_end compiles them, kernels_per_module to one code object
+ * (much cheaper per kernel than one compilation each), and returns how many
+ * kernels it compiled.  Host only. */
+int coot_precompile_begin(void);
+int coot_precompile_end(int kernels_per_module);
+
 /* ------------------------------------------------------ batched evaluation -- */
 /* Many matrices, one tree (the roadmap's "collections of matrices",
  * Section 6), evaluated by ONE persistent kernel launch.  For item i the tree
@@ -247,10 +255,12 @@ int coot_precompile(int red_op, int dim, const coot_expr* expr, const coot_opera
  * NULL, Y_i is stored there in out_dtype.  If red_expr is not NULL, r_i =
  * red_op of red_expr evaluated on Y_i (red_expr's slot 0 is Y_i itself; only
  * the sum-like red_ops ACCU, SUM(dim -1), DOT, NORM1, NORM2 are allowed) is
- * written to red_out[i] (red_dtype F32 or F64).  The plan copies the tables
- * to the device and, unless COOT_BATCH_NO_GRAPH is set, captures the launch
- * in a hipGraph that coot_batch_run replays.  The caller keeps every pointer
- * valid while the plan lives. */
+ * written to red_out[i] (red_dtype F32 or F64).  Each item is processed by
+ * one block (items are assigned to blocks longest first, on the host), so
+ * r_i is deterministic.  The plan copies the tables to the device and,
+ * unless COOT_BATCH_NO_GRAPH is set, captures the launch in a hipGraph that
+ * coot_batch_run replays.  The caller keeps every pointer valid while the
+ * plan lives. */
 typedef struct coot_batch {
     const coot_expr* expr;
     int32_t n_slots;
@@ -268,8 +278,9 @@ typedef struct coot_batch {
 } coot_batch;
 
 #define COOT_BATCH_NO_GRAPH 1u     /* launch directly instead of through a graph */
-#define COOT_BATCH_PER_ITEM 2u     /* baseline: one fused launch per item */
-#define COOT_BATCH_UNFUSED 4u      /* baseline: one launch per node per item */
+#define COOT_BATCH_PER_ITEM 2u     /* baseline: per item, the fused single-matrix calls
+                                      (coot_eval of the tree, coot_reduce of red_expr) */
+#define COOT_BATCH_UNFUSED 4u      /* baseline: per item, one launch per node (COOT_EXPR_UNFUSED) */
 
 typedef struct coot_batch_plan coot_batch_plan;
 
@@ -293,6 +304,10 @@ int coot_config_of(int index, coot_config* cfg);
  *                      precedence and the default as the fallback. */
 enum { COOT_TUNE_DEFAULT = 0, COOT_TUNE_CACHE = 1, COOT_TUNE_MODEL = 2 };
 int coot_set_tuning(int mode, const char* model_path);
+
+/* Index of the fixed heuristic's configuration for this call.  Host only. */
+int coot_default_config(int red_op, int dim, const coot_expr* expr, const coot_operand* ops,
+                        int n_ops, const coot_operand* out);
 
 /* The 32 features of a call (op mix, depth, element types, shape), as used
  * by the cost model.  Host only. */

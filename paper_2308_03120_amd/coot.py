@@ -100,7 +100,8 @@ EXPORTS = [
     "coot_validate", "coot_kernel_source", "coot_precompile", "coot_batch_create", "coot_batch_run",
     "coot_batch_destroy", "coot_config_of", "coot_set_tuning", "coot_features", "coot_autotune",
     "coot_mlp_forward", "coot_mlp_backward", "coot_mlp_adam", "coot_model_set", "coot_model_choose",
-    "coot_get_stats", "coot_copy",
+    "coot_get_stats", "coot_copy", "coot_precompile_begin", "coot_precompile_end",
+    "coot_default_config",
 ]
 
 
@@ -138,6 +139,8 @@ def lib():
         L.coot_model_choose.argtypes = [i32, i32, P(Expr), P(Operand), i32, P(Operand)]
         L.coot_get_stats.argtypes = [P(Stats)]
         L.coot_copy.argtypes = [vp, vp, i64, vp]
+        L.coot_precompile_end.argtypes = [i32]
+        L.coot_default_config.argtypes = [i32, i32, P(Expr), P(Operand), i32, P(Operand)]
         _lib = L
     return _lib
 
@@ -339,6 +342,14 @@ def precompile(red_op, dim, tree, operands: Sequence, out, cfg=None, pairwise: b
     return _check(lib().coot_precompile(rc, dim, C.byref(e), arr, n, C.byref(o)))
 
 
+def precompile_begin() -> None:
+    _check(lib().coot_precompile_begin())
+
+
+def precompile_end(kernels_per_module: int = 64) -> int:
+    return _check(lib().coot_precompile_end(kernels_per_module))
+
+
 def features(red_op, dim, tree, operands: Sequence, out):
     import numpy as np
 
@@ -364,6 +375,14 @@ def autotune(red_op, dim, tree, operands: Sequence, out, reps: int = 5, stream=N
                                       t.ctypes.data_as(C.POINTER(C.c_float)),
                                       stream if stream is not None else current_stream()))
     return best, t
+
+
+def default_config(red_op, dim, tree, operands: Sequence, out) -> int:
+    e = expr(tree)
+    arr, n = _ops(operands)
+    o = operand(out)
+    rc = -1 if red_op is None else _red_code(red_op, False)
+    return _check(lib().coot_default_config(rc, dim, C.byref(e), arr, n, C.byref(o)))
 
 
 def config_of(index: int):

@@ -188,11 +188,12 @@ struct Geometry {
     int64_t splits;
     int64_t comb_grid;
     size_t part_bytes;
+    int64_t aux;
 };
 
 static Geometry geometry(const Plan& p, const LaunchCfg& c)
 {
-    Geometry G{1, c.block, 1, 0, 0};
+    Geometry G{1, c.block, 1, 0, 0, 0};
     const int64_t cap = grid_cap(c);
     switch (p.kind) {
     case K_EW_FLAT:
@@ -209,18 +210,38 @@ static Geometry geometry(const Plan& p, const LaunchCfg& c)
         G.grid = std::max<int64_t>(1, std::min(nt, c.split >= 8 ? nt : (int64_t)g_state.cus * c.split * 2));
         break;
     }
-    case K_RED_COL:
-        G.grid = std::max<int64_t>(1, std::min(ceil_div(p.cols * 64, c.block), cap));
+    case K_RED_COL: {
+        // enough waves to stream: cut few long columns into row segments
+        const int64_t target = (int64_t)g_state.cus * 16;
+        int64_t S = 1;
+        if (p.cols < target) {
+            S = ceil_div(target, std::max<int64_t>(1, p.cols));
+            S = std::min<int64_t>(S, std::max<int64_t>(1, p.rows / (64 * p.ve * 4)));
+            S = std::min<int64_t>(S, 4096);
+        }
+        int64_t seg = ceil_div(p.rows, S);
+        seg = ceil_div(seg, p.ve) * p.ve;  // segments start on a vector boundary
+        S = std::max<int64_t>(1, ceil_div(p.rows, seg));
+        G.splits = S;
+        G.aux = seg;
+        G.grid = std::max<int64_t>(1, std::min(ceil_div(p.cols * S * 64, c.block), cap));
+        if (S > 1) {
+            G.comb_grid = std::min<int64_t>(p.cols, (int64_t)g_state.cus * 16);
+            G.part_bytes = (size_t)(p.cols * S) * 16;
+        }
         break;
+    }
     case K_RED_COLT:
         G.grid = std::max<int64_t>(1, std::min(ceil_div(p.cols, c.block), cap));
         break;
     case K_RED_ROW: {
+        // work units along the rows: vector groups of ve rows plus the leftover rows
+        const int64_t units = p.rows / p.ve + p.rows % p.ve;
         int64_t target = (int64_t)g_state.cus * 1024;
-        int64_t q = std::max<int64_t>(1, ceil_div(target, std::max<int64_t>(1, p.rows)));
+        int64_t q = std::max<int64_t>(1, ceil_div(target, std::max<int64_t>(1, units)));
         q = std::min<int64_t>(q, std::min<int64_t>(std::max<int64_t>(1, p.cols), 65536));
         G.splits = q;
-        G.grid = std::max<int64_t>(1, std::min(ceil_div(p.rows * q, c.block), cap));
+        G.grid = std::max<int64_t>(1, std::min(ceil_div(units * q, c.block), cap));
         if (q > 1) {
             G.comb_grid = std::min<int64_t>(p.rows, (int64_t)g_state.cus * 16);
             G.part_bytes = (size_t)(p.rows * q) * 16;
@@ -241,13 +262,39 @@ static void fill_reads(const Plan& p, const coot_operand* ops, coot_kargs& a)
 }
 
 // One fused launch (two for split per-row reductions) of a plan.
+// kernels by plan signature: a repeated call skips source generation
+static std::mutex g_sig_mu;
+static std::unordered_map<std::string, Kernel> g_sig_kernels;
+
+static Kernel kernel_for(const Plan& p, const LaunchCfg& c)
+{
+    std::string key = std::to_string(p.kind) + "|" + std::to_string(p.ve) + "|" + std::to_string(c.ept) + "|" +
+                      std::to_string(p.out_dtype) + "|" + std::to_string(p.red_op) + "|" + std::to_string(p.pairwise) +
+                      "|" + std::to_string(p.alias_out) + "|" + p.body_sig;
+    {
+        std::lock_guard<std::mutex> lk(g_sig_mu);
+        auto it = g_sig_kernels.find(key);
+        if (it != g_sig_kernels.end()) return it->second;
+    }
+    std::string name;
+    std::string src = kernel_source(p, c, &name, nullptr);
+    Kernel k = get_kernel(name, src, p.kind == K_RED_ROW || p.kind == K_RED_COL);
+    std::lock_guard<std::mutex> lk(g_sig_mu);
+    g_sig_kernels[key] = k;
+    return k;
+}
+
+void forget_kernels()
+{
+    std::lock_guard<std::mutex> lk(g_sig_mu);
+    g_sig_kernels.clear();
+}
+
 void run_plan(const Plan& p, const LaunchCfg& cfg_in, const coot_operand* ops, const coot_operand* out,
               hipStream_t st)
 {
     LaunchCfg c = normalise_config(p, cfg_in);
-    std::string name;
-    std::string src = kernel_source(p, c, &name, nullptr);
-    Kernel k = get_kernel(name, src, p.kind == K_RED_ROW);
+    Kernel k = kernel_for(p, c);
     Geometry G = geometry(p, c);
     coot_kargs a;
     std::memset(&a, 0, sizeof a);
@@ -256,6 +303,7 @@ void run_plan(const Plan& p, const LaunchCfg& cfg_in, const coot_operand* ops, c
     a.cols = p.cols;
     a.n = p.n;
     a.splits = G.splits;
+    a.aux = G.aux;
     if (p.red_op < 0) {
         a.out = out->ptr;
         a.ld_out = out->ld;
@@ -270,7 +318,7 @@ void run_plan(const Plan& p, const LaunchCfg& cfg_in, const coot_operand* ops, c
     a.counter = s.counters;
     a.res = host ? s.res : out->ptr;
     launch(k.fn, G.grid, G.block, a, st);
-    if (p.kind == K_RED_ROW && G.splits > 1) launch(k.fn2, G.comb_grid, 256, a, st);
+    if ((p.kind == K_RED_ROW || p.kind == K_RED_COL) && G.splits > 1) launch(k.fn2, G.comb_grid, 256, a, st);
     if (host) {
         hipchk(hipMemcpyAsync(out->ptr, s.res, res_bytes / 8 * (size_t)itemsize(out->dtype), hipMemcpyDeviceToHost, st),
                "hipMemcpyAsync");
@@ -424,6 +472,7 @@ int coot_finalize(void)
             g_state.scratch.clear();
         }
         batch_destroy_all();
+        forget_kernels();
         jit_unload_all();
         g_state.init = false;
         return COOT_OK;
@@ -482,16 +531,56 @@ int64_t coot_kernel_source(int red_op, int dim, const coot_expr* expr, const coo
     return rc ? rc : result;
 }
 
+// every fused kernel a call launches (two for a per-dimension reduction of a
+// tree that reads an operand transposed: the tree into a temporary, then the
+// reduction of the temporary)
+static int precompile_call(int red_op, int dim, const coot_expr* expr, const coot_operand* ops, int n_ops,
+                           const coot_operand* out)
+{
+    Plan p = make_plan(red_op, dim, expr, ops, n_ops, out);
+    LaunchCfg c = expr->cfg.ept ? LaunchCfg{expr->cfg.ept, expr->cfg.block, expr->cfg.split} : default_config(p);
+    if (p.temp_needed) {
+        int dt = p.root_prec == 64 ? COOT_F64 : COOT_F32;
+        // a stand-in address far from every operand (only alignment matters here)
+        coot_operand tv{(void*)(uintptr_t(1) << 46), p.rows, p.cols, std::max<int64_t>(1, p.rows), dt, 0};
+        coot_expr e2 = *expr;
+        e2.flags = 0;
+        int n = precompile_call(-1, -1, &e2, ops, n_ops, &tv);
+        coot_node one{COOT_LEAF, 0, -1, 0, 0.0};
+        coot_expr me{&one, 1, 0, expr->cfg};
+        return n + precompile_call(red_op == COOT_RED_DOT ? COOT_RED_ACCU : red_op, dim, &me, &tv, 1, out);
+    }
+    std::string name;
+    std::string src = kernel_source(p, normalise_config(p, c), &name, nullptr);
+    return precompile_kernel(name, src);
+}
+
 int coot_precompile(int red_op, int dim, const coot_expr* expr, const coot_operand* ops, int n_ops,
                     const coot_operand* out)
 {
+    return guard([&] { return precompile_call(red_op, dim, expr, ops, n_ops, out); });
+}
+
+int coot_default_config(int red_op, int dim, const coot_expr* expr, const coot_operand* ops, int n_ops,
+                        const coot_operand* out)
+{
     return guard([&] {
         Plan p = make_plan(red_op, dim, expr, ops, n_ops, out);
-        LaunchCfg c = expr->cfg.ept ? LaunchCfg{expr->cfg.ept, expr->cfg.block, expr->cfg.split} : default_config(p);
-        std::string name;
-        std::string src = kernel_source(p, normalise_config(p, c), &name, nullptr);
-        return precompile_kernel(name, src);
+        return config_index(default_config(p));
     });
+}
+
+int coot_precompile_begin(void)
+{
+    return guard([&] {
+        precompile_begin();
+        return COOT_OK;
+    });
+}
+
+int coot_precompile_end(int kernels_per_module)
+{
+    return guard([&] { return precompile_end(kernels_per_module); });
 }
 
 int coot_get_stats(coot_stats* s)

@@ -8,6 +8,7 @@
 #include <algorithm>
 #include <cstring>
 #include <mutex>
+#include <queue>
 #include <set>
 #include <vector>
 
@@ -20,12 +21,10 @@ using namespace coot;
 struct coot_batch_plan {
     Kernel k{};
     coot_batch_item_d* d_items = nullptr;
-    int* d_tile_item = nullptr;
-    int* d_zero_tiles = nullptr;
-    double* d_part = nullptr;
-    unsigned* d_counters = nullptr;
-    int64_t n_tiles = 0, n_items = 0, max_item_tiles = 1;
-    int64_t grid = 1;
+    int* d_order = nullptr;
+    int* d_blk_first = nullptr;
+    int64_t n_items = 0;
+    int64_t n_blocks = 1;
     coot_bargs args{};
     uint32_t flags = 0;
     hipGraph_t graph = nullptr;
@@ -34,6 +33,7 @@ struct coot_batch_plan {
     std::vector<coot_batch_item_d> h_items;
     std::vector<coot_node> nodes, red_nodes;
     std::vector<int32_t> slot_dtypes;
+    std::vector<int> slot_par;
     int32_t n_slots = 0, out_dtype = COOT_F32, red_op = COOT_RED_ACCU, red_dtype = COOT_F32;
     bool has_out = false, has_red = false;
     void* red_out = nullptr;
@@ -75,11 +75,39 @@ void free_plan(coot_batch_plan* p)
     if (p->exec) (void)hipGraphExecDestroy(p->exec);
     if (p->graph) (void)hipGraphDestroy(p->graph);
     (void)hipFree(p->d_items);
-    (void)hipFree(p->d_tile_item);
-    (void)hipFree(p->d_zero_tiles);
-    (void)hipFree(p->d_part);
-    (void)hipFree(p->d_counters);
+    (void)hipFree(p->d_order);
+    (void)hipFree(p->d_blk_first);
     delete p;
+}
+
+// Longest-processing-time-first assignment of whole items to blocks: the
+// costliest remaining item goes to the least loaded block (ties: lowest block).
+// Cost of an item: its tiles plus a fixed share for the per-item reduction.
+void lpt_schedule(const std::vector<coot_batch_item_d>& items, int64_t n_blocks, std::vector<int>* order,
+                  std::vector<int>* first)
+{
+    const int64_t n = (int64_t)items.size();
+    std::vector<int> idx((size_t)n);
+    for (int64_t i = 0; i < n; ++i) idx[(size_t)i] = (int)i;
+    auto cost = [&](int i) { return (double)items[(size_t)i].ntiles + 0.25; };
+    std::stable_sort(idx.begin(), idx.end(), [&](int a, int b) { return cost(a) > cost(b); });
+    typedef std::pair<double, int64_t> Load;
+    std::priority_queue<Load, std::vector<Load>, std::greater<Load>> heap;
+    for (int64_t b = 0; b < n_blocks; ++b) heap.push(Load(0.0, b));
+    std::vector<std::vector<int>> per((size_t)n_blocks);
+    for (int i : idx) {
+        Load l = heap.top();
+        heap.pop();
+        per[(size_t)l.second].push_back(i);
+        heap.push(Load(l.first + cost(i), l.second));
+    }
+    order->clear();
+    first->assign((size_t)n_blocks + 1, 0);
+    for (int64_t b = 0; b < n_blocks; ++b) {
+        (*first)[(size_t)b] = (int)order->size();
+        order->insert(order->end(), per[(size_t)b].begin(), per[(size_t)b].end());
+    }
+    (*first)[(size_t)n_blocks] = (int)order->size();
 }
 
 // trans parity of every leaf slot (bit 0: read straight, bit 1: read transposed)
@@ -195,53 +223,41 @@ int coot_batch_create(const coot_batch* b, void* stream, coot_batch_plan** out_p
             P->nodes.assign(b->expr->nodes, b->expr->nodes + b->expr->n_nodes);
             if (has_red) P->red_nodes.assign(b->red_expr->nodes, b->red_expr->nodes + b->red_expr->n_nodes);
             P->slot_dtypes.assign(b->slot_dtypes, b->slot_dtypes + b->n_slots);
-            // tiles and descriptors
+            // descriptors and the block schedule
             P->n_items = b->n_items;
+            P->slot_par = par;
             P->h_items.resize((size_t)b->n_items);
-            std::vector<int> tile_item;
-            int64_t t0 = 0;
             for (int i = 0; i < b->n_items; ++i) {
                 coot_batch_item_d& d = P->h_items[(size_t)i];
                 std::memset(&d, 0, sizeof d);
                 d.rows = b->shapes[2 * i];
                 d.cols = b->shapes[2 * i + 1];
-                int64_t nt = ((d.rows + 63) / 64) * ((d.cols + 63) / 64);
-                if (nt == 0) nt = 1;  // an empty item still has one (empty) tile so that its r_i is written
-                d.tile0 = t0;
-                d.ntiles = nt;
-                t0 += nt;
-                P->max_item_tiles = std::max(P->max_item_tiles, nt);
-                for (int s = 0; s < b->n_slots; ++s) {
-                    d.leaf[s] = b->leaf_ptrs[(size_t)i * b->n_slots + s];
-                    if (!d.leaf[s] && d.rows * d.cols > 0) fail(COOT_ERR_ARG, "batch: NULL operand pointer");
+                d.ntiles = ((d.rows + 63) / 64) * ((d.cols + 63) / 64);
+                for (int s2 = 0; s2 < b->n_slots; ++s2) {
+                    d.leaf[s2] = b->leaf_ptrs[(size_t)i * b->n_slots + s2];
+                    if (!d.leaf[s2] && d.rows * d.cols > 0) fail(COOT_ERR_ARG, "batch: NULL operand pointer");
                 }
                 if (has_out) {
                     d.out = b->out_ptrs[i];
                     if (!d.out && d.rows * d.cols > 0) fail(COOT_ERR_ARG, "batch: NULL output pointer");
                 }
-                for (int64_t q = 0; q < nt; ++q) tile_item.push_back(i);
             }
-            if (t0 > INT32_MAX) fail(COOT_ERR_UNSUPPORTED, "batch: too many tiles");
-            P->n_tiles = t0;
-            // device tables
+            P->n_blocks = std::max<int64_t>(1, std::min<int64_t>(b->n_items, (int64_t)g_state.cus * 4));
+            std::vector<int> order, first;
+            lpt_schedule(P->h_items, P->n_blocks, &order, &first);
             auto up = [](void** dst, const void* src, size_t bytes) {
                 hipchk(hipMalloc(dst, std::max<size_t>(bytes, 16)), "hipMalloc(batch table)");
                 if (bytes) hipchk(hipMemcpy(*dst, src, bytes, hipMemcpyHostToDevice), "hipMemcpy(batch table)");
             };
             up((void**)&P->d_items, P->h_items.data(), P->h_items.size() * sizeof(coot_batch_item_d));
-            up((void**)&P->d_tile_item, tile_item.data(), tile_item.size() * sizeof(int));
-            std::vector<int> zeros((size_t)P->max_item_tiles, 0);
-            up((void**)&P->d_zero_tiles, zeros.data(), zeros.size() * sizeof(int));
-            hipchk(hipMalloc((void**)&P->d_part, (size_t)std::max<int64_t>(1, P->n_tiles) * 16), "hipMalloc(batch partials)");
-            hipchk(hipMalloc((void**)&P->d_counters, (size_t)std::max<int64_t>(1, P->n_items) * 4), "hipMalloc(batch counters)");
-            hipchk(hipMemset(P->d_counters, 0, (size_t)std::max<int64_t>(1, P->n_items) * 4), "hipMemset(batch counters)");
+            up((void**)&P->d_order, order.data(), order.size() * sizeof(int));
+            up((void**)&P->d_blk_first, first.data(), first.size() * sizeof(int));
             // kernel
             std::string name;
             std::string src = batch_kernel_source(py, has_red ? &pr : nullptr, has_out, b->out_dtype, b->red_dtype,
                                                   read_slot, &name);
             P->k = get_kernel(name, src, false);
-            P->grid = std::max<int64_t>(1, std::min<int64_t>(P->n_tiles, (int64_t)g_state.cus * 8));
-            P->args = coot_bargs{P->d_items, P->d_tile_item, P->n_tiles, 0, P->d_part, P->d_counters, b->red_out};
+            P->args = coot_bargs{P->d_items, P->d_order, P->d_blk_first, P->n_blocks, b->red_out};
             // one launch captured in a graph
             if (!(b->flags & (COOT_BATCH_NO_GRAPH | COOT_BATCH_PER_ITEM | COOT_BATCH_UNFUSED)) && P->n_items > 0) {
                 hipStream_t cap;
@@ -249,7 +265,7 @@ int coot_batch_create(const coot_batch* b, void* stream, coot_batch_plan** out_p
                 hipError_t e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
                 if (e == hipSuccess) {
                     void* params[] = {&P->args};
-                    e = hipModuleLaunchKernel(P->k.fn, (unsigned)P->grid, 1, 1, 256, 1, 1, 0, cap, params, nullptr);
+                    e = hipModuleLaunchKernel(P->k.fn, (unsigned)P->n_blocks, 1, 1, 256, 1, 1, 0, cap, params, nullptr);
                     hipGraph_t g = nullptr;
                     hipError_t e2 = hipStreamEndCapture(cap, &g);
                     if (e == hipSuccess) e = e2;
@@ -282,26 +298,28 @@ int coot_batch_run(coot_batch_plan* P, void* stream)
         }
         hipStream_t st = (hipStream_t)stream;
         if (P->n_items == 0) return COOT_OK;
-        if (P->flags & COOT_BATCH_UNFUSED) {
-            // one kernel per node and item, temporaries in between
+        if (P->flags & (COOT_BATCH_UNFUSED | COOT_BATCH_PER_ITEM)) {
+            // baselines: per matrix, the fused single-matrix calls (two launches),
+            // or one kernel per node with temporaries
+            const uint32_t ef = (P->flags & COOT_BATCH_UNFUSED) ? COOT_EXPR_UNFUSED : 0u;
             for (int64_t i = 0; i < P->n_items; ++i) {
                 const coot_batch_item_d& d = P->h_items[(size_t)i];
                 std::vector<coot_operand> ops(P->n_slots);
-                coot_expr e{P->nodes.data(), (int32_t)P->nodes.size(), COOT_EXPR_UNFUSED, {0, 0, 0, 0}};
-                std::vector<int> sp = slot_parities(&e, P->n_slots);
+                coot_expr e{P->nodes.data(), (int32_t)P->nodes.size(), ef, {0, 0, 0, 0}};
                 for (int s = 0; s < P->n_slots; ++s) {
-                    bool t = sp[s] == 2;
+                    bool t = P->slot_par[s] == 2;
                     int64_t r = t ? d.cols : d.rows, c = t ? d.rows : d.cols;
                     ops[s] = coot_operand{(void*)d.leaf[s], r, c, std::max<int64_t>(1, r), P->slot_dtypes[s], 0};
                 }
                 int ydt = P->has_out ? P->out_dtype : (P->y_prec == 64 ? COOT_F64 : COOT_F32);
                 void* ybuf = d.out;
-                if (!P->has_out) hipchk(hipMallocAsync(&ybuf, (size_t)std::max<int64_t>(1, d.rows * d.cols) * itemsize(ydt), st),
-                                        "hipMallocAsync(Y)");
+                if (!P->has_out)
+                    hipchk(hipMallocAsync(&ybuf, (size_t)std::max<int64_t>(1, d.rows * d.cols) * itemsize(ydt), st),
+                           "hipMallocAsync(Y)");
                 coot_operand y{ybuf, d.rows, d.cols, std::max<int64_t>(1, d.rows), ydt, 0};
                 int rc = coot_eval(&e, ops.data(), P->n_slots, &y, stream);
                 if (rc == COOT_OK && P->has_red) {
-                    coot_expr er{P->red_nodes.data(), (int32_t)P->red_nodes.size(), COOT_EXPR_UNFUSED, {0, 0, 0, 0}};
+                    coot_expr er{P->red_nodes.data(), (int32_t)P->red_nodes.size(), ef, {0, 0, 0, 0}};
                     coot_operand ro{(char*)P->red_out + i * itemsize(P->red_dtype), 1, 1, 1, P->red_dtype, 0};
                     rc = coot_reduce(P->red_op, -1, &er, &y, 1, &ro, stream);
                 }
@@ -310,26 +328,11 @@ int coot_batch_run(coot_batch_plan* P, void* stream)
             }
             return COOT_OK;
         }
-        if (P->flags & COOT_BATCH_PER_ITEM) {
-            // the same fused kernel, launched once per item
-            for (int64_t i = 0; i < P->n_items; ++i) {
-                const coot_batch_item_d& d = P->h_items[(size_t)i];
-                coot_bargs a = P->args;
-                a.items = P->d_items + i;
-                a.tile_item = P->d_zero_tiles;
-                a.n_tiles = d.ntiles;
-                a.tile_base = d.tile0;
-                a.counters = P->d_counters + i;
-                a.red_out = P->red_out ? (void*)((char*)P->red_out + i * itemsize(P->red_dtype)) : nullptr;
-                launch_b(P->k.fn, d.ntiles, a, st);
-            }
-            return COOT_OK;
-        }
         if (P->exec) {
             hipchk(hipGraphLaunch(P->exec, st), "hipGraphLaunch");
             g_state.launches++;
         } else {
-            launch_b(P->k.fn, P->grid, P->args, st);
+            launch_b(P->k.fn, P->n_blocks, P->args, st);
         }
         return COOT_OK;
     });

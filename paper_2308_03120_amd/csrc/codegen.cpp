@@ -245,6 +245,10 @@ static std::string arglist(const Plan& p, F f)
 }
 
 // --- flat kinds: linear index, VE-element vectors, grid-stride loop ----------
+// Element-wise: EPT vectors per thread per step, loads first, then compute and
+// store.  Reductions: a software pipeline of two register buffers, so the
+// loads of the next step are in flight while the current step is folded into
+// the compensated accumulators (two per thread, alternating by vector).
 static std::string emit_flat(const Plan& p, const LaunchCfg& c, const std::string& name)
 {
     const bool ew = p.kind == K_EW_FLAT;
@@ -259,30 +263,60 @@ static std::string emit_flat(const Plan& p, const LaunchCfg& c, const std::strin
     s << "    const i64 nv = a.n / " << VE << ";\n";
     s << "    const i64 bs = blockDim.x;\n";
     s << "    const i64 step = (i64)gridDim.x * bs * " << EPT << ";\n";
-    s << "    for (i64 base = (i64)blockIdx.x * bs * " << EPT << " + threadIdx.x; base < nv; base += step) {\n";
-    for (size_t j = 0; j < p.reads.size(); ++j)
-        s << "        " << stype(p.reads[j].dtype) << " r" << j << "[" << EPT << "][" << VE << "];\n";
-    s << "#pragma unroll\n        for (int e = 0; e < " << EPT << "; ++e) {\n";
-    s << "            const i64 v = base + e * bs;\n            if (v < nv) {\n";
-    for (size_t j = 0; j < p.reads.size(); ++j)
-        s << "                ldv<" << stype(p.reads[j].dtype) << ", " << VE << ">(L" << j << ", v * " << VE << ", r" << j
-          << "[e]);\n";
-    s << "            }\n        }\n";
-    s << "#pragma unroll\n        for (int e = 0; e < " << EPT << "; ++e) {\n";
-    s << "            const i64 v = base + e * bs;\n            if (v < nv) {\n";
-    std::string args = arglist(p, [](int j) { return "r" + std::to_string(j) + "[e][k]"; });
+    auto load = [&](const std::string& buf, const std::string& b) {
+        std::ostringstream o;
+        o << "#pragma unroll\n        for (int e = 0; e < " << EPT << "; ++e) {\n";
+        o << "            const i64 v = " << b << " + e * bs;\n            if (v < nv) {\n";
+        for (size_t j = 0; j < p.reads.size(); ++j)
+            o << "                ldv<" << stype(p.reads[j].dtype) << ", " << VE << ">(L" << j << ", v * " << VE << ", "
+              << buf << j << "[e]);\n";
+        o << "            }\n        }\n";
+        return o.str();
+    };
+    auto decl = [&](const std::string& buf) {
+        std::ostringstream o;
+        for (size_t j = 0; j < p.reads.size(); ++j)
+            o << "    " << stype(p.reads[j].dtype) << " " << buf << j << "[" << EPT << "][" << VE << "];\n";
+        return o.str();
+    };
     if (ew) {
+        s << "    for (i64 base = (i64)blockIdx.x * bs * " << EPT << " + threadIdx.x; base < nv; base += step) {\n";
+        s << decl("r");
+        s << load("r", "base");
+        s << "#pragma unroll\n        for (int e = 0; e < " << EPT << "; ++e) {\n";
+        s << "            const i64 v = base + e * bs;\n            if (v < nv) {\n";
+        std::string args = arglist(p, [](int j) { return "r" + std::to_string(j) + "[e][k]"; });
         s << "                " << OS << " o[" << VE << "];\n";
         s << "#pragma unroll\n                for (int k = 0; k < " << VE << "; ++k) o[k] = "
           << narrow(p.out_dtype, rp, "x_eval(" + args + ")") << ";\n";
         s << "                stv<" << OS << ", " << VE << ">(O, v * " << VE << ", o);\n";
+        s << "            }\n        }\n    }\n";
     } else {
-        s << "#pragma unroll\n                for (int k = 0; k < " << VE << "; ++k) { const i64 gi = v * " << VE
-          << " + k; (void)gi; if (e & 1) " << accumulate(p, args, "gi", "acc2") << " else " << accumulate(p, args, "gi")
-          << " }\n";
+        auto fold = [&](const std::string& buf, const std::string& b) {
+            std::ostringstream o;
+            std::string args = arglist(p, [&](int j) { return buf + std::to_string(j) + "[e][k]"; });
+            o << "#pragma unroll\n        for (int e = 0; e < " << EPT << "; ++e) {\n";
+            o << "            const i64 v = " << b << " + e * bs;\n            if (v < nv) {\n";
+            o << "#pragma unroll\n                for (int k = 0; k < " << VE << "; ++k) { const i64 gi = v * " << VE
+              << " + k; (void)gi; if (e & 1) " << accumulate(p, args, "gi", "acc2") << " else "
+              << accumulate(p, args, "gi") << " }\n";
+            o << "            }\n        }\n";
+            return o.str();
+        };
+        s << decl("ra") << decl("rb");
+        s << "    i64 base = (i64)blockIdx.x * bs * " << EPT << " + threadIdx.x;\n";
+        s << "    {\n" << load("ra", "base") << "    }\n";
+        s << "    while (base < nv) {\n";
+        s << "        const i64 nb = base + step;\n";
+        s << load("rb", "nb");
+        s << fold("ra", "base");
+        s << "        base = nb;\n        if (base >= nv) break;\n";
+        s << "        const i64 nb2 = base + step;\n";
+        s << load("ra", "nb2");
+        s << fold("rb", "base");
+        s << "        base = nb2;\n    }\n";
+        s << "    acc.merge(acc2);\n";
     }
-    s << "            }\n        }\n    }\n";
-    if (!ew) s << "    acc.merge(acc2);\n";
     // tail elements that do not fill a vector
     std::string targs = arglist(p, [](int j) { return "ldnt(L" + std::to_string(j) + " + i)"; });
     s << "    if (blockIdx.x == gridDim.x - 1)\n";
@@ -301,28 +335,127 @@ static std::string emit_flat(const Plan& p, const LaunchCfg& c, const std::strin
 }
 
 // --- tiled kinds: 64x64 tiles, transposed reads staged through LDS ----------
-static std::string emit_tiled(const Plan& p, const std::string& name)
-{
-    const bool ew = p.kind == K_EW_TILED;
-    const int rp = p.nodes[p.root].prec;
-    std::ostringstream s;
-    // which transposed reads get an LDS tile (budget 96 KiB)
-    std::vector<bool> in_lds(p.reads.size(), false);
-    int budget = 96 * 1024;
+// A 256-thread block works on 64x64 tiles of the value; lane = row inside the
+// tile, wave w takes columns w, w+4, ..., so every straight read and the
+// output move 256-byte column segments.  A transposed read is loaded along
+// its own columns (also 256-byte segments) into a padded 64x65 LDS tile and
+// read back transposed (conflict-free both ways).  The tile loop is software
+// pipelined: the operands of the next tile are loaded into registers while
+// the current tile is computed.
+struct TilePlan {
+    std::vector<bool> in_lds;
     bool any_lds = false;
+};
+
+static TilePlan tile_plan(const Plan& p)
+{
+    TilePlan t;
+    t.in_lds.assign(p.reads.size(), false);
+    int budget = 96 * 1024;
     for (size_t j = 0; j < p.reads.size(); ++j) {
         if (!p.reads[j].trans) continue;
         int bytes = 64 * 65 * (p.reads[j].dtype == COOT_F64 ? 8 : 4);
         if (bytes <= budget) {
-            in_lds[j] = true;
+            t.in_lds[j] = true;
             budget -= bytes;
-            any_lds = true;
+            t.any_lds = true;
         }
     }
+    return t;
+}
+
+static std::string tile_shared_decls(const Plan& p, const TilePlan& tp, const std::string& ind)
+{
+    std::ostringstream s;
+    for (size_t j = 0; j < p.reads.size(); ++j)
+        if (tp.in_lds[j]) s << ind << "__shared__ " << ctype(p.reads[j].dtype == COOT_F64 ? 64 : 32) << " T" << j << "[64][65];\n";
+    return s.str();
+}
+
+// Tile loop over tiles t = first, next(t), ... (next gives -1 at the end).
+// Needs R, Cn, tr, lane, w, L<j>, ld<j> in scope; per_elem(args) is the
+// statement run for every element (ig, jg) of the tile inside the matrix.
+template <class F>
+static std::string tile_loop(const Plan& p, const TilePlan& tp, const std::string& ind, const std::string& first,
+                             const std::string& next_tt, F per_elem)
+{
+    std::ostringstream s;
+    const size_t nr = p.reads.size();
+    auto C = [&](size_t j) { return ctype(p.reads[j].dtype == COOT_F64 ? 64 : 32); };
+    for (size_t j = 0; j < nr; ++j) {
+        if (tp.in_lds[j]) s << ind << C(j) << " pt" << j << "[16];\n";
+        else s << ind << C(j) << " pr" << j << "[16], cr" << j << "[16];\n";
+    }
+    auto prefetch = [&](const std::string& tt, const std::string& in) {
+        std::ostringstream o;
+        o << in << "{\n" << in << "    const i64 pi0 = ((" << tt << ") % tr) << 6, pj0 = ((" << tt << ") / tr) << 6;\n";
+        o << in << "#pragma unroll\n" << in << "    for (int kk = 0; kk < 16; ++kk) {\n";
+        for (size_t j = 0; j < nr; ++j) {
+            std::string J = std::to_string(j);
+            if (tp.in_lds[j]) {
+                o << in << "        { const i64 ig = pi0 + w + 4 * kk, jg = pj0 + lane; pt" << J
+                  << "[kk] = (ig < R && jg < Cn) ? " << widen(p.reads[j].dtype, "ldnt(L" + J + " + jg + ig * ld" + J + ")")
+                  << " : (" << C(j) << ")0; }\n";
+            } else if (p.reads[j].trans) {
+                o << in << "        { const i64 ig = pi0 + lane, jg = pj0 + w + 4 * kk; pr" << J
+                  << "[kk] = (ig < R && jg < Cn) ? " << widen(p.reads[j].dtype, "ldnt(L" + J + " + jg + ig * ld" + J + ")")
+                  << " : (" << C(j) << ")0; }\n";
+            } else {
+                o << in << "        { const i64 ig = pi0 + lane, jg = pj0 + w + 4 * kk; pr" << J
+                  << "[kk] = (ig < R && jg < Cn) ? " << widen(p.reads[j].dtype, "ldnt(L" + J + " + ig + jg * ld" + J + ")")
+                  << " : (" << C(j) << ")0; }\n";
+            }
+        }
+        o << in << "    }\n" << in << "}\n";
+        return o.str();
+    };
+    auto subst = [](std::string e, const std::string& tt) {
+        for (size_t pos; (pos = e.find("@")) != std::string::npos;) e.replace(pos, 1, tt);
+        return e;
+    };
+    s << ind << "i64 t = " << first << ";\n";
+    s << ind << "if (t >= 0)\n" << prefetch("t", ind + "    ");
+    s << ind << "while (t >= 0) {\n";
+    const std::string in = ind + "    ";
+    s << in << "const i64 i0 = (t % tr) << 6, j0 = (t / tr) << 6;\n";
+    s << in << "const i64 tn = " << subst(next_tt, "t") << ";\n";
+    if (tp.any_lds) {
+        s << in << "__syncthreads();\n";
+        s << in << "#pragma unroll\n" << in << "for (int kk = 0; kk < 16; ++kk) {\n";
+        for (size_t j = 0; j < nr; ++j)
+            if (tp.in_lds[j]) s << in << "    T" << j << "[w + 4 * kk][lane] = pt" << j << "[kk];\n";
+        s << in << "}\n";
+    }
+    for (size_t j = 0; j < nr; ++j)
+        if (!tp.in_lds[j])
+            s << in << "#pragma unroll\n" << in << "for (int kk = 0; kk < 16; ++kk) cr" << j << "[kk] = pr" << j << "[kk];\n";
+    if (tp.any_lds) s << in << "__syncthreads();\n";
+    s << in << "if (tn >= 0)\n" << prefetch("tn", in + "    ");
+    s << in << "const i64 ig = i0 + lane;\n";
+    s << in << "if (ig < R) {\n" << in << "#pragma unroll\n" << in << "    for (int kk = 0; kk < 16; ++kk) {\n";
+    s << in << "        const int jj = w + 4 * kk;\n" << in << "        const i64 jg = j0 + jj;\n";
+    s << in << "        if (jg < Cn) {\n";
+    std::string args;
+    for (size_t j = 0; j < nr; ++j) {
+        if (j) args += ", ";
+        args += tp.in_lds[j] ? "T" + std::to_string(j) + "[lane][jj]" : "cr" + std::to_string(j) + "[kk]";
+    }
+    s << per_elem(args, in + "            ");
+    s << in << "        }\n" << in << "    }\n" << in << "}\n";
+    s << in << "t = tn;\n";
+    s << ind << "}\n";
+    return s.str();
+}
+
+static std::string emit_tiled(const Plan& p, const std::string& name)
+{
+    const bool ew = p.kind == K_EW_TILED;
+    const int rp = p.nodes[p.root].prec;
+    const TilePlan tp = tile_plan(p);
+    std::ostringstream s;
     s << "extern \"C\" __global__ void __launch_bounds__(256) " << name << "(const coot_kargs a)\n{\n";
     s << decl_reads(p, !p.alias_out);
-    for (size_t j = 0; j < p.reads.size(); ++j)
-        if (in_lds[j]) s << "    __shared__ " << ctype(p.reads[j].dtype == COOT_F64 ? 64 : 32) << " T" << j << "[64][65];\n";
+    s << tile_shared_decls(p, tp, "    ");
     if (ew) {
         const char* OS = stype(p.out_dtype);
         s << "    " << OS << "* " << (p.alias_out ? "" : "__restrict__ ") << "O = (" << OS << "*)a.out;\n";
@@ -333,37 +466,13 @@ static std::string emit_tiled(const Plan& p, const std::string& name)
     s << "    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;\n";
     s << "    const i64 R = a.rows, Cn = a.cols;\n";
     s << "    const i64 tr = (R + 63) >> 6, tc = (Cn + 63) >> 6, nt = tr * tc;\n";
-    s << "    for (i64 t = blockIdx.x; t < nt; t += gridDim.x) {\n";
-    s << "        const i64 i0 = (t % tr) << 6, j0 = (t / tr) << 6;\n";
-    if (any_lds) {
-        s << "        __syncthreads();\n#pragma unroll\n        for (int kk = 0; kk < 16; ++kk) {\n";
-        s << "            const int ii = w + 4 * kk;\n            const i64 ig = i0 + ii, jg = j0 + lane;\n";
-        s << "            if (ig < R && jg < Cn) {\n";
-        for (size_t j = 0; j < p.reads.size(); ++j)
-            if (in_lds[j])
-                s << "                T" << j << "[ii][lane] = " << widen(p.reads[j].dtype, "ldnt(L" + std::to_string(j) + " + jg + ig * ld" + std::to_string(j) + ")") << ";\n";
-        s << "            }\n        }\n        __syncthreads();\n";
-    }
-    s << "        const i64 ig = i0 + lane;\n        if (ig < R) {\n#pragma unroll\n";
-    s << "            for (int kk = 0; kk < 16; ++kk) {\n";
-    s << "                const int jj = w + 4 * kk;\n                const i64 jg = j0 + jj;\n";
-    s << "                if (jg < Cn) {\n";
-    std::string args;
-    for (size_t j = 0; j < p.reads.size(); ++j) {
-        if (j) args += ", ";
-        std::string J = std::to_string(j);
-        if (in_lds[j])
-            args += "T" + J + "[lane][jj]";
-        else if (p.reads[j].trans)
-            args += widen(p.reads[j].dtype, "ldnt(L" + J + " + jg + ig * ld" + J + ")");
-        else
-            args += widen(p.reads[j].dtype, "ldnt(L" + J + " + ig + jg * ld" + J + ")");
-    }
-    if (ew)
-        s << "                    stnt(O + ig + jg * ldo, (" << stype(p.out_dtype) << ")(" << narrow(p.out_dtype, rp, "x_eval(" + args + ")") << "));\n";
-    else
-        s << "                    " << accumulate(p, args, "(ig + jg * R)") << "\n";
-    s << "                }\n            }\n        }\n    }\n";
+    s << tile_loop(p, tp, "    ", "((i64)blockIdx.x < nt ? (i64)blockIdx.x : -1)",
+                   "(@ + (i64)gridDim.x < nt ? @ + (i64)gridDim.x : -1)", [&](const std::string& args, const std::string& in) {
+                       if (ew)
+                           return in + "stnt(O + ig + jg * ldo, (" + std::string(stype(p.out_dtype)) + ")(" +
+                                  narrow(p.out_dtype, rp, "x_eval(" + args + ")") + "));\n";
+                       return in + accumulate(p, args, "(ig + jg * R)") + "\n";
+                   });
     if (!ew) {
         s << "    __shared__ " << acc_type(p) << " lds_acc[4];\n";
         s << "    acc = block_reduce(acc, lds_acc);\n";
@@ -375,7 +484,10 @@ static std::string emit_tiled(const Plan& p, const std::string& name)
     return s.str();
 }
 
-// --- per-column reductions (dim 0): one wave per column ----------------------
+// --- per-column reductions (dim 0): one wave per (column, row segment) -------
+// With few columns each column is cut into a.splits segments of a.aux rows so
+// that enough waves stream; segment partials are combined per column, in
+// segment order, by the second entry point.
 static std::string emit_col(const Plan& p, const LaunchCfg& c, const std::string& name)
 {
     const int VE = p.ve, EPT = c.ept;
@@ -385,11 +497,15 @@ static std::string emit_col(const Plan& p, const LaunchCfg& c, const std::string
     s << "    const int lane = threadIdx.x & 63;\n";
     s << "    const i64 wv = ((i64)blockIdx.x * blockDim.x + threadIdx.x) >> 6;\n";
     s << "    const i64 nw = ((i64)gridDim.x * blockDim.x) >> 6;\n";
-    s << "    const i64 nvr = a.rows / " << VE << ";\n";
-    s << "    for (i64 j = wv; j < a.cols; j += nw) {\n";
+    s << "    const i64 total = a.cols * a.splits;\n";
+    s << "    for (i64 u = wv; u < total; u += nw) {\n";
+    s << "        const i64 j = u % a.cols, sg = u / a.cols;\n";
+    s << "        const i64 rs0 = sg * a.aux;\n";
+    s << "        const i64 rs1 = rs0 + a.aux < a.rows ? rs0 + a.aux : a.rows;\n";
+    s << "        const i64 nvr = (rs1 - rs0) / " << VE << ";\n";
     s << "        " << acc_type(p) << " acc;\n        acc.init();\n";
     for (size_t j = 0; j < p.reads.size(); ++j)
-        s << "        const " << stype(p.reads[j].dtype) << "* C" << j << " = L" << j << " + j * ld" << j << ";\n";
+        s << "        const " << stype(p.reads[j].dtype) << "* C" << j << " = L" << j << " + j * ld" << j << " + rs0;\n";
     s << "        for (i64 base = lane; base < nvr; base += 64 * " << EPT << ") {\n";
     for (size_t j = 0; j < p.reads.size(); ++j)
         s << "            " << stype(p.reads[j].dtype) << " r" << j << "[" << EPT << "][" << VE << "];\n";
@@ -402,14 +518,19 @@ static std::string emit_col(const Plan& p, const LaunchCfg& c, const std::string
     s << "#pragma unroll\n            for (int e = 0; e < " << EPT << "; ++e) {\n";
     s << "                const i64 v = base + e * 64;\n                if (v < nvr) {\n";
     std::string args = arglist(p, [](int j) { return "r" + std::to_string(j) + "[e][k]"; });
-    s << "#pragma unroll\n                    for (int k = 0; k < " << VE << "; ++k) { const i64 gi = v * " << VE
+    s << "#pragma unroll\n                    for (int k = 0; k < " << VE << "; ++k) { const i64 gi = rs0 + v * " << VE
       << " + k; (void)gi; " << accumulate(p, args, "gi") << " }\n";
     s << "                }\n            }\n        }\n";
     std::string targs = arglist(p, [](int j) { return "ldnt(C" + std::to_string(j) + " + r)"; });
-    s << "        for (i64 r = nvr * " << VE << " + lane; r < a.rows; r += 64) { " << accumulate(p, targs, "r") << " }\n";
+    s << "        for (i64 r = nvr * " << VE << " + lane; r < rs1 - rs0; r += 64) { " << accumulate(p, targs, "(rs0 + r)")
+      << " }\n";
     s << "        wave_reduce(acc);\n";
-    s << "        if (lane == 0) { " << write_direct(p, "j") << " }\n";
+    s << "        if (lane == 0) { if (a.splits == 1) { " << write_direct(p, "j") << " } else { "
+      << put_partial(p, "sg * a.cols + j") << " } }\n";
     s << "    }\n}\n";
+    s << "extern \"C\" __global__ void __launch_bounds__(256) " << name << "_comb(const coot_kargs a)\n{\n";
+    s << "    for (i64 j = blockIdx.x; j < a.cols; j += gridDim.x) {\n        "
+      << combine_and_write(p, "j", "a.splits", "a.cols", "j") << "\n    }\n}\n";
     return s.str();
 }
 
@@ -427,15 +548,44 @@ static std::string emit_colt(const Plan& p, const std::string& name)
     return s.str();
 }
 
-// --- per-row reductions (dim 1): thread per (row, column subset) -------------
+// --- per-row reductions (dim 1): thread per (VE rows, column subset) ---------
+// Work unit g < RV is a group of VE consecutive rows read with one vector load
+// per column; the rows % VE left over are scalar units.  With splits > 1 each
+// unit folds the columns q, q+splits, ... and a second kernel combines the
+// splits of every row in order.
 static std::string emit_row(const Plan& p, const std::string& name)
 {
+    const int VE = p.ve;
     std::ostringstream s;
     s << "extern \"C\" __global__ void __launch_bounds__(512) " << name << "(const coot_kargs a)\n{\n";
     s << decl_reads(p, true);
-    s << "    const i64 total = a.rows * a.splits;\n";
+    s << "    const i64 RV = a.rows / " << VE << ";\n";
+    s << "    const i64 groups = RV + (a.rows - RV * " << VE << ");\n";
+    s << "    const i64 total = groups * a.splits;\n";
     s << "    for (i64 w = (i64)blockIdx.x * blockDim.x + threadIdx.x; w < total; w += (i64)gridDim.x * blockDim.x) {\n";
-    s << "        const i64 r = w % a.rows, q = w / a.rows;\n";
+    s << "        const i64 g = w % groups, q = w / groups;\n";
+    if (VE > 1) {
+        s << "        if (g < RV) {\n";
+        s << "            " << acc_type(p) << " av[" << VE << "];\n";
+        s << "#pragma unroll\n            for (int k = 0; k < " << VE << "; ++k) av[k].init();\n";
+        s << "            for (i64 c = q; c < a.cols; c += a.splits) {\n";
+        for (size_t j = 0; j < p.reads.size(); ++j)
+            s << "                " << stype(p.reads[j].dtype) << " r" << j << "[" << VE << "];\n                ldv<"
+              << stype(p.reads[j].dtype) << ", " << VE << ">(L" << j << ", g * " << VE << " + c * ld" << j << ", r" << j
+              << ");\n";
+        std::string args = arglist(p, [](int j) { return "r" + std::to_string(j) + "[k]"; });
+        s << "#pragma unroll\n                for (int k = 0; k < " << VE << "; ++k) { " << accumulate(p, args, "c", "av[k]")
+          << " }\n";
+        s << "            }\n";
+        s << "#pragma unroll\n            for (int k = 0; k < " << VE << "; ++k) {\n";
+        s << "                const i64 r = g * " << VE << " + k;\n";
+        std::string wd = write_direct(p, "r"), pp = put_partial(p, "q * a.rows + r");
+        for (auto* str : {&wd, &pp})
+            for (size_t pos; (pos = str->find("acc.")) != std::string::npos;) str->replace(pos, 4, "av[k].");
+        s << "                if (a.splits == 1) { " << wd << " } else { " << pp << " }\n";
+        s << "            }\n            continue;\n        }\n";
+    }
+    s << "        const i64 r = RV * " << VE << " + (g - RV);\n";
     s << "        " << acc_type(p) << " acc;\n        acc.init();\n";
     std::string args = arglist(p, [](int j) { return "ldnt(L" + std::to_string(j) + " + r + c * ld" + std::to_string(j) + ")"; });
     s << "#pragma unroll 4\n        for (i64 c = q; c < a.cols; c += a.splits) { " << accumulate(p, args, "c") << " }\n";
@@ -449,13 +599,14 @@ static std::string emit_row(const Plan& p, const std::string& name)
     return s.str();
 }
 
-// --- batched kernel: one persistent launch over the 64x64 tiles of many items --
-// Every item has its own shape and operand pointers (a descriptor table).  A
-// block takes tiles in grid-stride order; per tile it evaluates the tree (reads
-// transposed through LDS), stores Y, and folds the reduction tree of Y into a
-// compensated partial.  The block that finishes an item's last tile (counted
-// with a per-item atomic) adds that item's tile partials in tile order in FP64,
-// so r_i does not depend on timing.
+// --- batched kernel: one persistent launch over many items ---------------------
+// Every block owns a list of whole items (a longest-first schedule computed on
+// the host, so the blocks finish together).  Per item, the block walks the
+// 64x64 tiles of Y in order, evaluates the tree (reads transposed through
+// LDS), stores Y and folds the reduction tree of Y into compensated
+// accumulators; one block reduction per item gives r_i.  No item is shared
+// between blocks, so there is no cross-block traffic and r_i does not depend
+// on timing.
 std::string batch_kernel_source(const Plan& py, const Plan* pr, bool has_out, int out_dtype, int red_dtype,
                                 const std::vector<int>& read_slot, std::string* name_out)
 {
@@ -467,32 +618,18 @@ std::string batch_kernel_source(const Plan& py, const Plan* pr, bool has_out, in
         s << "// reduction tree over Y: " << pr->body_sig << "\n";
         s << emit_eval(*pr, pr->product_form, "r");
     }
-    std::vector<bool> in_lds(py.reads.size(), false);
-    int budget = 96 * 1024;
-    for (size_t j = 0; j < py.reads.size(); ++j) {
-        if (!py.reads[j].trans) continue;
-        int bytes = 64 * 65 * (py.reads[j].dtype == COOT_F64 ? 8 : 4);
-        if (bytes <= budget) {
-            in_lds[j] = true;
-            budget -= bytes;
-        }
-    }
-    bool any_lds = false;
-    for (bool b : in_lds) any_lds = any_lds || b;
+    const TilePlan tp = tile_plan(py);
     const std::string ACC = pr ? (pr->nodes[pr->root].prec == 64 ? "AccKD" : (pr->pairwise ? "AccPF" : "AccKF")) : "";
     s << "extern \"C\" __global__ void __launch_bounds__(256) COOT_KERNEL_NAME(const coot_bargs b)\n{\n";
-    for (size_t j = 0; j < py.reads.size(); ++j)
-        if (in_lds[j]) s << "    __shared__ " << ctype(py.reads[j].dtype == COOT_F64 ? 64 : 32) << " T" << j << "[64][65];\n";
+    s << tile_shared_decls(py, tp, "    ");
     if (pr) s << "    __shared__ " << ACC << " lds_acc[4];\n";
     s << "    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;\n";
-    s << "    for (i64 t = blockIdx.x; t < b.n_tiles; t += gridDim.x) {\n";
-    s << "        const int it = b.tile_item[t];\n";
+    s << "    const int s_end = b.blk_first[blockIdx.x + 1];\n";
+    s << "    for (int si = b.blk_first[blockIdx.x]; si < s_end; ++si) {\n";
+    s << "        const int it = b.order[si];\n";
     s << "        const coot_batch_item_d* I = b.items + it;\n";
-    s << "        const i64 R = I->rows, Cn = I->cols;\n";
-    s << "        const i64 gt = t + b.tile_base;\n";
-    s << "        const i64 tl = gt - I->tile0;\n";
+    s << "        const i64 R = I->rows, Cn = I->cols, ntl = I->ntiles;\n";
     s << "        const i64 tr = (R + 63) >> 6;\n";
-    s << "        const i64 i0 = (tl % tr) << 6, j0 = (tl / tr) << 6;\n";
     for (size_t j = 0; j < py.reads.size(); ++j) {
         const char* S = stype(py.reads[j].dtype);
         s << "        const " << S << "* L" << j << " = (const " << S << "*)I->leaf[" << read_slot[j] << "];\n";
@@ -501,69 +638,37 @@ std::string batch_kernel_source(const Plan& py, const Plan* pr, bool has_out, in
     }
     if (has_out) s << "        " << stype(out_dtype) << "* O = (" << stype(out_dtype) << "*)I->out;\n";
     if (pr) s << "        " << ACC << " acc;\n        acc.init();\n";
-    if (any_lds) {
-        s << "        __syncthreads();\n#pragma unroll\n        for (int kk = 0; kk < 16; ++kk) {\n";
-        s << "            const int ii = w + 4 * kk;\n            const i64 ig = i0 + ii, jg = j0 + lane;\n";
-        s << "            if (ig < R && jg < Cn) {\n";
-        for (size_t j = 0; j < py.reads.size(); ++j)
-            if (in_lds[j])
-                s << "                T" << j << "[ii][lane] = "
-                  << widen(py.reads[j].dtype, "ldnt(L" + std::to_string(j) + " + jg + ig * ld" + std::to_string(j) + ")")
-                  << ";\n";
-        s << "            }\n        }\n        __syncthreads();\n";
-    }
-    s << "        const i64 ig = i0 + lane;\n        if (ig < R) {\n#pragma unroll\n";
-    s << "            for (int kk = 0; kk < 16; ++kk) {\n";
-    s << "                const int jj = w + 4 * kk;\n                const i64 jg = j0 + jj;\n";
-    s << "                if (jg < Cn) {\n";
-    std::string args;
-    for (size_t j = 0; j < py.reads.size(); ++j) {
-        if (j) args += ", ";
-        std::string J = std::to_string(j);
-        if (in_lds[j])
-            args += "T" + J + "[lane][jj]";
-        else if (py.reads[j].trans)
-            args += widen(py.reads[j].dtype, "ldnt(L" + J + " + jg + ig * ld" + J + ")");
-        else
-            args += widen(py.reads[j].dtype, "ldnt(L" + J + " + ig + jg * ld" + J + ")");
-    }
-    s << "                    const " << ctype(rp) << " y = x_eval(" << args << ");\n";
-    std::string yv = "y";
-    if (has_out) {
-        s << "                    const " << stype(out_dtype) << " yo = " << narrow(out_dtype, rp, "y") << ";\n";
-        s << "                    stnt(O + ig + jg * R, yo);\n";
-        if (out_dtype == COOT_F16) yv = "widen_f16(yo)";
-        else if (out_dtype == COOT_BF16) yv = "widen_bf16(yo)";
-        else yv = "yo";
-    }
-    if (pr) {
-        const int pp = pr->nodes[pr->root].prec;
-        if (pr->product_form)
-            s << "                    { " << ctype(pp) << " pa, pb; r_pair(" << yv << ", pa, pb); acc.add_prod(pa, pb); }\n";
-        else if (pr->red_op == COOT_RED_NORM2)
-            s << "                    { const " << ctype(pp) << " u = r_eval(" << yv << "); acc.add_prod(u, u); }\n";
-        else if (pr->red_op == COOT_RED_NORM1)
-            s << "                    acc.add(" << (pp == 64 ? "__builtin_fabs" : "__builtin_fabsf") << "(r_eval(" << yv
-              << ")));\n";
-        else
-            s << "                    acc.add(r_eval(" << yv << "));\n";
-    }
-    s << "                }\n            }\n        }\n";
+    s << tile_loop(py, tp, "        ", "(ntl > 0 ? (i64)0 : (i64)-1)", "(@ + 1 < ntl ? @ + 1 : -1)",
+                   [&](const std::string& args, const std::string& in) {
+                       std::ostringstream o;
+                       o << in << "const " << ctype(rp) << " y = x_eval(" << args << ");\n";
+                       std::string yv = "y";
+                       if (has_out) {
+                           o << in << "const " << stype(out_dtype) << " yo = " << narrow(out_dtype, rp, "y") << ";\n";
+                           o << in << "stnt(O + ig + jg * R, yo);\n";
+                           if (out_dtype == COOT_F16) yv = "widen_f16(yo)";
+                           else if (out_dtype == COOT_BF16) yv = "widen_bf16(yo)";
+                           else yv = "yo";
+                       }
+                       if (pr) {
+                           const int pp = pr->nodes[pr->root].prec;
+                           if (pr->product_form)
+                               o << in << "{ " << ctype(pp) << " pa, pb; r_pair(" << yv << ", pa, pb); acc.add_prod(pa, pb); }\n";
+                           else if (pr->red_op == COOT_RED_NORM2)
+                               o << in << "{ const " << ctype(pp) << " u = r_eval(" << yv << "); acc.add_prod(u, u); }\n";
+                           else if (pr->red_op == COOT_RED_NORM1)
+                               o << in << "acc.add(" << (pp == 64 ? "__builtin_fabs" : "__builtin_fabsf") << "(r_eval(" << yv
+                                 << ")));\n";
+                           else
+                               o << in << "acc.add(r_eval(" << yv << "));\n";
+                       }
+                       return o.str();
+                   });
     if (pr) {
         s << "        acc = block_reduce(acc, lds_acc);\n";
-        s << "        if (threadIdx.x == 0) {\n";
-        s << "            put_sum_partial((double*)b.part, gt, acc.hi(), acc.lo());\n";
-        s << "            const unsigned done = __hip_atomic_fetch_add(b.counters + it, 1u, __ATOMIC_RELEASE, "
-             "__HIP_MEMORY_SCOPE_AGENT);\n";
-        s << "            if (done == (unsigned)(I->ntiles - 1)) {\n";
-        s << "                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, \"agent\");\n";
-        s << "                AccKD f;\n                f.init();\n";
-        s << "                const double* P = (const double*)b.part + 2 * I->tile0;\n";
-        s << "                for (i64 q = 0; q < I->ntiles; ++q) { f.add(P[2 * q]); f.add(P[2 * q + 1]); }\n";
-        std::string v = pr->red_op == COOT_RED_NORM2 ? "__builtin_sqrt(f.s + f.c)" : "(f.s + f.c)";
-        s << "                " << (red_dtype == COOT_F64 ? "put_f64" : "put_f32") << "(b.red_out, it, " << v << ");\n";
-        s << "                __hip_atomic_store(b.counters + it, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);\n";
-        s << "            }\n        }\n";
+        std::string v = pr->red_op == COOT_RED_NORM2 ? "__builtin_sqrt(acc.hi() + acc.lo())" : "(acc.hi() + acc.lo())";
+        s << "        if (threadIdx.x == 0) " << (red_dtype == COOT_F64 ? "put_f64" : "put_f32") << "(b.red_out, it, " << v
+          << ");\n";
     }
     s << "    }\n}\n";
     std::string body = s.str();

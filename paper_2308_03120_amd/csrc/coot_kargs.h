@@ -23,22 +23,21 @@ typedef struct coot_kargs {
     long long aux;
 } coot_kargs;
 
-/* batched evaluation: one descriptor per item, one per 64x64 tile */
+/* batched evaluation: one descriptor per item; every block owns a list of
+ * whole items (a static longest-first schedule computed on the host) */
 typedef struct coot_batch_item_d {
     long long rows, cols;              /* Y_i shape */
-    long long tile0;                   /* first tile of the item */
-    long long ntiles;
+    long long ntiles;                  /* 64x64 tiles of Y_i */
+    long long pad;
     void* out;
     const void* leaf[6];
 } coot_batch_item_d;
 
 typedef struct coot_bargs {
     const coot_batch_item_d* items;
-    const int* tile_item;              /* item (index into items) of every tile */
-    long long n_tiles;
-    long long tile_base;               /* global index of tile 0 of this launch */
-    void* part;                        /* per-tile partials */
-    unsigned int* counters;            /* per-item tiles-done counters */
+    const int* order;                  /* item indices, block by block */
+    const int* blk_first;              /* block b owns order[blk_first[b] .. blk_first[b+1]) */
+    long long n_blocks;
     void* red_out;
 } coot_bargs;
 

@@ -8,6 +8,7 @@
 #include <sys/stat.h>
 #include <unistd.h>
 
+#include <algorithm>
 #include <chrono>
 #include <cstdio>
 #include <cstdlib>
@@ -136,15 +137,69 @@ static std::vector<char> compile(const std::string& name, const std::string& bod
     return code;
 }
 
+// ---- grouped compilation: many kernels in one code object ------------------
+// Each kernel body is wrapped in a namespace of its own (its helper functions
+// have the same names in every body); the entry points keep their C names.  A
+// small index file per kernel names the module file that holds it.
+static bool g_collect = false;
+static std::vector<std::pair<std::string, std::string>> g_pending;
+static std::unordered_map<std::string, hipModule_t> g_modules;  // module path -> loaded module
+
+static std::string index_of(const std::string& name) { return cache_dir() + "/" + name + "_" + hex64(options_hash()) + ".idx"; }
+
+static bool cached(const std::string& name)
+{
+    std::ifstream a(path_of(name)), b(index_of(name));
+    return (bool)a || (bool)b;
+}
+
 int precompile_kernel(const std::string& name, const std::string& body)
 {
     std::lock_guard<std::mutex> lk(g_mu);
-    std::vector<char> code;
-    std::string p = path_of(name);
-    if (read_file(p, &code)) return 0;
-    code = compile(name, body);
-    write_file_atomic(p, code);
+    if (cached(name)) return 0;
+    if (g_collect) {
+        for (auto& kv : g_pending)
+            if (kv.first == name) return 0;
+        g_pending.emplace_back(name, body);
+        return 1;
+    }
+    std::vector<char> code = compile(name, body);
+    write_file_atomic(path_of(name), code);
     return 1;
+}
+
+void precompile_begin()
+{
+    std::lock_guard<std::mutex> lk(g_mu);
+    g_collect = true;
+    g_pending.clear();
+}
+
+int precompile_end(int per_module)
+{
+    std::lock_guard<std::mutex> lk(g_mu);
+    g_collect = false;
+    if (per_module < 1) per_module = 1;
+    int done = 0;
+    for (size_t s = 0; s < g_pending.size(); s += (size_t)per_module) {
+        size_t e = std::min(g_pending.size(), s + (size_t)per_module);
+        std::string body, names;
+        for (size_t i = s; i < e; ++i) {
+            body += "namespace k" + std::to_string(i - s) + " {\n" + g_pending[i].second + "\n}\n";
+            names += g_pending[i].first + ";";
+        }
+        std::string mod = "coot_mod_" + hex64(fnv1a(names));
+        std::vector<char> code = compile(mod, body);
+        std::string mpath = path_of(mod);
+        write_file_atomic(mpath, code);
+        for (size_t i = s; i < e; ++i) {
+            std::string idx = mpath.substr(mpath.find_last_of('/') + 1);
+            write_file_atomic(index_of(g_pending[i].first), std::vector<char>(idx.begin(), idx.end()));
+            ++done;
+        }
+    }
+    g_pending.clear();
+    return done;
 }
 
 Kernel get_kernel(const std::string& name, const std::string& body, bool has_comb)
@@ -157,6 +212,36 @@ Kernel get_kernel(const std::string& name, const std::string& body, bool has_com
     }
     std::vector<char> code;
     std::string p = path_of(name);
+    // a kernel compiled together with others lives in a shared module
+    {
+        std::ifstream ix(index_of(name));
+        std::string mfile;
+        if (ix && std::getline(ix, mfile) && !mfile.empty() && mfile.find('/') == std::string::npos) {
+            std::string mpath = cache_dir() + "/" + mfile;
+            hipModule_t m = nullptr;
+            auto mi = g_modules.find(mpath);
+            if (mi != g_modules.end()) {
+                m = mi->second;
+            } else if (read_file(mpath, &code) && hipModuleLoadData(&m, code.data()) == hipSuccess) {
+                g_modules[mpath] = m;
+            } else {
+                (void)hipGetLastError();
+                m = nullptr;
+            }
+            Kernel k;
+            if (m && hipModuleGetFunction(&k.fn, m, name.c_str()) == hipSuccess) {
+                k.mod = m;
+                k.fn2 = nullptr;
+                if (!has_comb || hipModuleGetFunction(&k.fn2, m, (name + "_comb").c_str()) == hipSuccess) {
+                    g_jit_stats.disk_hits++;
+                    g_mem[name] = k;
+                    return k;
+                }
+            }
+            (void)hipGetLastError();
+            code.clear();
+        }
+    }
     if (read_file(p, &code)) {
         g_jit_stats.disk_hits++;
     } else {
@@ -186,8 +271,14 @@ Kernel get_kernel(const std::string& name, const std::string& body, bool has_com
 void jit_unload_all()
 {
     std::lock_guard<std::mutex> lk(g_mu);
-    for (auto& kv : g_mem) (void)hipModuleUnload(kv.second.mod);
+    for (auto& kv : g_mem) {
+        bool shared = false;
+        for (auto& m : g_modules) shared = shared || m.second == kv.second.mod;
+        if (!shared) (void)hipModuleUnload(kv.second.mod);
+    }
+    for (auto& m : g_modules) (void)hipModuleUnload(m.second);
     g_mem.clear();
+    g_modules.clear();
 }
 
 }  // namespace coot

@@ -29,6 +29,11 @@ Kernel get_kernel(const std::string& name, const std::string& body, bool has_com
 // Compile into the disk cache only (no device needed).  1 = compiled, 0 = cached.
 int precompile_kernel(const std::string& name, const std::string& body);
 
+// Grouped compilation: between begin and end, precompile_kernel only collects;
+// end compiles the collected kernels, per_module to a code object.
+void precompile_begin();
+int precompile_end(int per_module);
+
 void jit_unload_all();
 
 }  // namespace coot

@@ -347,7 +347,7 @@ Plan make_plan(int red_op_in, int dim, const coot_expr* expr, const coot_operand
 
     // --- vector width of the flat and per-column kinds
     P.ve = 1;
-    if (P.kind == K_EW_FLAT || P.kind == K_RED_FLAT || P.kind == K_RED_COL) {
+    if (P.kind == K_EW_FLAT || P.kind == K_RED_FLAT || P.kind == K_RED_COL || P.kind == K_RED_ROW) {
         int maxsz = 1;
         for (const Read& r : P.reads) maxsz = std::max(maxsz, itemsize(r.dtype));
         if (P.red_op < 0) maxsz = std::max(maxsz, itemsize(out->dtype));
@@ -356,7 +356,7 @@ Plan make_plan(int red_op_in, int dim, const coot_expr* expr, const coot_operand
         for (const Read& r : P.reads) {
             uintptr_t p = (uintptr_t)ops[r.slot].ptr;
             if (p % (uintptr_t)(ve * itemsize(r.dtype))) ok = false;
-            if (P.kind == K_RED_COL && (r.ld % ve)) ok = false;
+            if ((P.kind == K_RED_COL || P.kind == K_RED_ROW) && (r.ld % ve)) ok = false;
         }
         if (P.red_op < 0 && ((uintptr_t)out->ptr % (uintptr_t)(ve * itemsize(out->dtype)))) ok = false;
         P.ve = ok ? ve : 1;
@@ -413,9 +413,15 @@ LaunchCfg default_config(const Plan& p)
     return c;
 }
 
+// Knobs a kernel kind does not use are fixed, so that configurations that
+// differ only there share one compiled kernel.
 LaunchCfg normalise_config(const Plan& p, LaunchCfg c)
 {
-    if (p.kind == K_EW_TILED || p.kind == K_RED_TILED) c.block = 256;  // fixed 64x64 tile shape
+    if (p.kind == K_EW_TILED || p.kind == K_RED_TILED) {
+        c.block = 256;  // fixed 64x64 tile shape
+        c.ept = 1;
+    }
+    if (p.kind == K_RED_COLT || p.kind == K_RED_ROW) c.ept = 1;
     return c;
 }
 

@@ -115,6 +115,19 @@ def test_dim_reductions(g, shape):
         check_sel("index_min", X, [A], dim)
 
 
+@pytest.mark.parametrize("shape", [(100_003, 2), (1 << 20, 3), (300_001, 1), (4097, 17)])
+def test_dim0_of_few_long_columns(g, shape):
+    """Few long columns are cut into row segments combined in order."""
+    for dt in ("f32", "bf16", "f64"):
+        A = mat(g, shape, dt)
+        tol = 1e-13 if dt == "f64" else 1e-6
+        check_sum("sum", X, [A], dim=0, tol=tol)
+        check_sel("index_max", X, [A], 0)
+        check_sel("min", abs_(leaf(0)), [A], 0)
+    A = synth.Mat(synth.store(np.asfortranarray(g.integers(-3, 4, shape).astype(np.float64)), "f32"), "f32")
+    check_sel("index_min", X, [A], 0)   # many ties across segments: the lowest row must win
+
+
 def test_dim_reductions_f64_and_16bit(g):
     for dt, tol in (("f64", 1e-13), ("bf16", 1e-6), ("f16", 1e-6)):
         A = mat(g, (700, 300), dt)
