@@ -247,7 +247,8 @@ int coot_precompile_end(int kernels_per_module);
 
 /* ------------------------------------------------------ batched evaluation -- */
 /* Many matrices, one tree (the roadmap's "collections of matrices",
- * Section 6), evaluated by ONE persistent kernel launch.  For item i the tree
+ * Section 6), evaluated by ONE persistent tile pass (plus, with a reduction,
+ * one small per-item combine launch).  For item i the tree
  * reads slot s from leaf_ptrs[i*n_slots + s]; every operand and output of an
  * item is contiguous (ld = its own n_rows); item i's output is
  * shapes[2i] x shapes[2i+1] and each slot's shape follows from the tree (a
@@ -255,11 +256,14 @@ int coot_precompile_end(int kernels_per_module);
  * NULL, Y_i is stored there in out_dtype.  If red_expr is not NULL, r_i =
  * red_op of red_expr evaluated on Y_i (red_expr's slot 0 is Y_i itself; only
  * the sum-like red_ops ACCU, SUM(dim -1), DOT, NORM1, NORM2 are allowed) is
- * written to red_out[i] (red_dtype F32 or F64).  Each item is processed by
- * one block (items are assigned to blocks longest first, on the host), so
- * r_i is deterministic.  The plan copies the tables to the device and,
- * unless COOT_BATCH_NO_GRAPH is set, captures the launch in a hipGraph that
- * coot_batch_run replays.  The caller keeps every pointer valid while the
+ * written to red_out[i] (red_dtype F32 or F64).  Each item's 64x64 tiles are
+ * cut into tasks of at most 4 tiles; tasks are assigned to blocks longest
+ * first, on the host; each task leaves a compensated partial, and the combine
+ * launch adds an item's partials in task order in FP64, so r_i depends only
+ * on the item's shape and values (deterministic).  expr->cfg.split (if not
+ * 0) sets the tile pass's grid to 4*split blocks per CU (default 2).  The
+ * plan copies the tables to the device and, unless COOT_BATCH_NO_GRAPH is
+ * set, captures the launches in a hipGraph that coot_batch_run replays.  The caller keeps every pointer valid while the
  * plan lives. */
 typedef struct coot_batch {
     const coot_expr* expr;
@@ -286,6 +290,10 @@ typedef struct coot_batch_plan coot_batch_plan;
 
 int coot_batch_create(const coot_batch* batch, void* stream, coot_batch_plan** plan);
 int coot_batch_run(coot_batch_plan* plan, void* stream);
+/* Host only: the HIP source coot_batch_create would compile for this batch
+ * (prelude included) into buf (capacity cap, NUL-terminated); returns the
+ * source length or a negative code.  Pointers in the batch are not read. */
+int64_t coot_batch_kernel_source(const coot_batch* batch, char* buf, int64_t cap);
 int coot_batch_destroy(coot_batch_plan* plan);
 
 /* ---------------------------------------------- launch-configuration choice -- */

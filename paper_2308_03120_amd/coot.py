@@ -101,7 +101,7 @@ EXPORTS = [
     "coot_batch_destroy", "coot_config_of", "coot_set_tuning", "coot_features", "coot_autotune",
     "coot_mlp_forward", "coot_mlp_backward", "coot_mlp_adam", "coot_model_set", "coot_model_choose",
     "coot_get_stats", "coot_copy", "coot_precompile_begin", "coot_precompile_end",
-    "coot_default_config",
+    "coot_default_config", "coot_batch_kernel_source",
 ]
 
 
@@ -126,6 +126,8 @@ def lib():
         L.coot_precompile.argtypes = [i32, i32, P(Expr), P(Operand), i32, P(Operand)]
         L.coot_batch_create.argtypes = [P(Batch), vp, P(vp)]
         L.coot_batch_run.argtypes = [vp, vp]
+        L.coot_batch_kernel_source.argtypes = [P(Batch), C.c_char_p, i64]
+        L.coot_batch_kernel_source.restype = i64
         L.coot_batch_destroy.argtypes = [vp]
         L.coot_config_of.argtypes = [i32, P(Config)]
         L.coot_set_tuning.argtypes = [i32, C.c_char_p]
@@ -448,10 +450,19 @@ class BatchPlan:
     """One persistent launch for many matrices (see coot_batch in coot.h)."""
 
     def __init__(self, tree, slot_dtypes, leaf_ptrs, shapes, out_ptrs=None, out_dtype=F32, red_tree=None,
-                 red_op="accu", red_out=None, red_dtype=F32, flags=0, stream=None):
+                 red_op="accu", red_out=None, red_dtype=F32, flags=0, stream=None, split=None):
+        self.handle = C.c_void_p()
+        self._describe(tree, slot_dtypes, leaf_ptrs, shapes, out_ptrs, out_dtype, red_tree, red_op,
+                       red_out.data_ptr() if red_out is not None else None, red_dtype, flags, split)
+        _check(lib().coot_batch_create(C.byref(self._b), stream if stream is not None else current_stream(),
+                                       C.byref(self.handle)))
+
+    def _describe(self, tree, slot_dtypes, leaf_ptrs, shapes, out_ptrs, out_dtype, red_tree, red_op, red_out_ptr,
+                  red_dtype, flags, split):
         import numpy as np
 
-        self._e = expr(tree)
+        # split: 4*split blocks per CU for the tile pass (None: library default)
+        self._e = expr(tree, None if split is None else (1, 256, split))
         self._re = expr(red_tree) if red_tree is not None else None
         n_items = len(shapes)
         n_slots = len(slot_dtypes)
@@ -474,13 +485,26 @@ class BatchPlan:
         b.red_op = _red_code(red_op, False)
         b.shapes = C.cast(self._sh, C.POINTER(C.c_int64))
         b.red_expr = C.pointer(self._re) if self._re is not None else None
-        b.red_out = red_out.data_ptr() if red_out is not None else None
+        b.red_out = red_out_ptr
         b.red_dtype = red_dtype
         b.flags = flags
         self._b = b
-        self.handle = C.c_void_p()
-        _check(lib().coot_batch_create(C.byref(b), stream if stream is not None else current_stream(),
-                                       C.byref(self.handle)))
+
+    @staticmethod
+    def kernel_source(tree, slot_dtypes, shapes, out=True, out_dtype=F32, red_tree=None, red_op="accu",
+                      red_dtype=F32) -> str:
+        """Host only: the HIP source of the batched kernels (pointers are placeholders)."""
+        G = 1 << 40
+        n = len(shapes)
+        d = BatchPlan.__new__(BatchPlan)
+        d.handle = C.c_void_p()
+        d._describe(tree, slot_dtypes, [[G * (s + 1) for s in range(len(slot_dtypes))]] * n, shapes,
+                    [G * 9] * n if out else None, out_dtype, red_tree, red_op,
+                    G * 10 if red_tree is not None else None, red_dtype, 0, None)
+        size = _check(lib().coot_batch_kernel_source(C.byref(d._b), None, 0))
+        buf = C.create_string_buffer(size + 1)
+        _check(lib().coot_batch_kernel_source(C.byref(d._b), buf, size + 1))
+        return buf.value.decode()
 
     def run(self, stream=None) -> None:
         _check(lib().coot_batch_run(self.handle, stream if stream is not None else current_stream()))

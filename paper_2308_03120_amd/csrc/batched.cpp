@@ -21,8 +21,10 @@ using namespace coot;
 struct coot_batch_plan {
     Kernel k{};
     coot_batch_item_d* d_items = nullptr;
+    coot_batch_task_d* d_tasks = nullptr;
     int* d_order = nullptr;
     int* d_blk_first = nullptr;
+    double* d_part = nullptr;
     int64_t n_items = 0;
     int64_t n_blocks = 1;
     coot_bargs args{};
@@ -45,8 +47,8 @@ namespace {
 std::mutex g_plans_mu;
 std::set<coot_batch_plan*> g_plans;
 
-template <class F>
-int guard3(F&& f)
+template <class R = int, class F>
+R guard3(F&& f)
 {
     try {
         return f();
@@ -62,12 +64,18 @@ int guard3(F&& f)
     }
 }
 
-void launch_b(hipFunction_t f, int64_t grid, coot_bargs& a, hipStream_t st)
+hipError_t launch_b(hipFunction_t f, int64_t grid, coot_bargs& a, hipStream_t st)
 {
     void* params[] = {&a};
-    hipchk(hipModuleLaunchKernel(f, (unsigned)std::max<int64_t>(1, grid), 1, 1, 256, 1, 1, 0, st, params, nullptr),
-           "hipModuleLaunchKernel(batch)");
-    g_state.launches++;
+    return hipModuleLaunchKernel(f, (unsigned)std::max<int64_t>(1, grid), 1, 1, 256, 1, 1, 0, st, params, nullptr);
+}
+
+// the tile pass, then (with a reduction) the per-item combine of the task partials
+hipError_t launch_plan(coot_batch_plan* P, hipStream_t st)
+{
+    hipError_t e = launch_b(P->k.fn, P->n_blocks, P->args, st);
+    if (e == hipSuccess && P->has_red) e = launch_b(P->k.fn2, (P->n_items + 255) / 256, P->args, st);
+    return e;
 }
 
 void free_plan(coot_batch_plan* p)
@@ -75,21 +83,23 @@ void free_plan(coot_batch_plan* p)
     if (p->exec) (void)hipGraphExecDestroy(p->exec);
     if (p->graph) (void)hipGraphDestroy(p->graph);
     (void)hipFree(p->d_items);
+    (void)hipFree(p->d_tasks);
+    (void)hipFree(p->d_part);
     (void)hipFree(p->d_order);
     (void)hipFree(p->d_blk_first);
     delete p;
 }
 
-// Longest-processing-time-first assignment of whole items to blocks: the
-// costliest remaining item goes to the least loaded block (ties: lowest block).
-// Cost of an item: its tiles plus a fixed share for the per-item reduction.
-void lpt_schedule(const std::vector<coot_batch_item_d>& items, int64_t n_blocks, std::vector<int>* order,
+// Longest-processing-time-first assignment of tasks to blocks: the costliest
+// remaining task goes to the least loaded block (ties: lowest block).  Cost of
+// a task: its tiles plus a fixed share for its partial reduction.
+void lpt_schedule(const std::vector<coot_batch_task_d>& tasks, int64_t n_blocks, std::vector<int>* order,
                   std::vector<int>* first)
 {
-    const int64_t n = (int64_t)items.size();
+    const int64_t n = (int64_t)tasks.size();
     std::vector<int> idx((size_t)n);
     for (int64_t i = 0; i < n; ++i) idx[(size_t)i] = (int)i;
-    auto cost = [&](int i) { return (double)items[(size_t)i].ntiles + 0.25; };
+    auto cost = [&](int i) { return (double)(tasks[(size_t)i].t1 - tasks[(size_t)i].t0) + 0.25; };
     std::stable_sort(idx.begin(), idx.end(), [&](int a, int b) { return cost(a) > cost(b); });
     typedef std::pair<double, int64_t> Load;
     std::priority_queue<Load, std::vector<Load>, std::greater<Load>> heap;
@@ -131,6 +141,87 @@ std::vector<int> slot_parities(const coot_expr* e, int n_slots)
     return slot;
 }
 
+// Checks of a batch description and the plans of its element function and
+// reduction tree (host only).
+struct BatchTrees {
+    bool has_out = false, has_red = false;
+    std::vector<int> par, read_slot;
+    Plan py, pr;
+    int y_prec = 32;
+};
+
+BatchTrees plan_batch(const coot_batch* b)
+{
+    BatchTrees T;
+    if (!b->expr || !b->expr->nodes || b->expr->n_nodes < 1) fail(COOT_ERR_BAD_TREE, "batch: empty expression");
+    if (b->n_slots < 1 || b->n_slots > 6) fail(COOT_ERR_UNSUPPORTED, "batch: 1 to 6 operand slots");
+    if (b->n_items < 0) fail(COOT_ERR_ARG, "batch: negative item count");
+    if (!b->slot_dtypes || !b->shapes || (b->n_items > 0 && !b->leaf_ptrs)) fail(COOT_ERR_ARG, "batch: NULL table");
+    if (b->flags & ~(COOT_BATCH_NO_GRAPH | COOT_BATCH_PER_ITEM | COOT_BATCH_UNFUSED))
+        fail(COOT_ERR_ARG, "batch: unknown flags");
+    const bool has_out = b->out_ptrs != nullptr;
+    const bool has_red = b->red_expr != nullptr;
+    if (!has_out && !has_red) fail(COOT_ERR_ARG, "batch: neither outputs nor a reduction requested");
+    for (int s = 0; s < b->n_slots; ++s)
+        if (!is_value_dtype(b->slot_dtypes[s])) fail(COOT_ERR_DTYPE, "batch: slot dtype");
+    if (has_out && !is_value_dtype(b->out_dtype)) fail(COOT_ERR_DTYPE, "batch: out dtype");
+    if (has_red) {
+        const int base = b->red_op & 0xff;
+        if ((b->red_op & ~(0xff | COOT_RED_PAIRWISE)) ||
+            (base != COOT_RED_ACCU && base != COOT_RED_SUM && base != COOT_RED_DOT && base != COOT_RED_NORM1 &&
+             base != COOT_RED_NORM2))
+            fail(COOT_ERR_UNSUPPORTED, "batch: only accu, sum, dot, norm1 and norm2 per item");
+        if (b->red_dtype != COOT_F32 && b->red_dtype != COOT_F64) fail(COOT_ERR_DTYPE, "batch: reduction dtype");
+        if (!b->red_out && b->n_items > 0) fail(COOT_ERR_ARG, "batch: NULL red_out");
+    }
+    if (b->expr->flags != 0 || (has_red && b->red_expr->flags != 0)) fail(COOT_ERR_ARG, "batch: expression flags");
+
+    // per-slot transposition and the shape rule it implies
+    std::vector<int> par = slot_parities(b->expr, b->n_slots);
+    bool need_square = false;
+    for (int s = 0; s < b->n_slots; ++s) need_square = need_square || par[s] == 3;
+    for (int i = 0; i < b->n_items; ++i) {
+        int64_t r = b->shapes[2 * i], c = b->shapes[2 * i + 1];
+        if (r < 0 || c < 0 || r > (1 << 30) || c > (1 << 30)) fail(COOT_ERR_SHAPE, "batch: item shape out of range");
+        if (need_square && r != c) fail(COOT_ERR_SHAPE, "batch: a slot read both straight and transposed needs square items");
+    }
+    // plan the element function on canonical shapes (never vectors)
+    const int64_t cr = need_square ? 3 : 2, cc = 3;
+    const uintptr_t G = uintptr_t(1) << 40;
+    std::vector<coot_operand> fake(b->n_slots);
+    for (int s = 0; s < b->n_slots; ++s) {
+        bool t = par[s] == 2;
+        fake[s] = coot_operand{(void*)(G * (s + 1)), t ? cc : cr, t ? cr : cc, t ? cc : cr, b->slot_dtypes[s], 0};
+    }
+    coot_operand fout{(void*)(G * 9), cr, cc, cr, has_out ? b->out_dtype : COOT_F32, 0};
+    coot_expr ey = *b->expr;
+    ey.cfg = coot_config{0, 0, 0, 0};
+    Plan py = make_plan(-1, -1, &ey, fake.data(), b->n_slots, &fout);
+    const int y_prec = py.nodes[py.root].prec;
+    Plan pr;
+    if (has_red) {
+        int ydt = has_out ? b->out_dtype : (y_prec == 64 ? COOT_F64 : COOT_F32);
+        coot_operand fy{(void*)(G * 10), cr, cc, cr, ydt, 0};
+        coot_operand fr{(void*)(G * 11), 1, 1, 1, b->red_dtype, 0};
+        coot_expr er = *b->red_expr;
+        er.cfg = coot_config{0, 0, 0, 0};
+        pr = make_plan(b->red_op, -1, &er, &fy, 1, &fr);
+        for (const Read& r : pr.reads)
+            if (r.trans) fail(COOT_ERR_UNSUPPORTED, "batch: the reduction tree cannot transpose Y");
+    }
+    std::vector<int> read_slot;
+    for (const Read& r : py.reads) read_slot.push_back(r.slot);
+
+    T.has_out = has_out;
+    T.has_red = has_red;
+    T.par = par;
+    T.read_slot = read_slot;
+    T.py = py;
+    T.pr = pr;
+    T.y_prec = y_prec;
+    return T;
+}
+
 }  // namespace
 
 namespace coot {
@@ -149,66 +240,14 @@ int coot_batch_create(const coot_batch* b, void* stream, coot_batch_plan** out_p
     return guard3([&] {
         if (!b || !out_plan) fail(COOT_ERR_ARG, "NULL batch or plan pointer");
         *out_plan = nullptr;
-        if (!b->expr || !b->expr->nodes || b->expr->n_nodes < 1) fail(COOT_ERR_BAD_TREE, "batch: empty expression");
-        if (b->n_slots < 1 || b->n_slots > 6) fail(COOT_ERR_UNSUPPORTED, "batch: 1 to 6 operand slots");
-        if (b->n_items < 0) fail(COOT_ERR_ARG, "batch: negative item count");
-        if (!b->slot_dtypes || !b->shapes || (b->n_items > 0 && !b->leaf_ptrs)) fail(COOT_ERR_ARG, "batch: NULL table");
-        if (b->flags & ~(COOT_BATCH_NO_GRAPH | COOT_BATCH_PER_ITEM | COOT_BATCH_UNFUSED))
-            fail(COOT_ERR_ARG, "batch: unknown flags");
-        const bool has_out = b->out_ptrs != nullptr;
-        const bool has_red = b->red_expr != nullptr;
-        if (!has_out && !has_red) fail(COOT_ERR_ARG, "batch: neither outputs nor a reduction requested");
-        for (int s = 0; s < b->n_slots; ++s)
-            if (!is_value_dtype(b->slot_dtypes[s])) fail(COOT_ERR_DTYPE, "batch: slot dtype");
-        if (has_out && !is_value_dtype(b->out_dtype)) fail(COOT_ERR_DTYPE, "batch: out dtype");
-        if (has_red) {
-            const int base = b->red_op & 0xff;
-            if ((b->red_op & ~(0xff | COOT_RED_PAIRWISE)) ||
-                (base != COOT_RED_ACCU && base != COOT_RED_SUM && base != COOT_RED_DOT && base != COOT_RED_NORM1 &&
-                 base != COOT_RED_NORM2))
-                fail(COOT_ERR_UNSUPPORTED, "batch: only accu, sum, dot, norm1 and norm2 per item");
-            if (b->red_dtype != COOT_F32 && b->red_dtype != COOT_F64) fail(COOT_ERR_DTYPE, "batch: reduction dtype");
-            if (!b->red_out && b->n_items > 0) fail(COOT_ERR_ARG, "batch: NULL red_out");
-        }
-        if (b->expr->flags != 0 || (has_red && b->red_expr->flags != 0)) fail(COOT_ERR_ARG, "batch: expression flags");
+        BatchTrees T = plan_batch(b);
         ensure_init();
-
-        // per-slot transposition and the shape rule it implies
-        std::vector<int> par = slot_parities(b->expr, b->n_slots);
-        bool need_square = false;
-        for (int s = 0; s < b->n_slots; ++s) need_square = need_square || par[s] == 3;
-        for (int i = 0; i < b->n_items; ++i) {
-            int64_t r = b->shapes[2 * i], c = b->shapes[2 * i + 1];
-            if (r < 0 || c < 0 || r > (1 << 30) || c > (1 << 30)) fail(COOT_ERR_SHAPE, "batch: item shape out of range");
-            if (need_square && r != c) fail(COOT_ERR_SHAPE, "batch: a slot read both straight and transposed needs square items");
-        }
-        // plan the element function on canonical shapes (never vectors)
-        const int64_t cr = need_square ? 3 : 2, cc = 3;
-        const uintptr_t G = uintptr_t(1) << 40;
-        std::vector<coot_operand> fake(b->n_slots);
-        for (int s = 0; s < b->n_slots; ++s) {
-            bool t = par[s] == 2;
-            fake[s] = coot_operand{(void*)(G * (s + 1)), t ? cc : cr, t ? cr : cc, t ? cc : cr, b->slot_dtypes[s], 0};
-        }
-        coot_operand fout{(void*)(G * 9), cr, cc, cr, has_out ? b->out_dtype : COOT_F32, 0};
-        coot_expr ey = *b->expr;
-        ey.cfg = coot_config{0, 0, 0, 0};
-        Plan py = make_plan(-1, -1, &ey, fake.data(), b->n_slots, &fout);
-        const int y_prec = py.nodes[py.root].prec;
-        Plan pr;
-        if (has_red) {
-            int ydt = has_out ? b->out_dtype : (y_prec == 64 ? COOT_F64 : COOT_F32);
-            coot_operand fy{(void*)(G * 10), cr, cc, cr, ydt, 0};
-            coot_operand fr{(void*)(G * 11), 1, 1, 1, b->red_dtype, 0};
-            coot_expr er = *b->red_expr;
-            er.cfg = coot_config{0, 0, 0, 0};
-            pr = make_plan(b->red_op, -1, &er, &fy, 1, &fr);
-            for (const Read& r : pr.reads)
-                if (r.trans) fail(COOT_ERR_UNSUPPORTED, "batch: the reduction tree cannot transpose Y");
-        }
-        std::vector<int> read_slot;
-        for (const Read& r : py.reads) read_slot.push_back(r.slot);
-
+        const bool has_out = T.has_out, has_red = T.has_red;
+        const std::vector<int>& par = T.par;
+        const std::vector<int>& read_slot = T.read_slot;
+        const Plan& py = T.py;
+        const Plan& pr = T.pr;
+        const int y_prec = T.y_prec;
         auto* P = new coot_batch_plan();
         try {
             P->flags = b->flags;
@@ -227,12 +266,20 @@ int coot_batch_create(const coot_batch* b, void* stream, coot_batch_plan** out_p
             P->n_items = b->n_items;
             P->slot_par = par;
             P->h_items.resize((size_t)b->n_items);
+            std::vector<coot_batch_task_d> tasks;
             for (int i = 0; i < b->n_items; ++i) {
                 coot_batch_item_d& d = P->h_items[(size_t)i];
                 std::memset(&d, 0, sizeof d);
                 d.rows = b->shapes[2 * i];
                 d.cols = b->shapes[2 * i + 1];
                 d.ntiles = ((d.rows + 63) / 64) * ((d.cols + 63) / 64);
+                if (d.ntiles > INT32_MAX) fail(COOT_ERR_SHAPE, "batch: item too large (more than 2^31 tiles)");
+                d.part0 = (int64_t)tasks.size();
+                for (int64_t t0 = 0; t0 < d.ntiles; t0 += COOT_BATCH_CHUNK) {
+                    if (tasks.size() >= (size_t)INT32_MAX) fail(COOT_ERR_SHAPE, "batch: more than 2^31 tasks");
+                    tasks.push_back(coot_batch_task_d{i, (int)t0, (int)std::min<int64_t>(d.ntiles, t0 + COOT_BATCH_CHUNK),
+                                                      (int)tasks.size()});
+                }
                 for (int s2 = 0; s2 < b->n_slots; ++s2) {
                     d.leaf[s2] = b->leaf_ptrs[(size_t)i * b->n_slots + s2];
                     if (!d.leaf[s2] && d.rows * d.cols > 0) fail(COOT_ERR_ARG, "batch: NULL operand pointer");
@@ -242,30 +289,38 @@ int coot_batch_create(const coot_batch* b, void* stream, coot_batch_plan** out_p
                     if (!d.out && d.rows * d.cols > 0) fail(COOT_ERR_ARG, "batch: NULL output pointer");
                 }
             }
-            P->n_blocks = std::max<int64_t>(1, std::min<int64_t>(b->n_items, (int64_t)g_state.cus * 4));
+            // 4 blocks of 256 threads per CU per unit of the tree's split setting (default 2)
+            const int split = b->expr->cfg.split > 0 ? b->expr->cfg.split : 2;
+            P->n_blocks = std::max<int64_t>(1, std::min<int64_t>((int64_t)tasks.size(), (int64_t)g_state.cus * 4 * split));
             std::vector<int> order, first;
-            lpt_schedule(P->h_items, P->n_blocks, &order, &first);
+            lpt_schedule(tasks, P->n_blocks, &order, &first);
             auto up = [](void** dst, const void* src, size_t bytes) {
                 hipchk(hipMalloc(dst, std::max<size_t>(bytes, 16)), "hipMalloc(batch table)");
                 if (bytes) hipchk(hipMemcpy(*dst, src, bytes, hipMemcpyHostToDevice), "hipMemcpy(batch table)");
             };
             up((void**)&P->d_items, P->h_items.data(), P->h_items.size() * sizeof(coot_batch_item_d));
+            up((void**)&P->d_tasks, tasks.data(), tasks.size() * sizeof(coot_batch_task_d));
             up((void**)&P->d_order, order.data(), order.size() * sizeof(int));
             up((void**)&P->d_blk_first, first.data(), first.size() * sizeof(int));
-            // kernel
+            if (has_red) {
+                (void)hipFree(P->d_part);
+                P->d_part = nullptr;
+                hipchk(hipMalloc((void**)&P->d_part, std::max<size_t>(16, tasks.size() * 2 * sizeof(double))),
+                       "hipMalloc(batch partials)");
+            }
+            // kernels
             std::string name;
             std::string src = batch_kernel_source(py, has_red ? &pr : nullptr, has_out, b->out_dtype, b->red_dtype,
                                                   read_slot, &name);
-            P->k = get_kernel(name, src, false);
-            P->args = coot_bargs{P->d_items, P->d_order, P->d_blk_first, P->n_blocks, b->red_out};
+            P->k = get_kernel(name, src, has_red);
+            P->args = coot_bargs{P->d_items, P->d_tasks, P->d_order, P->d_blk_first, P->n_items, P->d_part, b->red_out};
             // one launch captured in a graph
             if (!(b->flags & (COOT_BATCH_NO_GRAPH | COOT_BATCH_PER_ITEM | COOT_BATCH_UNFUSED)) && P->n_items > 0) {
                 hipStream_t cap;
                 hipchk(hipStreamCreateWithFlags(&cap, hipStreamNonBlocking), "hipStreamCreate(capture)");
                 hipError_t e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
                 if (e == hipSuccess) {
-                    void* params[] = {&P->args};
-                    e = hipModuleLaunchKernel(P->k.fn, (unsigned)P->n_blocks, 1, 1, 256, 1, 1, 0, cap, params, nullptr);
+                    e = launch_plan(P, cap);
                     hipGraph_t g = nullptr;
                     hipError_t e2 = hipStreamEndCapture(cap, &g);
                     if (e == hipSuccess) e = e2;
@@ -286,6 +341,24 @@ int coot_batch_create(const coot_batch* b, void* stream, coot_batch_plan** out_p
         }
         *out_plan = P;
         return COOT_OK;
+    });
+}
+
+int64_t coot_batch_kernel_source(const coot_batch* b, char* buf, int64_t cap)
+{
+    return guard3<int64_t>([&]() -> int64_t {
+        if (!b) fail(COOT_ERR_ARG, "NULL batch");
+        BatchTrees T = plan_batch(b);
+        std::string name;
+        std::string src = batch_kernel_source(T.py, T.has_red ? &T.pr : nullptr, T.has_out, b->out_dtype, b->red_dtype,
+                                              T.read_slot, &name);
+        src = prelude_source() + "\n" + src;
+        if (buf && cap > 0) {
+            const size_t n = std::min<size_t>(src.size(), (size_t)cap - 1);
+            std::memcpy(buf, src.data(), n);
+            buf[n] = 0;
+        }
+        return (int64_t)src.size();
     });
 }
 
@@ -332,7 +405,8 @@ int coot_batch_run(coot_batch_plan* P, void* stream)
             hipchk(hipGraphLaunch(P->exec, st), "hipGraphLaunch");
             g_state.launches++;
         } else {
-            launch_b(P->k.fn, P->n_blocks, P->args, st);
+            hipchk(launch_plan(P, st), "hipModuleLaunchKernel(batch)");
+            g_state.launches += P->has_red ? 2 : 1;
         }
         return COOT_OK;
     });

@@ -8,6 +8,7 @@
 // either stored once or folded into a reduction accumulator.
 #include <cmath>
 #include <cstdio>
+#include <functional>
 #include <sstream>
 
 #include "internal.h"
@@ -372,78 +373,127 @@ static std::string tile_shared_decls(const Plan& p, const TilePlan& tp, const st
     return s.str();
 }
 
-// Tile loop over tiles t = first, next(t), ... (next gives -1 at the end).
-// Needs R, Cn, tr, lane, w, L<j>, ld<j> in scope; per_elem(args) is the
-// statement run for every element (ig, jg) of the tile inside the matrix.
-template <class F>
-static std::string tile_loop(const Plan& p, const TilePlan& tp, const std::string& ind, const std::string& first,
-                             const std::string& next_tt, F per_elem)
+// A 64x64 tile of the tree's value is read by 4 waves: wave w, step kk
+// (0..15) handles tile column (or, for an LDS-staged transposed read, stored
+// row) q = w + 4*kk, lane l the 64 contiguous elements along it.  Every
+// address is a wave-uniform base plus the lane, so the loads and stores take
+// a scalar base and a 32-bit lane offset; the only per-lane condition of a
+// tile is lane < (rows or columns left), tested once, and lanes past it load
+// the tile's first element again (same cache line, value unused).  Register
+// buffers: pt<j> for LDS-staged transposed reads, pr<j> (prefetch) and cr<j>
+// (current) for the others.
+static std::string tile_regs(const Plan& p, const TilePlan& tp, const std::string& ind)
 {
     std::ostringstream s;
-    const size_t nr = p.reads.size();
-    auto C = [&](size_t j) { return ctype(p.reads[j].dtype == COOT_F64 ? 64 : 32); };
-    for (size_t j = 0; j < nr; ++j) {
-        if (tp.in_lds[j]) s << ind << C(j) << " pt" << j << "[16];\n";
-        else s << ind << C(j) << " pr" << j << "[16], cr" << j << "[16];\n";
+    for (size_t j = 0; j < p.reads.size(); ++j) {
+        const std::string C = ctype(p.reads[j].dtype == COOT_F64 ? 64 : 32);
+        if (tp.in_lds[j]) s << ind << C << " pt" << j << "[16];\n";
+        else s << ind << C << " pr" << j << "[16], cr" << j << "[16];\n";
     }
-    auto prefetch = [&](const std::string& tt, const std::string& in) {
-        std::ostringstream o;
-        o << in << "{\n" << in << "    const i64 pi0 = ((" << tt << ") % tr) << 6, pj0 = ((" << tt << ") / tr) << 6;\n";
-        o << in << "#pragma unroll\n" << in << "    for (int kk = 0; kk < 16; ++kk) {\n";
-        for (size_t j = 0; j < nr; ++j) {
-            std::string J = std::to_string(j);
-            if (tp.in_lds[j]) {
-                o << in << "        { const i64 ig = pi0 + w + 4 * kk, jg = pj0 + lane; pt" << J
-                  << "[kk] = (ig < R && jg < Cn) ? " << widen(p.reads[j].dtype, "ldnt(L" + J + " + jg + ig * ld" + J + ")")
-                  << " : (" << C(j) << ")0; }\n";
-            } else if (p.reads[j].trans) {
-                o << in << "        { const i64 ig = pi0 + lane, jg = pj0 + w + 4 * kk; pr" << J
-                  << "[kk] = (ig < R && jg < Cn) ? " << widen(p.reads[j].dtype, "ldnt(L" + J + " + jg + ig * ld" + J + ")")
-                  << " : (" << C(j) << ")0; }\n";
-            } else {
-                o << in << "        { const i64 ig = pi0 + lane, jg = pj0 + w + 4 * kk; pr" << J
-                  << "[kk] = (ig < R && jg < Cn) ? " << widen(p.reads[j].dtype, "ldnt(L" + J + " + ig + jg * ld" + J + ")")
-                  << " : (" << C(j) << ")0; }\n";
-            }
+    return s.str();
+}
+
+// Names the prefetch reads through: the operand's shape, base and leading
+// dimension of every read.
+struct TileView {
+    std::string R, Cn;
+    std::function<std::string(size_t)> L, ld;
+};
+
+// Load tile (ti, tj) of the view into the prefetch registers.  Each read
+// walks a wave-uniform pointer a<j> by s<j> per step.
+static std::string tile_prefetch(const Plan& p, const TilePlan& tp, const std::string& in, const std::string& ti,
+                                 const std::string& tj, const TileView& v, const std::string& ldf = "ldnt")
+{
+    std::ostringstream o;
+    o << in << "{\n";
+    o << in << "    const i64 pi0 = (i64)(" << ti << ") << 6, pj0 = (i64)(" << tj << ") << 6;\n";
+    o << in << "    const int pri = (int)(" << v.R << " - pi0 < 64 ? " << v.R << " - pi0 : 64);\n";
+    o << in << "    const int prj = (int)(" << v.Cn << " - pj0 < 64 ? " << v.Cn << " - pj0 : 64);\n";
+    o << in << "    const u32 lr = lane < pri ? (u32)lane : 0u, lc = lane < prj ? (u32)lane : 0u;\n";
+    for (size_t j = 0; j < p.reads.size(); ++j) {
+        const std::string J = std::to_string(j), L = v.L(j), ld = v.ld(j), S = stype(p.reads[j].dtype);
+        if (tp.in_lds[j]) {
+            // stored rows pi0+q of the read operand (columns of the value), elements pj0+lane
+            o << in << "    const " << S << "* a" << J << " = " << L << " + (pj0 + (pi0 + w) * " << ld << ");\n";
+            o << in << "    const i64 s" << J << " = 4 * " << ld << ";\n";
+        } else if (p.reads[j].trans) {
+            o << in << "    const " << S << "* a" << J << " = " << L << " + (pj0 + w + pi0 * " << ld << ");\n";
+            o << in << "    const i64 s" << J << " = 4;\n";
+            o << in << "    const i64 lrs" << J << " = (i64)lr * " << ld << ";\n";
+        } else {
+            o << in << "    const " << S << "* a" << J << " = " << L << " + (pi0 + (pj0 + w) * " << ld << ");\n";
+            o << in << "    const i64 s" << J << " = 4 * " << ld << ";\n";
         }
-        o << in << "    }\n" << in << "}\n";
-        return o.str();
-    };
-    auto subst = [](std::string e, const std::string& tt) {
-        for (size_t pos; (pos = e.find("@")) != std::string::npos;) e.replace(pos, 1, tt);
-        return e;
-    };
-    s << ind << "i64 t = " << first << ";\n";
-    s << ind << "if (t >= 0)\n" << prefetch("t", ind + "    ");
-    s << ind << "while (t >= 0) {\n";
-    const std::string in = ind + "    ";
-    s << in << "const i64 i0 = (t % tr) << 6, j0 = (t / tr) << 6;\n";
-    s << in << "const i64 tn = " << subst(next_tt, "t") << ";\n";
+    }
+    o << in << "#pragma unroll\n" << in << "    for (int kk = 0; kk < 16; ++kk) {\n";
+    o << in << "        const int q = w + 4 * kk;\n";
+    for (size_t j = 0; j < p.reads.size(); ++j) {
+        const std::string J = std::to_string(j), C = ctype(p.reads[j].dtype == COOT_F64 ? 64 : 32);
+        if (tp.in_lds[j])
+            o << in << "        pt" << J << "[kk] = q < pri ? " << widen(p.reads[j].dtype, ldf + "(a" + J + " + lc)") << " : (" << C
+              << ")0;\n";
+        else if (p.reads[j].trans)
+            o << in << "        pr" << J << "[kk] = q < prj ? " << widen(p.reads[j].dtype, ldf + "(a" + J + " + lrs" + J + ")")
+              << " : (" << C << ")0;\n";
+        else
+            o << in << "        pr" << J << "[kk] = q < prj ? " << widen(p.reads[j].dtype, ldf + "(a" + J + " + lr)") << " : (" << C
+              << ")0;\n";
+        o << in << "        a" << J << " += s" << J << ";\n";
+    }
+    o << in << "    }\n" << in << "}\n";
+    return o.str();
+}
+
+// Move the prefetched tile to where the compute step reads it.
+static std::string tile_stage(const Plan& p, const TilePlan& tp, const std::string& in)
+{
+    std::ostringstream s;
     if (tp.any_lds) {
         s << in << "__syncthreads();\n";
         s << in << "#pragma unroll\n" << in << "for (int kk = 0; kk < 16; ++kk) {\n";
-        for (size_t j = 0; j < nr; ++j)
+        for (size_t j = 0; j < p.reads.size(); ++j)
             if (tp.in_lds[j]) s << in << "    T" << j << "[w + 4 * kk][lane] = pt" << j << "[kk];\n";
         s << in << "}\n";
     }
-    for (size_t j = 0; j < nr; ++j)
+    for (size_t j = 0; j < p.reads.size(); ++j)
         if (!tp.in_lds[j])
             s << in << "#pragma unroll\n" << in << "for (int kk = 0; kk < 16; ++kk) cr" << j << "[kk] = pr" << j << "[kk];\n";
     if (tp.any_lds) s << in << "__syncthreads();\n";
-    s << in << "if (tn >= 0)\n" << prefetch("tn", in + "    ");
-    s << in << "const i64 ig = i0 + lane;\n";
-    s << in << "if (ig < R) {\n" << in << "#pragma unroll\n" << in << "    for (int kk = 0; kk < 16; ++kk) {\n";
-    s << in << "        const int jj = w + 4 * kk;\n" << in << "        const i64 jg = j0 + jj;\n";
-    s << in << "        if (jg < Cn) {\n";
+    return s.str();
+}
+
+// Run per_elem(args, indent) for every element of the staged tile (ti, tj)
+// inside an R x Cn value.  In scope for per_elem: i0, j0 (tile origin),
+// ig = i0 + lane (per lane), jg = j0 + jj (wave-uniform) and, when out is
+// given (an OT* with leading dimension ldo), po + lane, the element's address
+// in it.
+template <class F>
+static std::string tile_compute(const Plan& p, const TilePlan& tp, const std::string& in, const std::string& ti,
+                                const std::string& tj, const std::string& R, const std::string& Cn, const std::string& out,
+                                const std::string& OT, const std::string& ldo, F per_elem)
+{
+    std::ostringstream s;
+    s << in << "{\n";
+    s << in << "    const i64 i0 = (i64)(" << ti << ") << 6, j0 = (i64)(" << tj << ") << 6;\n";
+    s << in << "    const int ri = (int)(" << R << " - i0 < 64 ? " << R << " - i0 : 64);\n";
+    s << in << "    const int rj = (int)(" << Cn << " - j0 < 64 ? " << Cn << " - j0 : 64);\n";
+    if (!out.empty()) s << in << "    " << OT << "* po = " << out << " + (i0 + (j0 + w) * " << ldo << ");\n";
+    s << in << "    if (lane < ri) {\n";
+    s << in << "        const i64 ig = i0 + lane;\n";
+    s << in << "#pragma unroll\n" << in << "        for (int kk = 0; kk < 16; ++kk) {\n";
+    s << in << "            const int jj = w + 4 * kk;\n";
+    s << in << "            if (jj < rj) {\n";
+    s << in << "                const i64 jg = j0 + jj;\n";
     std::string args;
-    for (size_t j = 0; j < nr; ++j) {
+    for (size_t j = 0; j < p.reads.size(); ++j) {
         if (j) args += ", ";
         args += tp.in_lds[j] ? "T" + std::to_string(j) + "[lane][jj]" : "cr" + std::to_string(j) + "[kk]";
     }
-    s << per_elem(args, in + "            ");
+    s << per_elem(args, in + "                ");
+    s << in << "            }\n";
+    if (!out.empty()) s << in << "            po += 4 * " << ldo << ";\n";
     s << in << "        }\n" << in << "    }\n" << in << "}\n";
-    s << in << "t = tn;\n";
-    s << ind << "}\n";
     return s.str();
 }
 
@@ -463,16 +513,29 @@ static std::string emit_tiled(const Plan& p, const std::string& name)
     } else {
         s << "    " << acc_type(p) << " acc;\n    acc.init();\n";
     }
-    s << "    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;\n";
+    s << "    const int lane = threadIdx.x & 63, w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);\n";
     s << "    const i64 R = a.rows, Cn = a.cols;\n";
-    s << "    const i64 tr = (R + 63) >> 6, tc = (Cn + 63) >> 6, nt = tr * tc;\n";
-    s << tile_loop(p, tp, "    ", "((i64)blockIdx.x < nt ? (i64)blockIdx.x : -1)",
-                   "(@ + (i64)gridDim.x < nt ? @ + (i64)gridDim.x : -1)", [&](const std::string& args, const std::string& in) {
-                       if (ew)
-                           return in + "stnt(O + ig + jg * ldo, (" + std::string(stype(p.out_dtype)) + ")(" +
-                                  narrow(p.out_dtype, rp, "x_eval(" + args + ")") + "));\n";
-                       return in + accumulate(p, args, "(ig + jg * R)") + "\n";
-                   });
+    // tile counts fit in int for every matrix that fits in device memory
+    s << "    const int tr = (int)((R + 63) >> 6), tc = tr > 0 ? (int)((Cn + 63) >> 6) : 0, trs = tr > 0 ? tr : 1;\n";
+    s << "    const int gq = (int)gridDim.x / trs, gr = (int)gridDim.x % trs;\n";
+    s << "    int ti = (int)blockIdx.x % trs, tj = (int)blockIdx.x / trs;\n";
+    s << tile_regs(p, tp, "    ");
+    TileView v{"R", "Cn", [](size_t j) { return "L" + std::to_string(j); }, [](size_t j) { return "ld" + std::to_string(j); }};
+    s << "    if (tj < tc)\n" << tile_prefetch(p, tp, "        ", "ti", "tj", v);
+    s << "    while (tj < tc) {\n";
+    s << "        int ni = ti + gr, nj = tj + gq;\n";
+    s << "        if (ni >= tr) { ni -= tr; ++nj; }\n";
+    s << tile_stage(p, tp, "        ");
+    s << "        if (nj < tc)\n" << tile_prefetch(p, tp, "            ", "ni", "nj", v);
+    s << tile_compute(p, tp, "        ", "ti", "tj", "R", "Cn", ew ? "O" : "", stype(p.out_dtype), "ldo",
+                      [&](const std::string& args, const std::string& in) {
+        if (ew)
+            return in + "stnt(po + lane, (" + std::string(stype(p.out_dtype)) + ")(" +
+                   narrow(p.out_dtype, rp, "x_eval(" + args + ")") + "));\n";
+        return in + accumulate(p, args, "(ig + jg * R)") + "\n";
+    });
+    s << "        ti = ni;\n        tj = nj;\n";
+    s << "    }\n";
     if (!ew) {
         s << "    __shared__ " << acc_type(p) << " lds_acc[4];\n";
         s << "    acc = block_reduce(acc, lds_acc);\n";
@@ -610,6 +673,10 @@ static std::string emit_row(const Plan& p, const std::string& name)
 std::string batch_kernel_source(const Plan& py, const Plan* pr, bool has_out, int out_dtype, int red_dtype,
                                 const std::vector<int>& read_slot, std::string* name_out)
 {
+    // Loads and stores go through the caches: an item's column segments are
+    // rarely aligned to cache lines, and a line shared by two tiles is then
+    // served from L2 the second time (streaming hints cost ~15% here).
+    const std::string LDF = "ldpl", STF = "stpl";
     std::ostringstream s;
     const int rp = py.nodes[py.root].prec;
     s << "// batch tree: " << py.body_sig << "\n";
@@ -620,57 +687,123 @@ std::string batch_kernel_source(const Plan& py, const Plan* pr, bool has_out, in
     }
     const TilePlan tp = tile_plan(py);
     const std::string ACC = pr ? (pr->nodes[pr->root].prec == 64 ? "AccKD" : (pr->pairwise ? "AccPF" : "AccKF")) : "";
+    const std::string OS = stype(out_dtype);
+    const size_t nr = py.reads.size();
+    auto S = [&](size_t j) { return std::string(stype(py.reads[j].dtype)); };
+    // Each block runs its tasks' tiles as one sequence; the tile after the
+    // current one (possibly the next task's first) is prefetched while the
+    // current one is computed.  Three views: c (the task being computed), q
+    // (the item of the prefetched tile) and d (the next task, its descriptor
+    // loaded one task ahead).
+    auto load_d = [&](const std::string& in, bool decl) {
+        std::ostringstream o;
+        const std::string T = decl ? "i64 " : "";
+        o << in << (decl ? "coot_batch_task_d " : "") << "dt = b.tasks[dk];\n";
+        o << in << (decl ? "i64 " : "") << "dR = b.items[dt.item].rows;\n";
+        o << in << (decl ? "i64 " : "") << "dCn = b.items[dt.item].cols;\n";
+        for (size_t j = 0; j < nr; ++j)
+            o << in << (decl ? "const " + S(j) + "* " : std::string()) << "dL" << j << " = (const " << S(j)
+              << "*)b.items[dt.item].leaf[" << read_slot[j] << "];\n";
+        if (has_out) o << in << (decl ? OS + "* " : std::string()) << "dO = (" << OS << "*)b.items[dt.item].out;\n";
+        (void)T;
+        return o.str();
+    };
     s << "extern \"C\" __global__ void __launch_bounds__(256) COOT_KERNEL_NAME(const coot_bargs b)\n{\n";
     s << tile_shared_decls(py, tp, "    ");
     if (pr) s << "    __shared__ " << ACC << " lds_acc[4];\n";
-    s << "    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;\n";
+    s << "    const int lane = threadIdx.x & 63, w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);\n";
+    s << "    int si = b.blk_first[blockIdx.x];\n";
     s << "    const int s_end = b.blk_first[blockIdx.x + 1];\n";
-    s << "    for (int si = b.blk_first[blockIdx.x]; si < s_end; ++si) {\n";
-    s << "        const int it = b.order[si];\n";
-    s << "        const coot_batch_item_d* I = b.items + it;\n";
-    s << "        const i64 R = I->rows, Cn = I->cols, ntl = I->ntiles;\n";
-    s << "        const i64 tr = (R + 63) >> 6;\n";
-    for (size_t j = 0; j < py.reads.size(); ++j) {
-        const char* S = stype(py.reads[j].dtype);
-        s << "        const " << S << "* L" << j << " = (const " << S << "*)I->leaf[" << read_slot[j] << "];\n";
-        // a straight read has the item's shape (ld = R); a transposed one is Cn x R (ld = Cn)
-        s << "        const i64 ld" << j << " = " << (py.reads[j].trans ? "Cn" : "R") << ";\n";
-    }
-    if (has_out) s << "        " << stype(out_dtype) << "* O = (" << stype(out_dtype) << "*)I->out;\n";
-    if (pr) s << "        " << ACC << " acc;\n        acc.init();\n";
-    s << tile_loop(py, tp, "        ", "(ntl > 0 ? (i64)0 : (i64)-1)", "(@ + 1 < ntl ? @ + 1 : -1)",
-                   [&](const std::string& args, const std::string& in) {
-                       std::ostringstream o;
-                       o << in << "const " << ctype(rp) << " y = x_eval(" << args << ");\n";
-                       std::string yv = "y";
-                       if (has_out) {
-                           o << in << "const " << stype(out_dtype) << " yo = " << narrow(out_dtype, rp, "y") << ";\n";
-                           o << in << "stnt(O + ig + jg * R, yo);\n";
-                           if (out_dtype == COOT_F16) yv = "widen_f16(yo)";
-                           else if (out_dtype == COOT_BF16) yv = "widen_bf16(yo)";
-                           else yv = "yo";
-                       }
-                       if (pr) {
-                           const int pp = pr->nodes[pr->root].prec;
-                           if (pr->product_form)
-                               o << in << "{ " << ctype(pp) << " pa, pb; r_pair(" << yv << ", pa, pb); acc.add_prod(pa, pb); }\n";
-                           else if (pr->red_op == COOT_RED_NORM2)
-                               o << in << "{ const " << ctype(pp) << " u = r_eval(" << yv << "); acc.add_prod(u, u); }\n";
-                           else if (pr->red_op == COOT_RED_NORM1)
-                               o << in << "acc.add(" << (pp == 64 ? "__builtin_fabs" : "__builtin_fabsf") << "(r_eval(" << yv
-                                 << ")));\n";
-                           else
-                               o << in << "acc.add(r_eval(" << yv << "));\n";
-                       }
-                       return o.str();
-                   });
+    s << "    if (si >= s_end) return;\n";
+    s << "    int dk = b.order[si];\n";
+    s << load_d("    ", true);
+    s << "    i64 cR = dR, cCn = dCn;\n";
+    if (has_out) s << "    " << OS << "* cO = dO;\n";
+    s << "    int ctr = (int)((cR + 63) >> 6), crem = dt.t1 - dt.t0, cpart = dt.part;\n";
+    s << "    int ti = dt.t0 % ctr, tj = dt.t0 / ctr;\n";
+    s << "    i64 qR = dR, qCn = dCn;\n";
+    for (size_t j = 0; j < nr; ++j) s << "    const " << S(j) << "* qL" << j << " = dL" << j << ";\n";
+    s << "    dk = si + 1 < s_end ? b.order[si + 1] : dk;\n";
+    s << load_d("    ", false);
+    s << tile_regs(py, tp, "    ");
+    if (pr) s << "    " << ACC << " acc;\n    acc.init();\n";
+    // a straight read has the item's shape (ld = rows); a transposed one is cols x rows (ld = cols)
+    TileView v{"qR", "qCn", [](size_t j) { return "qL" + std::to_string(j); },
+               [&](size_t j) { return std::string(py.reads[j].trans ? "qCn" : "qR"); }};
+    s << tile_prefetch(py, tp, "    ", "ti", "tj", v, LDF);
+    s << "    for (;;) {\n";
+    s << "        int ni = ti + 1, nj = tj, nsi = si;\n";
+    s << "        if (ni >= ctr) { ni = 0; ++nj; }\n";
+    s << "        if (crem <= 1) {\n";
+    s << "            ++nsi;\n";
+    s << "            const int dtr = (int)((dR + 63) >> 6);\n";
+    s << "            ni = dt.t0 % dtr;\n            nj = dt.t0 / dtr;\n";
+    s << "        }\n";
+    s << "        const bool more = nsi < s_end;\n";
+    s << "        if (more && nsi != si) {\n";
+    s << "            qR = dR;\n            qCn = dCn;\n";
+    for (size_t j = 0; j < nr; ++j) s << "            qL" << j << " = dL" << j << ";\n";
+    s << "        }\n";
+    s << tile_stage(py, tp, "        ");
+    s << "        if (more)\n" << tile_prefetch(py, tp, "            ", "ni", "nj", v, LDF);
+    s << tile_compute(py, tp, "        ", "ti", "tj", "cR", "cCn", has_out ? "cO" : "", OS, "cR",
+                      [&](const std::string& args, const std::string& in) {
+        std::ostringstream o;
+        o << in << "const " << ctype(rp) << " y = x_eval(" << args << ");\n";
+        std::string yv = "y";
+        if (has_out) {
+            o << in << "const " << OS << " yo = " << narrow(out_dtype, rp, "y") << ";\n";
+            o << in << STF << "(po + lane, yo);\n";
+            if (out_dtype == COOT_F16) yv = "widen_f16(yo)";
+            else if (out_dtype == COOT_BF16) yv = "widen_bf16(yo)";
+            else yv = "yo";
+        }
+        if (pr) {
+            const int pp = pr->nodes[pr->root].prec;
+            if (pr->product_form)
+                o << in << "{ " << ctype(pp) << " pa, pb; r_pair(" << yv << ", pa, pb); acc.add_prod(pa, pb); }\n";
+            else if (pr->red_op == COOT_RED_NORM2)
+                o << in << "{ const " << ctype(pp) << " u = r_eval(" << yv << "); acc.add_prod(u, u); }\n";
+            else if (pr->red_op == COOT_RED_NORM1)
+                o << in << "acc.add(" << (pp == 64 ? "__builtin_fabs" : "__builtin_fabsf") << "(r_eval(" << yv << ")));\n";
+            else
+                o << in << "acc.add(r_eval(" << yv << "));\n";
+        }
+        return o.str();
+    });
+    s << "        if (nsi != si) {\n";
     if (pr) {
-        s << "        acc = block_reduce(acc, lds_acc);\n";
-        std::string v = pr->red_op == COOT_RED_NORM2 ? "__builtin_sqrt(acc.hi() + acc.lo())" : "(acc.hi() + acc.lo())";
-        s << "        if (threadIdx.x == 0) " << (red_dtype == COOT_F64 ? "put_f64" : "put_f32") << "(b.red_out, it, " << v
-          << ");\n";
+        s << "            acc = block_reduce(acc, lds_acc);\n";
+        s << "            if (threadIdx.x == 0) {\n";
+        s << "                b.part[2 * (i64)cpart] = acc.hi();\n";
+        s << "                b.part[2 * (i64)cpart + 1] = acc.lo();\n";
+        s << "            }\n";
+        s << "            acc.init();\n";
     }
+    s << "            if (!more) break;\n";
+    s << "            cR = dR;\n            cCn = dCn;\n";
+    if (has_out) s << "            cO = dO;\n";
+    s << "            ctr = (int)((cR + 63) >> 6);\n            crem = dt.t1 - dt.t0;\n            cpart = dt.part;\n";
+    s << "            dk = nsi + 1 < s_end ? b.order[nsi + 1] : dk;\n";
+    s << load_d("            ", false);
+    s << "        } else {\n            --crem;\n        }\n";
+    s << "        si = nsi;\n        ti = ni;\n        tj = nj;\n";
     s << "    }\n}\n";
+    if (pr) {
+        // per item: FP64 compensated sum of its tasks' partials in task order,
+        // then the final transform
+        s << "extern \"C\" __global__ void __launch_bounds__(256) COOT_KERNEL_NAME_comb(const coot_bargs b)\n{\n";
+        s << "    const i64 i = (i64)blockIdx.x * 256 + threadIdx.x;\n";
+        s << "    if (i >= b.n_items) return;\n";
+        s << "    const i64 nt = b.items[i].ntiles, p0 = b.items[i].part0;\n";
+        s << "    const i64 np = (nt + COOT_BATCH_CHUNK - 1) / COOT_BATCH_CHUNK;\n";
+        s << "    AccKD a;\n    a.init();\n";
+        s << "    for (i64 k = 0; k < np; ++k) {\n";
+        s << "        a.add(b.part[2 * (p0 + k)]);\n        a.add(b.part[2 * (p0 + k) + 1]);\n    }\n";
+        std::string val = pr->red_op == COOT_RED_NORM2 ? "__builtin_sqrt(a.hi() + a.lo())" : "(a.hi() + a.lo())";
+        s << "    " << (red_dtype == COOT_F64 ? "put_f64" : "put_f32") << "(b.red_out, i, " << val << ");\n";
+        s << "}\n";
+    }
     std::string body = s.str();
     static const uint64_t prelude_hash = fnv1a(prelude_source());
     std::string name = "coot_batch_" + hex64(fnv1a(body + (has_out ? "o" : "") + std::to_string(out_dtype) + "|" +

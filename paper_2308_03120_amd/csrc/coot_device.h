@@ -135,6 +135,19 @@ CD void stnt(S* p, S v)
 #endif
 }
 
+/* single-element load / store through the caches */
+template <class S>
+CD S ldpl(const S* p)
+{
+    return *p;
+}
+
+template <class S>
+CD void stpl(S* p, S v)
+{
+    *p = v;
+}
+
 /* ------------------------------------------------------------------ */
 /* accumulators                                                         */
 /* ------------------------------------------------------------------ */

@@ -23,21 +23,33 @@ typedef struct coot_kargs {
     long long aux;
 } coot_kargs;
 
-/* batched evaluation: one descriptor per item; every block owns a list of
- * whole items (a static longest-first schedule computed on the host) */
+/* batched evaluation: one descriptor per item; the items' 64x64 tiles are cut
+ * into tasks of at most COOT_BATCH_CHUNK consecutive tiles (column-major tile
+ * order within the item), and every block runs a list of tasks (a static
+ * longest-first schedule computed on the host) */
+#define COOT_BATCH_CHUNK 4
+
 typedef struct coot_batch_item_d {
     long long rows, cols;              /* Y_i shape */
     long long ntiles;                  /* 64x64 tiles of Y_i */
-    long long pad;
+    long long part0;                   /* partial slot of the item's first task */
     void* out;
     const void* leaf[6];
 } coot_batch_item_d;
 
+typedef struct coot_batch_task_d {
+    int item;
+    int t0, t1;                        /* tiles [t0, t1) of the item */
+    int part;                          /* partial slot (item's tasks are consecutive) */
+} coot_batch_task_d;
+
 typedef struct coot_bargs {
     const coot_batch_item_d* items;
-    const int* order;                  /* item indices, block by block */
-    const int* blk_first;              /* block b owns order[blk_first[b] .. blk_first[b+1]) */
-    long long n_blocks;
+    const coot_batch_task_d* tasks;
+    const int* order;                  /* task indices, block by block */
+    const int* blk_first;              /* block b runs order[blk_first[b] .. blk_first[b+1]) */
+    long long n_items;
+    double* part;                      /* (hi, lo) per task when there is a reduction */
     void* red_out;
 } coot_bargs;
 

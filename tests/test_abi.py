@@ -148,3 +148,28 @@ def test_generated_kernels_compile_for_gfx950(tmp_path, monkeypatch, red, dim, t
     odt = "u64" if red == "index_max" else "f32"
     o = F(out[0], out[1], odt, ld=1 if out[0] == 1 else out[0], ptr=9 * G)
     assert coot.precompile(red, dim, trees[tree], opnds, o) in (0, 1)
+
+
+def test_batched_kernels_compile_for_gfx950(tmp_path):
+    """The batched tile pass and its per-item combine, generated on the host,
+    compile for gfx950 with the library's strict floating-point options."""
+    import shutil
+    import subprocess
+
+    hipcc = shutil.which("hipcc") or "/opt/rocm/bin/hipcc"
+    if not os.path.exists(hipcc):
+        pytest.skip("hipcc not available")
+    import synth
+    src = coot.BatchPlan.kernel_source(synth.cfg4_tree(), [coot.F32, coot.F32], [[5, 7], [64, 64], [0, 3]],
+                                       red_tree=synth.leaf(0) % synth.leaf(0))
+    names = re.findall(r"__global__ void __launch_bounds__\(256\) (coot_batch_[0-9a-f]{16}(?:_comb)?)\(", src)
+    assert len(names) == 2 and names[1] == names[0] + "_comb"
+    f = tmp_path / "batch.hip"
+    f.write_text("#include <hip/hip_runtime.h>\n" + src)
+    r = subprocess.run([hipcc, "--offload-arch=gfx950", "-O3", "-std=c++17", "-ffp-contract=off", "-Xclang",
+                        "-target-feature", "-Xclang", "-packed-fp32-ops", "--cuda-device-only", "-c", str(f), "-o",
+                        str(tmp_path / "batch.o")], capture_output=True, text=True)
+    assert r.returncode == 0, r.stderr[-2000:]
+    # without a reduction there is no combine kernel
+    src2 = coot.BatchPlan.kernel_source(synth.cfg4_tree(), [coot.F32, coot.F32], [[5, 7]])
+    assert "_comb" not in src2

@@ -85,6 +85,37 @@ def test_small_ragged_batch_against_oracle(dt):
     plan.close()
 
 
+def test_results_do_not_depend_on_the_grid():
+    """Items are cut into fixed 4-tile tasks whose partials are combined in task
+    order, so Y and r are bit-identical for every grid size."""
+    g = np.random.default_rng(8)
+    shapes = np.concatenate([np.array([[512, 512], [300, 500], [1, 4000], [4000, 1], [65, 65]]),
+                             g.integers(1, 300, (200, 2))])
+    offs, total, A, B = make_batch(shapes, g)
+    dA, dB = torch.from_numpy(A).cuda(), torch.from_numpy(B).cuda()
+    es = 4
+    ptrs = [[dA.data_ptr() + int(o) * es, dB.data_ptr() + int(o) * es] for o in offs]
+    res = []
+    for split in (1, 2, 8):
+        dY = torch.full((total,), float("nan"), device="cuda")
+        red = torch.zeros(len(shapes), device="cuda")
+        plan = coot.BatchPlan(Ytree, [coot.F32, coot.F32], ptrs, [[int(c), int(r)] for r, c in shapes],
+                              out_ptrs=[dY.data_ptr() + int(o) * es for o in offs], red_tree=Rtree, red_op="accu",
+                              red_out=red, split=split)
+        plan.run()
+        torch.cuda.synchronize()
+        res.append((dY.clone(), red.clone()))
+        plan.close()
+    for y, r in res[1:]:
+        assert torch.equal(torch.nan_to_num(y, nan=7.0), torch.nan_to_num(res[0][0], nan=7.0))
+        assert torch.equal(r, res[0][1])
+    rh = res[0][1].cpu().numpy().astype(np.float64)
+    for i in (0, 1, 2, 3):
+        Am, Bm = host_mats(shapes, offs, A, B, i)
+        o, _, _ = oracle.reduce("accu", (Ytree % Ytree).postfix(), [Am, Bm], mode="emu")
+        assert abs(rh[i] - o[0]) <= 1e-6 * abs(o[0]), (i, rh[i], o[0])
+
+
 def test_reduction_only_and_empty_items():
     g = np.random.default_rng(6)
     shapes = np.array([[5, 9], [0, 4], [33, 0], [100, 100], [1, 1]])
