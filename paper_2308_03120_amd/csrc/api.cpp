@@ -158,12 +158,21 @@ void launch(hipFunction_t f, int64_t grid, int block, coot_kargs& a, hipStream_t
     g_state.launches++;
 }
 
+// Size class of a call for the tuned and model caches: kernel signature,
+// floor(log2) of the element count and of the row count (the shape decides
+// the grid of the per-dimension kinds).
 std::string tune_key(const Plan& p)
 {
-    int lg = 0;
-    while (lg < 62 && (int64_t(1) << (lg + 1)) <= p.n) ++lg;
+    auto lg2 = [](int64_t v) {
+        int lg = 0;
+        while (lg < 62 && (int64_t(1) << (lg + 1)) <= v) ++lg;
+        return lg;
+    };
     return std::to_string(p.kind) + "|" + std::to_string(p.ve) + "|" + std::to_string(p.red_op) + "|" +
-           std::to_string(p.pairwise) + "|" + std::to_string(p.out_dtype) + "|" + p.body_sig + "|n" + std::to_string(lg);
+           std::to_string(p.pairwise) + "|" + std::to_string(p.dim) + "|" + std::to_string(p.tile_lr) + "," +
+           std::to_string(p.tile_lc) + "|" +
+           std::to_string(p.out_dtype) + "|" +
+           p.body_sig + "|n" + std::to_string(lg2(p.n)) + "|r" + std::to_string(lg2(p.rows));
 }
 
 LaunchCfg choose_config(const Plan& p, const coot_config& user)
@@ -205,7 +214,7 @@ static Geometry geometry(const Plan& p, const LaunchCfg& c)
     }
     case K_EW_TILED:
     case K_RED_TILED: {
-        int64_t nt = ceil_div(p.rows, 64) * ceil_div(p.cols, 64);
+        int64_t nt = ceil_div(p.rows, int64_t(1) << p.tile_lr) * ceil_div(p.cols, int64_t(1) << p.tile_lc);
         G.block = 256;
         G.grid = std::max<int64_t>(1, std::min(nt, c.split >= 8 ? nt : (int64_t)g_state.cus * c.split * 2));
         break;
@@ -270,7 +279,8 @@ static Kernel kernel_for(const Plan& p, const LaunchCfg& c)
 {
     std::string key = std::to_string(p.kind) + "|" + std::to_string(p.ve) + "|" + std::to_string(c.ept) + "|" +
                       std::to_string(p.out_dtype) + "|" + std::to_string(p.red_op) + "|" + std::to_string(p.pairwise) +
-                      "|" + std::to_string(p.alias_out) + "|" + p.body_sig;
+                      "|" + std::to_string(p.alias_out) + "|" + std::to_string(p.tile_gen) + std::to_string(p.tile_lr) + "," +
+                      std::to_string(p.tile_lc) + "|" + p.body_sig;
     {
         std::lock_guard<std::mutex> lk(g_sig_mu);
         auto it = g_sig_kernels.find(key);

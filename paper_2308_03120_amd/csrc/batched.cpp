@@ -272,7 +272,10 @@ int coot_batch_create(const coot_batch* b, void* stream, coot_batch_plan** out_p
                 std::memset(&d, 0, sizeof d);
                 d.rows = b->shapes[2 * i];
                 d.cols = b->shapes[2 * i + 1];
-                d.ntiles = ((d.rows + 63) / 64) * ((d.cols + 63) / 64);
+                coot_batch_tile_shape(d.rows, d.cols, &d.lr, &d.lc);
+                d.ntiles = d.rows > 0 && d.cols > 0
+                               ? ((d.rows + (1 << d.lr) - 1) >> d.lr) * ((d.cols + (1 << d.lc) - 1) >> d.lc)
+                               : 0;
                 if (d.ntiles > INT32_MAX) fail(COOT_ERR_SHAPE, "batch: item too large (more than 2^31 tiles)");
                 d.part0 = (int64_t)tasks.size();
                 for (int64_t t0 = 0; t0 < d.ntiles; t0 += COOT_BATCH_CHUNK) {

@@ -355,7 +355,7 @@ static TilePlan tile_plan(const Plan& p)
     int budget = 96 * 1024;
     for (size_t j = 0; j < p.reads.size(); ++j) {
         if (!p.reads[j].trans) continue;
-        int bytes = 64 * 65 * (p.reads[j].dtype == COOT_F64 ? 8 : 4);
+        int bytes = COOT_TILE_LDS * (p.reads[j].dtype == COOT_F64 ? 8 : 4);
         if (bytes <= budget) {
             t.in_lds[j] = true;
             budget -= bytes;
@@ -369,19 +369,24 @@ static std::string tile_shared_decls(const Plan& p, const TilePlan& tp, const st
 {
     std::ostringstream s;
     for (size_t j = 0; j < p.reads.size(); ++j)
-        if (tp.in_lds[j]) s << ind << "__shared__ " << ctype(p.reads[j].dtype == COOT_F64 ? 64 : 32) << " T" << j << "[64][65];\n";
+        if (tp.in_lds[j])
+            s << ind << "__shared__ " << ctype(p.reads[j].dtype == COOT_F64 ? 64 : 32) << " T" << j << "[COOT_TILE_LDS];\n";
     return s.str();
 }
 
-// A 64x64 tile of the tree's value is read by 4 waves: wave w, step kk
-// (0..15) handles tile column (or, for an LDS-staged transposed read, stored
-// row) q = w + 4*kk, lane l the 64 contiguous elements along it.  Every
-// address is a wave-uniform base plus the lane, so the loads and stores take
-// a scalar base and a 32-bit lane offset; the only per-lane condition of a
-// tile is lane < (rows or columns left), tested once, and lanes past it load
-// the tile's first element again (same cache line, value unused).  Register
-// buffers: pt<j> for LDS-staged transposed reads, pr<j> (prefetch) and cr<j>
-// (current) for the others.
+// A tile of 2^lr x 2^lc elements of the tree's value is handled in up to 64
+// steps m = w + 4*kk (wave w, kk = 0..15) of 64 lanes.  Position
+// p = 64*m + lane of the tile maps to (p mod TR, p / TR) for the value's
+// layout ("Y order": straight reads, register-held transposed reads, the
+// output) and to (p / TC, p mod TC) for an operand read transposed and staged
+// through LDS ("A order": lanes run along the operand's own columns).  Either
+// way a step touches 64 consecutive elements of a column (or whole short
+// columns), so loads and stores coalesce.  The square 64 x 64 case has its
+// own code: lane = row, step = column.  Register buffers: pt<j> for
+// LDS-staged transposed reads, pr<j> (prefetch) and cr<j> (current) for the
+// others.  Every address is a wave-uniform base plus a per-lane offset that
+// is fixed for the tile; a lane outside the value reads the step's first
+// element instead (same cache line, value unused).
 static std::string tile_regs(const Plan& p, const TilePlan& tp, const std::string& ind)
 {
     std::ostringstream s;
@@ -393,34 +398,32 @@ static std::string tile_regs(const Plan& p, const TilePlan& tp, const std::strin
     return s.str();
 }
 
-// Names the prefetch reads through: the operand's shape, base and leading
-// dimension of every read.
+// Names the prefetch reads through: the value's shape, its tile shape
+// (log2), and the base and leading dimension of every read.
 struct TileView {
-    std::string R, Cn;
+    std::string R, Cn, lr, lc;
     std::function<std::string(size_t)> L, ld;
 };
 
-// Load tile (ti, tj) of the view into the prefetch registers.  Each read
-// walks a wave-uniform pointer a<j> by s<j> per step.
-static std::string tile_prefetch(const Plan& p, const TilePlan& tp, const std::string& in, const std::string& ti,
-                                 const std::string& tj, const TileView& v, const std::string& ldf = "ldnt")
+// --- square 64 x 64 tiles --------------------------------------------------
+static std::string tile_prefetch_sq(const Plan& p, const TilePlan& tp, const std::string& in, const std::string& ti,
+                                    const std::string& tj, const TileView& v, const std::string& ldf)
 {
     std::ostringstream o;
     o << in << "{\n";
     o << in << "    const i64 pi0 = (i64)(" << ti << ") << 6, pj0 = (i64)(" << tj << ") << 6;\n";
     o << in << "    const int pri = (int)(" << v.R << " - pi0 < 64 ? " << v.R << " - pi0 : 64);\n";
     o << in << "    const int prj = (int)(" << v.Cn << " - pj0 < 64 ? " << v.Cn << " - pj0 : 64);\n";
-    o << in << "    const u32 lr = lane < pri ? (u32)lane : 0u, lc = lane < prj ? (u32)lane : 0u;\n";
+    o << in << "    const u32 lnr = lane < pri ? (u32)lane : 0u, lnc = lane < prj ? (u32)lane : 0u;\n";
     for (size_t j = 0; j < p.reads.size(); ++j) {
         const std::string J = std::to_string(j), L = v.L(j), ld = v.ld(j), S = stype(p.reads[j].dtype);
         if (tp.in_lds[j]) {
-            // stored rows pi0+q of the read operand (columns of the value), elements pj0+lane
             o << in << "    const " << S << "* a" << J << " = " << L << " + (pj0 + (pi0 + w) * " << ld << ");\n";
             o << in << "    const i64 s" << J << " = 4 * " << ld << ";\n";
         } else if (p.reads[j].trans) {
             o << in << "    const " << S << "* a" << J << " = " << L << " + (pj0 + w + pi0 * " << ld << ");\n";
             o << in << "    const i64 s" << J << " = 4;\n";
-            o << in << "    const i64 lrs" << J << " = (i64)lr * " << ld << ";\n";
+            o << in << "    const i64 lrs" << J << " = (i64)lnr * " << ld << ";\n";
         } else {
             o << in << "    const " << S << "* a" << J << " = " << L << " + (pi0 + (pj0 + w) * " << ld << ");\n";
             o << in << "    const i64 s" << J << " = 4 * " << ld << ";\n";
@@ -431,13 +434,13 @@ static std::string tile_prefetch(const Plan& p, const TilePlan& tp, const std::s
     for (size_t j = 0; j < p.reads.size(); ++j) {
         const std::string J = std::to_string(j), C = ctype(p.reads[j].dtype == COOT_F64 ? 64 : 32);
         if (tp.in_lds[j])
-            o << in << "        pt" << J << "[kk] = q < pri ? " << widen(p.reads[j].dtype, ldf + "(a" + J + " + lc)") << " : (" << C
+            o << in << "        pt" << J << "[kk] = q < pri ? " << widen(p.reads[j].dtype, ldf + "(a" + J + " + lnc)") << " : (" << C
               << ")0;\n";
         else if (p.reads[j].trans)
             o << in << "        pr" << J << "[kk] = q < prj ? " << widen(p.reads[j].dtype, ldf + "(a" + J + " + lrs" + J + ")")
               << " : (" << C << ")0;\n";
         else
-            o << in << "        pr" << J << "[kk] = q < prj ? " << widen(p.reads[j].dtype, ldf + "(a" + J + " + lr)") << " : (" << C
+            o << in << "        pr" << J << "[kk] = q < prj ? " << widen(p.reads[j].dtype, ldf + "(a" + J + " + lnr)") << " : (" << C
               << ")0;\n";
         o << in << "        a" << J << " += s" << J << ";\n";
     }
@@ -445,15 +448,14 @@ static std::string tile_prefetch(const Plan& p, const TilePlan& tp, const std::s
     return o.str();
 }
 
-// Move the prefetched tile to where the compute step reads it.
-static std::string tile_stage(const Plan& p, const TilePlan& tp, const std::string& in)
+static std::string tile_stage_sq(const Plan& p, const TilePlan& tp, const std::string& in)
 {
     std::ostringstream s;
     if (tp.any_lds) {
         s << in << "__syncthreads();\n";
         s << in << "#pragma unroll\n" << in << "for (int kk = 0; kk < 16; ++kk) {\n";
         for (size_t j = 0; j < p.reads.size(); ++j)
-            if (tp.in_lds[j]) s << in << "    T" << j << "[w + 4 * kk][lane] = pt" << j << "[kk];\n";
+            if (tp.in_lds[j]) s << in << "    T" << j << "[(w + 4 * kk) * 65 + lane] = pt" << j << "[kk];\n";
         s << in << "}\n";
     }
     for (size_t j = 0; j < p.reads.size(); ++j)
@@ -463,15 +465,14 @@ static std::string tile_stage(const Plan& p, const TilePlan& tp, const std::stri
     return s.str();
 }
 
-// Run per_elem(args, indent) for every element of the staged tile (ti, tj)
-// inside an R x Cn value.  In scope for per_elem: i0, j0 (tile origin),
-// ig = i0 + lane (per lane), jg = j0 + jj (wave-uniform) and, when out is
-// given (an OT* with leading dimension ldo), po + lane, the element's address
-// in it.
+// per_elem(args, indent, addr): run for every element of the tile inside the
+// value; in scope: i0, j0 (tile origin), ig, jg (the element's row and
+// column); addr is the element's address in the output when out is given (an
+// OT* with leading dimension ldo).
 template <class F>
-static std::string tile_compute(const Plan& p, const TilePlan& tp, const std::string& in, const std::string& ti,
-                                const std::string& tj, const std::string& R, const std::string& Cn, const std::string& out,
-                                const std::string& OT, const std::string& ldo, F per_elem)
+static std::string tile_compute_sq(const Plan& p, const TilePlan& tp, const std::string& in, const std::string& ti,
+                                   const std::string& tj, const std::string& R, const std::string& Cn,
+                                   const std::string& out, const std::string& OT, const std::string& ldo, F per_elem)
 {
     std::ostringstream s;
     s << in << "{\n";
@@ -488,18 +489,214 @@ static std::string tile_compute(const Plan& p, const TilePlan& tp, const std::st
     std::string args;
     for (size_t j = 0; j < p.reads.size(); ++j) {
         if (j) args += ", ";
-        args += tp.in_lds[j] ? "T" + std::to_string(j) + "[lane][jj]" : "cr" + std::to_string(j) + "[kk]";
+        args += tp.in_lds[j] ? "T" + std::to_string(j) + "[lane * 65 + jj]" : "cr" + std::to_string(j) + "[kk]";
     }
-    s << per_elem(args, in + "                ");
+    s << per_elem(args, in + "                ", "po + lane");
     s << in << "            }\n";
     if (!out.empty()) s << in << "            po += 4 * " << ldo << ";\n";
     s << in << "        }\n" << in << "    }\n" << in << "}\n";
     return s.str();
 }
 
+// --- shape-adaptive tiles ---------------------------------------------------
+// Steps: wave w takes steps m = w*spw .. w*spw + spw - 1 (spw = steps per
+// wave).  Two orders walk the tile: Y order (rows along lanes: the value's
+// layout; straight reads, register-held transposed reads, the output) and A
+// order (columns along lanes: an operand read transposed and staged through
+// LDS).  For an order whose lane dimension is at most 64 long, a step covers
+// 64/T whole lines; otherwise a step covers 64 elements of one line and
+// consecutive steps move down the line, then to the next one.  Walkers keep
+// the step origin (row, column) and one running pointer per read, advanced
+// by scalar adds.
+static std::string tile_lanes(const std::string& in, const std::string& lr, const std::string& lc, const std::string& rr,
+                              const std::string& cc)
+{
+    std::ostringstream o;
+    o << in << "const int yi = " << lr << " <= 6 ? (lane & ((1 << " << lr << ") - 1)) : lane;\n";
+    o << in << "const int yj = " << lr << " <= 6 ? (lane >> " << lr << ") : 0;\n";
+    o << in << "const int aj = " << lc << " <= 6 ? (lane & ((1 << " << lc << ") - 1)) : lane;\n";
+    o << in << "const int ai = " << lc << " <= 6 ? (lane >> " << lc << ") : 0;\n";
+    o << in << "const int nst = " << lr << " + " << lc << " >= 6 ? 1 << (" << lr << " + " << lc << " - 6) : 1;\n";
+    o << in << "const int spw = nst >= 4 ? nst >> 2 : 1, m0 = w * spw;\n";
+    o << in << "const bool lin = lane < (1 << (" << lr << " + " << lc << "));\n";
+    o << in << "const bool yok = lin && (" << lr << " > 6 || yi < " << rr << ");\n";
+    o << in << "const bool aok = lin && (" << lc << " > 6 || aj < " << cc << ");\n";
+    o << in << "int ysr = " << lr << " <= 6 ? 0 : (m0 & ((1 << (" << lr << " - 6)) - 1)) << 6;\n";
+    o << in << "int ysc = " << lr << " <= 6 ? m0 << (6 - " << lr << ") : m0 >> (" << lr << " - 6);\n";
+    o << in << "int asc = " << lc << " <= 6 ? 0 : (m0 & ((1 << (" << lc << " - 6)) - 1)) << 6;\n";
+    o << in << "int asr = " << lc << " <= 6 ? m0 << (6 - " << lc << ") : m0 >> (" << lc << " - 6);\n";
+    return o.str();
+}
+
+// advance the Y walker (ptrs: running pointers with their leading dimension
+// and whether they are read transposed) or the A walker
+static std::string walk_y(const std::string& in, const std::string& lr,
+                          const std::vector<std::pair<std::string, std::pair<std::string, bool>>>& ptrs)
+{
+    std::ostringstream o;
+    o << in << "if (" << lr << " <= 6) {\n";
+    o << in << "    ysc += 64 >> " << lr << ";\n";
+    for (auto& p : ptrs)
+        o << in << "    " << p.first << " += " << (p.second.second ? "(i64)(64 >> " + lr + ")" : "(i64)(64 >> " + lr + ") * " + p.second.first)
+          << ";\n";
+    o << in << "} else {\n";
+    o << in << "    ysr += 64;\n";
+    for (auto& p : ptrs) o << in << "    " << p.first << " += " << (p.second.second ? "64 * " + p.second.first : "64") << ";\n";
+    o << in << "    if (ysr == (1 << " << lr << ")) {\n";
+    o << in << "        ysr = 0;\n" << in << "        ++ysc;\n";
+    for (auto& p : ptrs)
+        o << in << "        " << p.first << " += "
+          << (p.second.second ? "1 - ((i64)1 << " + lr + ") * " + p.second.first : p.second.first + " - (1 << " + lr + ")") << ";\n";
+    o << in << "    }\n" << in << "}\n";
+    return o.str();
+}
+
+static std::string walk_a(const std::string& in, const std::string& lc,
+                          const std::vector<std::pair<std::string, std::string>>& ptrs)
+{
+    std::ostringstream o;
+    o << in << "if (" << lc << " <= 6) {\n";
+    o << in << "    asr += 64 >> " << lc << ";\n";
+    for (auto& p : ptrs) o << in << "    " << p.first << " += (i64)(64 >> " << lc << ") * " << p.second << ";\n";
+    o << in << "} else {\n";
+    o << in << "    asc += 64;\n";
+    for (auto& p : ptrs) o << in << "    " << p.first << " += 64;\n";
+    o << in << "    if (asc == (1 << " << lc << ")) {\n";
+    o << in << "        asc = 0;\n" << in << "        ++asr;\n";
+    for (auto& p : ptrs) o << in << "        " << p.first << " += " << p.second << " - (1 << " << lc << ");\n";
+    o << in << "    }\n" << in << "}\n";
+    return o.str();
+}
+
+static std::string tile_prefetch_gen(const Plan& p, const TilePlan& tp, const std::string& in, const std::string& ti,
+                                     const std::string& tj, const TileView& v, const std::string& ldf)
+{
+    std::ostringstream o;
+    o << in << "{\n";
+    const std::string i2 = in + "    ";
+    o << i2 << "const i64 pi0 = (i64)(" << ti << ") << " << v.lr << ", pj0 = (i64)(" << tj << ") << " << v.lc << ";\n";
+    o << i2 << "const int prr = (int)(" << v.R << " - pi0 < (1 << " << v.lr << ") ? " << v.R << " - pi0 : (1 << " << v.lr
+      << "));\n";
+    o << i2 << "const int pcc = (int)(" << v.Cn << " - pj0 < (1 << " << v.lc << ") ? " << v.Cn << " - pj0 : (1 << " << v.lc
+      << "));\n";
+    o << tile_lanes(i2, v.lr, v.lc, "prr", "pcc");
+    std::vector<std::pair<std::string, std::pair<std::string, bool>>> yp;
+    std::vector<std::pair<std::string, std::string>> ap;
+    for (size_t j = 0; j < p.reads.size(); ++j) {
+        const std::string J = std::to_string(j), L = v.L(j), ld = v.ld(j), S = stype(p.reads[j].dtype);
+        if (tp.in_lds[j]) {
+            o << i2 << "const " << S << "* a" << J << " = " << L << " + ((pj0 + asc) + (pi0 + asr) * " << ld << ");\n";
+            o << i2 << "const i64 v" << J << " = aj + (i64)ai * " << ld << ";\n";
+            ap.push_back({"a" + J, ld});
+        } else if (p.reads[j].trans) {
+            o << i2 << "const " << S << "* a" << J << " = " << L << " + ((pj0 + ysc) + (pi0 + ysr) * " << ld << ");\n";
+            o << i2 << "const i64 v" << J << " = yj + (i64)yi * " << ld << ";\n";
+            yp.push_back({"a" + J, {ld, true}});
+        } else {
+            o << i2 << "const " << S << "* a" << J << " = " << L << " + ((pi0 + ysr) + (pj0 + ysc) * " << ld << ");\n";
+            o << i2 << "const i64 v" << J << " = yi + (i64)yj * " << ld << ";\n";
+            yp.push_back({"a" + J, {ld, false}});
+        }
+    }
+    o << in << "#pragma unroll\n" << i2 << "for (int kk = 0; kk < 16; ++kk) {\n";
+    const std::string i3 = i2 + "    ";
+    o << i3 << "if (kk < spw && m0 < nst) {\n";
+    const std::string i4 = i3 + "    ";
+    if (!yp.empty()) {
+        o << i4 << "const bool yu = ysr < prr && ysc < pcc;\n";
+        o << i4 << "const bool yv = yok && (" << v.lr << " <= 6 ? yj < pcc - ysc : yi < prr - ysr);\n";
+    }
+    if (!ap.empty()) {
+        o << i4 << "const bool au = asr < prr && asc < pcc;\n";
+        o << i4 << "const bool av = aok && (" << v.lc << " <= 6 ? ai < prr - asr : aj < pcc - asc);\n";
+    }
+    for (size_t j = 0; j < p.reads.size(); ++j) {
+        const std::string J = std::to_string(j), C = ctype(p.reads[j].dtype == COOT_F64 ? 64 : 32);
+        if (tp.in_lds[j])
+            o << i4 << "pt" << J << "[kk] = au ? " << widen(p.reads[j].dtype, ldf + "(a" + J + " + (av ? v" + J + " : 0))")
+              << " : (" << C << ")0;\n";
+        else
+            o << i4 << "pr" << J << "[kk] = yu ? " << widen(p.reads[j].dtype, ldf + "(a" + J + " + (yv ? v" + J + " : 0))")
+              << " : (" << C << ")0;\n";
+    }
+    if (!yp.empty()) o << walk_y(i4, v.lr, yp);
+    if (!ap.empty()) o << walk_a(i4, v.lc, ap);
+    o << i3 << "}\n" << i2 << "}\n" << in << "}\n";
+    return o.str();
+}
+
+static std::string tile_stage_gen(const Plan& p, const TilePlan& tp, const std::string& in, const std::string& R,
+                                  const std::string& Cn, const std::string& ti, const std::string& tj, const std::string& lr,
+                                  const std::string& lc)
+{
+    std::ostringstream s;
+    if (tp.any_lds) {
+        s << in << "__syncthreads();\n";
+        s << in << "{\n";
+        const std::string i2 = in + "    ";
+        s << i2 << "const int prr = (int)(" << R << " - ((i64)(" << ti << ") << " << lr << ") < (1 << " << lr << ") ? " << R
+          << " - ((i64)(" << ti << ") << " << lr << ") : (1 << " << lr << "));\n";
+        s << i2 << "const int pcc = (int)(" << Cn << " - ((i64)(" << tj << ") << " << lc << ") < (1 << " << lc << ") ? " << Cn
+          << " - ((i64)(" << tj << ") << " << lc << ") : (1 << " << lc << "));\n";
+        s << tile_lanes(i2, lr, lc, "prr", "pcc");
+        s << i2 << "const int sst = coot_tile_stride(" << lr << ", " << lc << ");\n";
+        s << in << "#pragma unroll\n" << i2 << "for (int kk = 0; kk < 16; ++kk) {\n";
+        s << i2 << "    if (kk < spw && m0 < nst) {\n";
+        s << i2 << "        if (lin) {\n";
+        for (size_t j = 0; j < p.reads.size(); ++j)
+            if (tp.in_lds[j]) s << i2 << "            T" << j << "[(asr + ai) * sst + asc + aj] = pt" << j << "[kk];\n";
+        s << i2 << "        }\n";
+        s << walk_a(i2 + "        ", lc, {});
+        s << i2 << "    }\n" << i2 << "}\n" << in << "}\n";
+    }
+    for (size_t j = 0; j < p.reads.size(); ++j)
+        if (!tp.in_lds[j])
+            s << in << "#pragma unroll\n" << in << "for (int kk = 0; kk < 16; ++kk) cr" << j << "[kk] = pr" << j << "[kk];\n";
+    if (tp.any_lds) s << in << "__syncthreads();\n";
+    return s.str();
+}
+
+template <class F>
+static std::string tile_compute_gen(const Plan& p, const TilePlan& tp, const std::string& in, const std::string& ti,
+                                    const std::string& tj, const std::string& R, const std::string& Cn,
+                                    const std::string& lr, const std::string& lc, const std::string& out,
+                                    const std::string& OT, const std::string& ldo, F per_elem)
+{
+    std::ostringstream s;
+    s << in << "{\n";
+    const std::string i2 = in + "    ";
+    s << i2 << "const i64 i0 = (i64)(" << ti << ") << " << lr << ", j0 = (i64)(" << tj << ") << " << lc << ";\n";
+    s << i2 << "const int rr = (int)(" << R << " - i0 < (1 << " << lr << ") ? " << R << " - i0 : (1 << " << lr << "));\n";
+    s << i2 << "const int cc = (int)(" << Cn << " - j0 < (1 << " << lc << ") ? " << Cn << " - j0 : (1 << " << lc << "));\n";
+    s << tile_lanes(i2, lr, lc, "rr", "cc");
+    if (tp.any_lds) s << i2 << "const int sst = coot_tile_stride(" << lr << ", " << lc << ");\n";
+    std::vector<std::pair<std::string, std::pair<std::string, bool>>> yp;
+    if (!out.empty()) {
+        s << i2 << OT << "* po = " << out << " + ((i0 + ysr) + (j0 + ysc) * " << ldo << ");\n";
+        s << i2 << "const i64 vo = yi + (i64)yj * " << ldo << ";\n";
+        yp.push_back({"po", {ldo, false}});
+    }
+    s << in << "#pragma unroll\n" << i2 << "for (int kk = 0; kk < 16; ++kk) {\n";
+    s << i2 << "    if (kk < spw && m0 < nst) {\n";
+    const std::string i4 = i2 + "        ";
+    s << i4 << "if (ysr < rr && ysc < cc && yok && (" << lr << " <= 6 ? yj < cc - ysc : yi < rr - ysr)) {\n";
+    s << i4 << "    const i64 ig = i0 + ysr + yi, jg = j0 + ysc + yj;\n";
+    std::string args;
+    for (size_t j = 0; j < p.reads.size(); ++j) {
+        if (j) args += ", ";
+        args += tp.in_lds[j] ? "T" + std::to_string(j) + "[(ysr + yi) * sst + ysc + yj]" : "cr" + std::to_string(j) + "[kk]";
+    }
+    s << per_elem(args, i4 + "    ", "(po + vo)");
+    s << i4 << "}\n";
+    s << walk_y(i4, lr, yp);
+    s << i2 << "    }\n" << i2 << "}\n" << in << "}\n";
+    return s.str();
+}
+
 static std::string emit_tiled(const Plan& p, const std::string& name)
 {
     const bool ew = p.kind == K_EW_TILED;
+    const bool gen = p.tile_gen;
     const int rp = p.nodes[p.root].prec;
     const TilePlan tp = tile_plan(p);
     std::ostringstream s;
@@ -515,25 +712,36 @@ static std::string emit_tiled(const Plan& p, const std::string& name)
     }
     s << "    const int lane = threadIdx.x & 63, w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);\n";
     s << "    const i64 R = a.rows, Cn = a.cols;\n";
+    // tile shape, fixed per kernel: 2^lr x 2^lc
+    s << "    const int lr = " << p.tile_lr << ", lc = " << p.tile_lc << ";\n";
     // tile counts fit in int for every matrix that fits in device memory
-    s << "    const int tr = (int)((R + 63) >> 6), tc = tr > 0 ? (int)((Cn + 63) >> 6) : 0, trs = tr > 0 ? tr : 1;\n";
+    s << "    const int tr = (int)((R + (1 << lr) - 1) >> lr);\n";
+    s << "    const int tc = tr > 0 ? (int)((Cn + (1 << lc) - 1) >> lc) : 0, trs = tr > 0 ? tr : 1;\n";
     s << "    const int gq = (int)gridDim.x / trs, gr = (int)gridDim.x % trs;\n";
     s << "    int ti = (int)blockIdx.x % trs, tj = (int)blockIdx.x / trs;\n";
     s << tile_regs(p, tp, "    ");
-    TileView v{"R", "Cn", [](size_t j) { return "L" + std::to_string(j); }, [](size_t j) { return "ld" + std::to_string(j); }};
-    s << "    if (tj < tc)\n" << tile_prefetch(p, tp, "        ", "ti", "tj", v);
+    TileView v{"R", "Cn", "lr", "lc", [](size_t j) { return "L" + std::to_string(j); },
+               [](size_t j) { return "ld" + std::to_string(j); }};
+    auto prefetch = [&](const std::string& in, const std::string& a, const std::string& b) {
+        return gen ? tile_prefetch_gen(p, tp, in, a, b, v, "ldnt") : tile_prefetch_sq(p, tp, in, a, b, v, "ldnt");
+    };
+    auto elem = [&](const std::string& args, const std::string& in, const std::string& addr) {
+        if (ew)
+            return in + "stnt(" + addr + ", (" + std::string(stype(p.out_dtype)) + ")(" +
+                   narrow(p.out_dtype, rp, "x_eval(" + args + ")") + "));\n";
+        return in + accumulate(p, args, "(ig + jg * R)") + "\n";
+    };
+    s << "    if (tj < tc)\n" << prefetch("        ", "ti", "tj");
     s << "    while (tj < tc) {\n";
     s << "        int ni = ti + gr, nj = tj + gq;\n";
     s << "        if (ni >= tr) { ni -= tr; ++nj; }\n";
-    s << tile_stage(p, tp, "        ");
-    s << "        if (nj < tc)\n" << tile_prefetch(p, tp, "            ", "ni", "nj", v);
-    s << tile_compute(p, tp, "        ", "ti", "tj", "R", "Cn", ew ? "O" : "", stype(p.out_dtype), "ldo",
-                      [&](const std::string& args, const std::string& in) {
-        if (ew)
-            return in + "stnt(po + lane, (" + std::string(stype(p.out_dtype)) + ")(" +
-                   narrow(p.out_dtype, rp, "x_eval(" + args + ")") + "));\n";
-        return in + accumulate(p, args, "(ig + jg * R)") + "\n";
-    });
+    s << (gen ? tile_stage_gen(p, tp, "        ", "R", "Cn", "ti", "tj", "lr", "lc") : tile_stage_sq(p, tp, "        "));
+    s << "        if (nj < tc)\n" << prefetch("            ", "ni", "nj");
+    if (gen)
+        s << tile_compute_gen(p, tp, "        ", "ti", "tj", "R", "Cn", "lr", "lc", ew ? "O" : "", stype(p.out_dtype), "ldo",
+                              elem);
+    else
+        s << tile_compute_sq(p, tp, "        ", "ti", "tj", "R", "Cn", ew ? "O" : "", stype(p.out_dtype), "ldo", elem);
     s << "        ti = ni;\n        tj = nj;\n";
     s << "    }\n";
     if (!ew) {
@@ -701,6 +909,8 @@ std::string batch_kernel_source(const Plan& py, const Plan* pr, bool has_out, in
         o << in << (decl ? "coot_batch_task_d " : "") << "dt = b.tasks[dk];\n";
         o << in << (decl ? "i64 " : "") << "dR = b.items[dt.item].rows;\n";
         o << in << (decl ? "i64 " : "") << "dCn = b.items[dt.item].cols;\n";
+        o << in << (decl ? "int " : "") << "dlr = b.items[dt.item].lr;\n";
+        o << in << (decl ? "int " : "") << "dlc = b.items[dt.item].lc;\n";
         for (size_t j = 0; j < nr; ++j)
             o << in << (decl ? "const " + S(j) + "* " : std::string()) << "dL" << j << " = (const " << S(j)
               << "*)b.items[dt.item].leaf[" << read_slot[j] << "];\n";
@@ -718,42 +928,68 @@ std::string batch_kernel_source(const Plan& py, const Plan* pr, bool has_out, in
     s << "    int dk = b.order[si];\n";
     s << load_d("    ", true);
     s << "    i64 cR = dR, cCn = dCn;\n";
+    s << "    int clr = dlr, clc = dlc;\n";
     if (has_out) s << "    " << OS << "* cO = dO;\n";
-    s << "    int ctr = (int)((cR + 63) >> 6), crem = dt.t1 - dt.t0, cpart = dt.part;\n";
+    s << "    int ctr = (int)((cR + (1 << clr) - 1) >> clr), crem = dt.t1 - dt.t0, cpart = dt.part;\n";
     s << "    int ti = dt.t0 % ctr, tj = dt.t0 / ctr;\n";
     s << "    i64 qR = dR, qCn = dCn;\n";
+    s << "    int qlr = dlr, qlc = dlc;\n";
     for (size_t j = 0; j < nr; ++j) s << "    const " << S(j) << "* qL" << j << " = dL" << j << ";\n";
     s << "    dk = si + 1 < s_end ? b.order[si + 1] : dk;\n";
     s << load_d("    ", false);
     s << tile_regs(py, tp, "    ");
     if (pr) s << "    " << ACC << " acc;\n    acc.init();\n";
     // a straight read has the item's shape (ld = rows); a transposed one is cols x rows (ld = cols)
-    TileView v{"qR", "qCn", [](size_t j) { return "qL" + std::to_string(j); },
+    TileView v{"qR", "qCn", "qlr", "qlc", [](size_t j) { return "qL" + std::to_string(j); },
                [&](size_t j) { return std::string(py.reads[j].trans ? "qCn" : "qR"); }};
-    s << tile_prefetch(py, tp, "    ", "ti", "tj", v, LDF);
+    // one specialised tile body per tile class (coot_batch_tile_shape)
+    static const int classes[7][2] = {{6, 6}, {3, 9}, {4, 8}, {5, 7}, {8, 3}, {7, 4}, {6, 5}};
+    auto by_class = [&](const std::string& in, const std::string& lrv, const std::string& lcv,
+                        const std::function<std::string(const std::string&, int, int)>& body) {
+        std::ostringstream o;
+        o << in << "switch (" << lrv << " * 16 + " << lcv << ") {\n";
+        for (const auto& c : classes) {
+            o << in << "case " << c[0] * 16 + c[1] << ": {\n" << body(in + "    ", c[0], c[1]);
+            o << in << "    break;\n" << in << "}\n";
+        }
+        o << in << "default:\n" << in << "    break;\n" << in << "}\n";
+        return o.str();
+    };
+    auto prefetch = [&](const std::string& in, const std::string& a1, const std::string& a2) {
+        return by_class(in, "qlr", "qlc", [&](const std::string& i2, int lr, int lc) {
+            if (lr == 6 && lc == 6) return tile_prefetch_sq(py, tp, i2, a1, a2, v, LDF);
+            TileView w = v;
+            w.lr = std::to_string(lr);
+            w.lc = std::to_string(lc);
+            return tile_prefetch_gen(py, tp, i2, a1, a2, w, LDF);
+        });
+    };
+    s << prefetch("    ", "ti", "tj");
     s << "    for (;;) {\n";
     s << "        int ni = ti + 1, nj = tj, nsi = si;\n";
     s << "        if (ni >= ctr) { ni = 0; ++nj; }\n";
     s << "        if (crem <= 1) {\n";
     s << "            ++nsi;\n";
-    s << "            const int dtr = (int)((dR + 63) >> 6);\n";
+    s << "            const int dtr = (int)((dR + (1 << dlr) - 1) >> dlr);\n";
     s << "            ni = dt.t0 % dtr;\n            nj = dt.t0 / dtr;\n";
     s << "        }\n";
     s << "        const bool more = nsi < s_end;\n";
     s << "        if (more && nsi != si) {\n";
-    s << "            qR = dR;\n            qCn = dCn;\n";
+    s << "            qR = dR;\n            qCn = dCn;\n            qlr = dlr;\n            qlc = dlc;\n";
     for (size_t j = 0; j < nr; ++j) s << "            qL" << j << " = dL" << j << ";\n";
     s << "        }\n";
-    s << tile_stage(py, tp, "        ");
-    s << "        if (more)\n" << tile_prefetch(py, tp, "            ", "ni", "nj", v, LDF);
-    s << tile_compute(py, tp, "        ", "ti", "tj", "cR", "cCn", has_out ? "cO" : "", OS, "cR",
-                      [&](const std::string& args, const std::string& in) {
+    s << by_class("        ", "clr", "clc", [&](const std::string& i2, int lr, int lc) {
+        if (lr == 6 && lc == 6) return tile_stage_sq(py, tp, i2);
+        return tile_stage_gen(py, tp, i2, "cR", "cCn", "ti", "tj", std::to_string(lr), std::to_string(lc));
+    });
+    s << "        if (more) {\n" << prefetch("            ", "ni", "nj") << "        }\n";
+    auto elem = [&](const std::string& args, const std::string& in, const std::string& addr) {
         std::ostringstream o;
         o << in << "const " << ctype(rp) << " y = x_eval(" << args << ");\n";
         std::string yv = "y";
         if (has_out) {
             o << in << "const " << OS << " yo = " << narrow(out_dtype, rp, "y") << ";\n";
-            o << in << STF << "(po + lane, yo);\n";
+            o << in << STF << "(" << addr << ", yo);\n";
             if (out_dtype == COOT_F16) yv = "widen_f16(yo)";
             else if (out_dtype == COOT_BF16) yv = "widen_bf16(yo)";
             else yv = "yo";
@@ -770,6 +1006,12 @@ std::string batch_kernel_source(const Plan& py, const Plan* pr, bool has_out, in
                 o << in << "acc.add(r_eval(" << yv << "));\n";
         }
         return o.str();
+    };
+    s << by_class("        ", "clr", "clc", [&](const std::string& i2, int lr, int lc) {
+        if (lr == 6 && lc == 6)
+            return tile_compute_sq(py, tp, i2, "ti", "tj", "cR", "cCn", has_out ? "cO" : "", OS, "cR", elem);
+        return tile_compute_gen(py, tp, i2, "ti", "tj", "cR", "cCn", std::to_string(lr), std::to_string(lc),
+                                has_out ? "cO" : "", OS, "cR", elem);
     });
     s << "        if (nsi != si) {\n";
     if (pr) {
@@ -783,7 +1025,8 @@ std::string batch_kernel_source(const Plan& py, const Plan* pr, bool has_out, in
     s << "            if (!more) break;\n";
     s << "            cR = dR;\n            cCn = dCn;\n";
     if (has_out) s << "            cO = dO;\n";
-    s << "            ctr = (int)((cR + 63) >> 6);\n            crem = dt.t1 - dt.t0;\n            cpart = dt.part;\n";
+    s << "            clr = dlr;\n            clc = dlc;\n";
+    s << "            ctr = (int)((cR + (1 << clr) - 1) >> clr);\n            crem = dt.t1 - dt.t0;\n            cpart = dt.part;\n";
     s << "            dk = nsi + 1 < s_end ? b.order[nsi + 1] : dk;\n";
     s << load_d("            ", false);
     s << "        } else {\n            --crem;\n        }\n";

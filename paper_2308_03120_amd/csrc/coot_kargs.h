@@ -8,6 +8,65 @@
 
 #define COOT_MAX_READS 16
 
+#if defined(__HIPCC_RTC__) || defined(__HIP_DEVICE_COMPILE__) || defined(__HIP__)
+#define COOT_HD __host__ __device__ inline
+#else
+#define COOT_HD static inline
+#endif
+
+/* Tile shape of an R x Cn value for the tiled kernels: TR x TC = 2^lr x 2^lc
+ * with TR*TC <= 4096.  Square 64 x 64 when both sides reach 64; a thin value
+ * gets whole-height (or whole-width) tiles: TR = R rounded up to a power of
+ * two and TC = 4096/TR, or the mirror image capped at 2048 elements (so that
+ * the padded LDS tile, TR*(TC+1) elements, stays within 4160). */
+COOT_HD int coot_lg2ceil(long long v)
+{
+    return v <= 1 ? 0 : 64 - __builtin_clzll((unsigned long long)(v - 1));
+}
+
+COOT_HD void coot_tile_shape(long long R, long long Cn, int* lr, int* lc)
+{
+    const int r0 = coot_lg2ceil(R), c0 = coot_lg2ceil(Cn);
+    if (r0 >= 6 && c0 >= 6) {
+        *lr = 6;
+        *lc = 6;
+    } else if (r0 < 6) {
+        *lr = r0;
+        *lc = c0 < 12 - r0 ? c0 : 12 - r0;
+    } else {
+        const int cap = c0 == 0 ? 12 : 11 - c0;
+        *lc = c0;
+        *lr = r0 < cap ? r0 : cap;
+    }
+}
+
+/* LDS row stride of a 2^lr x 2^lc tile (conflict-free column reads) */
+COOT_HD int coot_tile_stride(int lr, int lc)
+{
+    return lr < 6 ? (1 << lc) + (64 >> lr) : (lc == 0 ? 1 : (1 << lc) + 1);
+}
+#define COOT_TILE_LDS 4160
+
+/* Tile shape of a batched item: one of seven classes, so that the batched
+ * kernel can hold a specialised body for each.  64 x 64 when both sides reach
+ * 64; otherwise the narrow side (rounded up to a power of two, at least 8)
+ * spans the tile and the long side fills the rest: 8/16/32 x 512/256/128 or
+ * 256/128/64 x 8/16/32. */
+COOT_HD void coot_batch_tile_shape(long long R, long long Cn, int* lr, int* lc)
+{
+    const int r0 = coot_lg2ceil(R), c0 = coot_lg2ceil(Cn);
+    if (r0 >= 6 && c0 >= 6) {
+        *lr = 6;
+        *lc = 6;
+    } else if (r0 <= c0) {
+        *lr = r0 < 3 ? 3 : r0;
+        *lc = 12 - *lr;
+    } else {
+        *lc = c0 < 3 ? 3 : c0;
+        *lr = 11 - *lc;
+    }
+}
+
 typedef struct coot_kargs {
     const void* leaf[COOT_MAX_READS];  /* distinct leaf reads (slot, transposed) */
     long long ld[COOT_MAX_READS];      /* leading dimension of each read's operand */
@@ -23,16 +82,17 @@ typedef struct coot_kargs {
     long long aux;
 } coot_kargs;
 
-/* batched evaluation: one descriptor per item; the items' 64x64 tiles are cut
- * into tasks of at most COOT_BATCH_CHUNK consecutive tiles (column-major tile
- * order within the item), and every block runs a list of tasks (a static
+/* batched evaluation: one descriptor per item; the items' tiles (shape from
+ * coot_tile_shape) are cut into tasks of at most COOT_BATCH_CHUNK consecutive
+ * tiles (column-major tile order within the item), and every block runs a list of tasks (a static
  * longest-first schedule computed on the host) */
 #define COOT_BATCH_CHUNK 4
 
 typedef struct coot_batch_item_d {
     long long rows, cols;              /* Y_i shape */
-    long long ntiles;                  /* 64x64 tiles of Y_i */
+    long long ntiles;                  /* tiles of Y_i */
     long long part0;                   /* partial slot of the item's first task */
+    int lr, lc;                        /* tile shape: 2^lr x 2^lc (coot_tile_shape) */
     void* out;
     const void* leaf[6];
 } coot_batch_item_d;

@@ -338,6 +338,8 @@ Plan make_plan(int red_op_in, int dim, const coot_expr* expr, const coot_operand
         else
             P.kind = K_RED_ROW;
     }
+    P.tile_gen = (P.kind == K_EW_TILED || P.kind == K_RED_TILED) && (P.rows < 64 || P.cols < 64);
+    if (P.tile_gen) coot_tile_shape(P.rows, P.cols, &P.tile_lr, &P.tile_lc);
     if (P.red_op >= 0 && (P.red_op == COOT_RED_ACCU || P.red_op == COOT_RED_SUM || P.red_op == COOT_RED_DOT) &&
         P.nodes[P.root].op == COOT_SCHUR) {
         P.product_form = true;

@@ -122,6 +122,40 @@ def test_transposed_reads(g):
         check_tree(trans(trans(x) % y) - x, [A, B])
 
 
+THIN = [(1, 5), (2, 9), (3, 70), (5, 1000), (12, 300), (31, 65), (33, 4100), (63, 129),
+        (5, 1), (9, 2), (70, 3), (1000, 5), (300, 12), (65, 31), (4100, 33), (129, 63), (2, 2), (7, 9)]
+
+
+@pytest.mark.parametrize("r,c", THIN)
+def test_thin_transposed_shapes(g, r, c):
+    """Thin values (fewer than 64 rows or columns) use shape-adaptive tiles:
+    whole short columns per step, or 64-element runs down long columns."""
+    A, B = mats_like(g, [(r, c), (c, r)], "f32")
+    x, y = leaves(2)
+    check_tree(trans(x) + 0.5 * y, [A, B])
+    check_tree(trans(trans(x) % y) - x, [A, B])
+
+
+def test_thin_transposed_views_and_dtypes(g):
+    """Thin tiles with padded leading dimensions, offsets, FP64 and 16-bit data."""
+    x, y = leaves(2)
+    for (r, c) in [(12, 300), (300, 12), (3, 2000), (2000, 3)]:
+        A, B = mats_like(g, [(r, c), (c, r)], "f32")
+        t = trans(x) % y - 2.5
+        em = oracle.evaluate(t.postfix(), [A, B], "emu")
+        for ldA, ldB, ldO, off in [(r + 3, c + 1, c + 5, 1), (r + 64, c, c + 17, 3)]:
+            dA, dB = dev(A, ld=ldA, offset=off), dev(B, ld=ldB)
+            O = empty(c, r, "f32", ld=ldO, offset=off)
+            coot.eval(t, [dA, dB], O)
+            torch.cuda.synchronize()
+            assert same(host(O), em), (r, c, ldA, ldB, ldO, off)
+        A, B = mats_like(g, [(r, c), (c, r)], "f64")
+        check_tree(trans(leaf(0)) / (1.0 + abs_(leaf(1))), [A, B])
+        for dt in ("bf16", "f16"):
+            A, B = mats_like(g, [(r, c), (c, r)], dt)
+            check_tree(trans(leaf(0)) + leaf(1) % leaf(1), [A, B])
+
+
 def test_transposed_reads_f64_and_16bit(g):
     A, B = mats_like(g, [(130, 70), (70, 130)], "f64")
     check_tree(trans(leaf(0)) / (1.0 + abs_(leaf(1))), [A, B])

@@ -146,6 +146,22 @@ def test_dim_reduction_of_transposed_tree(g):
     check_sel("max", t, [A, B])
 
 
+@pytest.mark.parametrize("r,c", [(2, 3000), (3000, 2), (12, 300), (300, 12), (1, 70), (70, 1), (63, 65), (5, 7)])
+def test_thin_transposed_reductions(g, r, c):
+    """Full reductions over thin transposed trees (shape-adaptive tiles): sums,
+    extrema and the linear index of the extremum."""
+    A, B = mat(g, (r, c), "f32"), mat(g, (c, r), "f32")
+    t = trans(leaf(0)) + 0.5 * leaf(1)
+    check_sum("accu", t, [A, B])
+    check_sum("accu", t % t, [A, B])
+    check_sel("index_max", t, [A, B])
+    check_sel("index_min", t, [A, B])
+    check_sel("max", t, [A, B])
+    A64, B64 = mat(g, (r, c), "f64"), mat(g, (c, r), "f64")
+    check_sum("accu", t, [A64, B64], tol=1e-13)
+    check_sel("index_max", t, [A64, B64])
+
+
 def test_dim_reduction_with_ld_view(g):
     A = mat(g, (300, 50), "f32")
     dA = dev(A, ld=333)
