@@ -182,7 +182,9 @@ BatchTrees plan_batch(const coot_batch* b)
     for (int s = 0; s < b->n_slots; ++s) need_square = need_square || par[s] == 3;
     for (int i = 0; i < b->n_items; ++i) {
         int64_t r = b->shapes[2 * i], c = b->shapes[2 * i + 1];
-        if (r < 0 || c < 0 || r > (1 << 30) || c > (1 << 30)) fail(COOT_ERR_SHAPE, "batch: item shape out of range");
+        // sides up to 2^22 keep every per-lane tile offset within 32 bits
+        if (r < 0 || c < 0 || r > (1 << 22) || c > (1 << 22))
+            fail(COOT_ERR_SHAPE, "batch: item sides must be at most 2^22");
         if (need_square && r != c) fail(COOT_ERR_SHAPE, "batch: a slot read both straight and transposed needs square items");
     }
     // plan the element function on canonical shapes (never vectors)

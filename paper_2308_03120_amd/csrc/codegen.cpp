@@ -499,15 +499,17 @@ static std::string tile_compute_sq(const Plan& p, const TilePlan& tp, const std:
 }
 
 // --- shape-adaptive tiles ---------------------------------------------------
-// Steps: wave w takes steps m = w*spw .. w*spw + spw - 1 (spw = steps per
-// wave).  Two orders walk the tile: Y order (rows along lanes: the value's
-// layout; straight reads, register-held transposed reads, the output) and A
-// order (columns along lanes: an operand read transposed and staged through
-// LDS).  For an order whose lane dimension is at most 64 long, a step covers
-// 64/T whole lines; otherwise a step covers 64 elements of one line and
-// consecutive steps move down the line, then to the next one.  Walkers keep
-// the step origin (row, column) and one running pointer per read, advanced
-// by scalar adds.
+// Steps m = w + 4*kk (kk = 0..15, m < steps of the tile).  Two orders walk the
+// tile: Y order (rows along lanes: the value's layout; straight reads,
+// register-held transposed reads, the output) and A order (columns along
+// lanes: an operand read transposed and staged through LDS).  For an order
+// whose lane dimension is at most 64 long, a step covers 64/T whole lines;
+// otherwise a step covers 64 elements of one line, and the step four later
+// lies 256 elements further down, carrying into the next lines.  Walkers
+// keep the step origin (row, column) and one running pointer per read,
+// advanced by scalar arithmetic.  With off32 the per-lane part of an address
+// is a 32-bit byte offset (the host checks that it fits), so loads take a
+// scalar base.
 static std::string tile_lanes(const std::string& in, const std::string& lr, const std::string& lc, const std::string& rr,
                               const std::string& cc)
 {
@@ -517,37 +519,37 @@ static std::string tile_lanes(const std::string& in, const std::string& lr, cons
     o << in << "const int aj = " << lc << " <= 6 ? (lane & ((1 << " << lc << ") - 1)) : lane;\n";
     o << in << "const int ai = " << lc << " <= 6 ? (lane >> " << lc << ") : 0;\n";
     o << in << "const int nst = " << lr << " + " << lc << " >= 6 ? 1 << (" << lr << " + " << lc << " - 6) : 1;\n";
-    o << in << "const int spw = nst >= 4 ? nst >> 2 : 1, m0 = w * spw;\n";
     o << in << "const bool lin = lane < (1 << (" << lr << " + " << lc << "));\n";
     o << in << "const bool yok = lin && (" << lr << " > 6 || yi < " << rr << ");\n";
     o << in << "const bool aok = lin && (" << lc << " > 6 || aj < " << cc << ");\n";
-    o << in << "int ysr = " << lr << " <= 6 ? 0 : (m0 & ((1 << (" << lr << " - 6)) - 1)) << 6;\n";
-    o << in << "int ysc = " << lr << " <= 6 ? m0 << (6 - " << lr << ") : m0 >> (" << lr << " - 6);\n";
-    o << in << "int asc = " << lc << " <= 6 ? 0 : (m0 & ((1 << (" << lc << " - 6)) - 1)) << 6;\n";
-    o << in << "int asr = " << lc << " <= 6 ? m0 << (6 - " << lc << ") : m0 >> (" << lc << " - 6);\n";
+    o << in << "int ysr = " << lr << " <= 6 ? 0 : (w & ((1 << (" << lr << " - 6)) - 1)) << 6;\n";
+    o << in << "int ysc = " << lr << " <= 6 ? w << (6 - " << lr << ") : w >> (" << lr << " - 6);\n";
+    o << in << "int asc = " << lc << " <= 6 ? 0 : (w & ((1 << (" << lc << " - 6)) - 1)) << 6;\n";
+    o << in << "int asr = " << lc << " <= 6 ? w << (6 - " << lc << ") : w >> (" << lc << " - 6);\n";
     return o.str();
 }
 
-// advance the Y walker (ptrs: running pointers with their leading dimension
-// and whether they are read transposed) or the A walker
+// Advance the Y walker by four steps.  ptrs: running pointers with their
+// leading dimension and whether they are read transposed.
 static std::string walk_y(const std::string& in, const std::string& lr,
                           const std::vector<std::pair<std::string, std::pair<std::string, bool>>>& ptrs)
 {
     std::ostringstream o;
     o << in << "if (" << lr << " <= 6) {\n";
-    o << in << "    ysc += 64 >> " << lr << ";\n";
+    o << in << "    ysc += 256 >> " << lr << ";\n";
     for (auto& p : ptrs)
-        o << in << "    " << p.first << " += " << (p.second.second ? "(i64)(64 >> " + lr + ")" : "(i64)(64 >> " + lr + ") * " + p.second.first)
-          << ";\n";
+        o << in << "    " << p.first << " += "
+          << (p.second.second ? "(i64)(256 >> " + lr + ")" : "(i64)(256 >> " + lr + ") * " + p.second.first) << ";\n";
     o << in << "} else {\n";
-    o << in << "    ysr += 64;\n";
-    for (auto& p : ptrs) o << in << "    " << p.first << " += " << (p.second.second ? "64 * " + p.second.first : "64") << ";\n";
-    o << in << "    if (ysr == (1 << " << lr << ")) {\n";
-    o << in << "        ysr = 0;\n" << in << "        ++ysc;\n";
+    o << in << "    const int cy = (ysr + 256) >> " << lr << ";\n";
+    o << in << "    ysr = (ysr + 256) & ((1 << " << lr << ") - 1);\n";
+    o << in << "    ysc += cy;\n";
     for (auto& p : ptrs)
-        o << in << "        " << p.first << " += "
-          << (p.second.second ? "1 - ((i64)1 << " + lr + ") * " + p.second.first : p.second.first + " - (1 << " + lr + ")") << ";\n";
-    o << in << "    }\n" << in << "}\n";
+        o << in << "    " << p.first << " += "
+          << (p.second.second ? "(i64)cy + (i64)(256 - (cy << " + lr + ")) * " + p.second.first
+                              : "(i64)(256 - (cy << " + lr + ")) + (i64)cy * " + p.second.first)
+          << ";\n";
+    o << in << "}\n";
     return o.str();
 }
 
@@ -556,24 +558,33 @@ static std::string walk_a(const std::string& in, const std::string& lc,
 {
     std::ostringstream o;
     o << in << "if (" << lc << " <= 6) {\n";
-    o << in << "    asr += 64 >> " << lc << ";\n";
-    for (auto& p : ptrs) o << in << "    " << p.first << " += (i64)(64 >> " << lc << ") * " << p.second << ";\n";
+    o << in << "    asr += 256 >> " << lc << ";\n";
+    for (auto& p : ptrs) o << in << "    " << p.first << " += (i64)(256 >> " << lc << ") * " << p.second << ";\n";
     o << in << "} else {\n";
-    o << in << "    asc += 64;\n";
-    for (auto& p : ptrs) o << in << "    " << p.first << " += 64;\n";
-    o << in << "    if (asc == (1 << " << lc << ")) {\n";
-    o << in << "        asc = 0;\n" << in << "        ++asr;\n";
-    for (auto& p : ptrs) o << in << "        " << p.first << " += " << p.second << " - (1 << " << lc << ");\n";
-    o << in << "    }\n" << in << "}\n";
+    o << in << "    const int ca = (asc + 256) >> " << lc << ";\n";
+    o << in << "    asc = (asc + 256) & ((1 << " << lc << ") - 1);\n";
+    o << in << "    asr += ca;\n";
+    for (auto& p : ptrs)
+        o << in << "    " << p.first << " += (i64)(256 - (ca << " << lc << ")) + (i64)ca * " << p.second << ";\n";
+    o << in << "}\n";
     return o.str();
 }
 
+// address of a running pointer plus its per-lane offset (zero when invalid)
+static std::string lane_addr(const std::string& ptr, const std::string& cond, const std::string& off, bool off32)
+{
+    if (off32) return "at(" + ptr + ", " + cond + " ? " + off + " : 0u)";
+    return ptr + " + (" + cond + " ? " + off + " : 0)";
+}
+
 static std::string tile_prefetch_gen(const Plan& p, const TilePlan& tp, const std::string& in, const std::string& ti,
-                                     const std::string& tj, const TileView& v, const std::string& ldf)
+                                     const std::string& tj, const TileView& v, const std::string& ldf, bool off32)
 {
     std::ostringstream o;
     o << in << "{\n";
     const std::string i2 = in + "    ";
+    const std::string OT = off32 ? "const u32 " : "const i64 ";
+    const std::string cast = off32 ? "(u32)" : "(i64)";
     o << i2 << "const i64 pi0 = (i64)(" << ti << ") << " << v.lr << ", pj0 = (i64)(" << tj << ") << " << v.lc << ";\n";
     o << i2 << "const int prr = (int)(" << v.R << " - pi0 < (1 << " << v.lr << ") ? " << v.R << " - pi0 : (1 << " << v.lr
       << "));\n";
@@ -586,21 +597,21 @@ static std::string tile_prefetch_gen(const Plan& p, const TilePlan& tp, const st
         const std::string J = std::to_string(j), L = v.L(j), ld = v.ld(j), S = stype(p.reads[j].dtype);
         if (tp.in_lds[j]) {
             o << i2 << "const " << S << "* a" << J << " = " << L << " + ((pj0 + asc) + (pi0 + asr) * " << ld << ");\n";
-            o << i2 << "const i64 v" << J << " = aj + (i64)ai * " << ld << ";\n";
+            o << i2 << OT << "v" << J << " = " << cast << "(aj + (i64)ai * " << ld << ");\n";
             ap.push_back({"a" + J, ld});
         } else if (p.reads[j].trans) {
             o << i2 << "const " << S << "* a" << J << " = " << L << " + ((pj0 + ysc) + (pi0 + ysr) * " << ld << ");\n";
-            o << i2 << "const i64 v" << J << " = yj + (i64)yi * " << ld << ";\n";
+            o << i2 << OT << "v" << J << " = " << cast << "(yj + (i64)yi * " << ld << ");\n";
             yp.push_back({"a" + J, {ld, true}});
         } else {
             o << i2 << "const " << S << "* a" << J << " = " << L << " + ((pi0 + ysr) + (pj0 + ysc) * " << ld << ");\n";
-            o << i2 << "const i64 v" << J << " = yi + (i64)yj * " << ld << ";\n";
+            o << i2 << OT << "v" << J << " = " << cast << "(yi + (i64)yj * " << ld << ");\n";
             yp.push_back({"a" + J, {ld, false}});
         }
     }
     o << in << "#pragma unroll\n" << i2 << "for (int kk = 0; kk < 16; ++kk) {\n";
     const std::string i3 = i2 + "    ";
-    o << i3 << "if (kk < spw && m0 < nst) {\n";
+    o << i3 << "if (w + 4 * kk < nst) {\n";
     const std::string i4 = i3 + "    ";
     if (!yp.empty()) {
         o << i4 << "const bool yu = ysr < prr && ysc < pcc;\n";
@@ -613,10 +624,10 @@ static std::string tile_prefetch_gen(const Plan& p, const TilePlan& tp, const st
     for (size_t j = 0; j < p.reads.size(); ++j) {
         const std::string J = std::to_string(j), C = ctype(p.reads[j].dtype == COOT_F64 ? 64 : 32);
         if (tp.in_lds[j])
-            o << i4 << "pt" << J << "[kk] = au ? " << widen(p.reads[j].dtype, ldf + "(a" + J + " + (av ? v" + J + " : 0))")
+            o << i4 << "pt" << J << "[kk] = au ? " << widen(p.reads[j].dtype, ldf + "(" + lane_addr("a" + J, "av", "v" + J, off32) + ")")
               << " : (" << C << ")0;\n";
         else
-            o << i4 << "pr" << J << "[kk] = yu ? " << widen(p.reads[j].dtype, ldf + "(a" + J + " + (yv ? v" + J + " : 0))")
+            o << i4 << "pr" << J << "[kk] = yu ? " << widen(p.reads[j].dtype, ldf + "(" + lane_addr("a" + J, "yv", "v" + J, off32) + ")")
               << " : (" << C << ")0;\n";
     }
     if (!yp.empty()) o << walk_y(i4, v.lr, yp);
@@ -641,7 +652,7 @@ static std::string tile_stage_gen(const Plan& p, const TilePlan& tp, const std::
         s << tile_lanes(i2, lr, lc, "prr", "pcc");
         s << i2 << "const int sst = coot_tile_stride(" << lr << ", " << lc << ");\n";
         s << in << "#pragma unroll\n" << i2 << "for (int kk = 0; kk < 16; ++kk) {\n";
-        s << i2 << "    if (kk < spw && m0 < nst) {\n";
+        s << i2 << "    if (w + 4 * kk < nst) {\n";
         s << i2 << "        if (lin) {\n";
         for (size_t j = 0; j < p.reads.size(); ++j)
             if (tp.in_lds[j]) s << i2 << "            T" << j << "[(asr + ai) * sst + asc + aj] = pt" << j << "[kk];\n";
@@ -660,7 +671,7 @@ template <class F>
 static std::string tile_compute_gen(const Plan& p, const TilePlan& tp, const std::string& in, const std::string& ti,
                                     const std::string& tj, const std::string& R, const std::string& Cn,
                                     const std::string& lr, const std::string& lc, const std::string& out,
-                                    const std::string& OT, const std::string& ldo, F per_elem)
+                                    const std::string& OT, const std::string& ldo, bool off32, F per_elem)
 {
     std::ostringstream s;
     s << in << "{\n";
@@ -673,11 +684,11 @@ static std::string tile_compute_gen(const Plan& p, const TilePlan& tp, const std
     std::vector<std::pair<std::string, std::pair<std::string, bool>>> yp;
     if (!out.empty()) {
         s << i2 << OT << "* po = " << out << " + ((i0 + ysr) + (j0 + ysc) * " << ldo << ");\n";
-        s << i2 << "const i64 vo = yi + (i64)yj * " << ldo << ";\n";
+        s << i2 << (off32 ? "const u32 vo = (u32)" : "const i64 vo = (i64)") << "(yi + (i64)yj * " << ldo << ");\n";
         yp.push_back({"po", {ldo, false}});
     }
     s << in << "#pragma unroll\n" << i2 << "for (int kk = 0; kk < 16; ++kk) {\n";
-    s << i2 << "    if (kk < spw && m0 < nst) {\n";
+    s << i2 << "    if (w + 4 * kk < nst) {\n";
     const std::string i4 = i2 + "        ";
     s << i4 << "if (ysr < rr && ysc < cc && yok && (" << lr << " <= 6 ? yj < cc - ysc : yi < rr - ysr)) {\n";
     s << i4 << "    const i64 ig = i0 + ysr + yi, jg = j0 + ysc + yj;\n";
@@ -686,7 +697,7 @@ static std::string tile_compute_gen(const Plan& p, const TilePlan& tp, const std
         if (j) args += ", ";
         args += tp.in_lds[j] ? "T" + std::to_string(j) + "[(ysr + yi) * sst + ysc + yj]" : "cr" + std::to_string(j) + "[kk]";
     }
-    s << per_elem(args, i4 + "    ", "(po + vo)");
+    s << per_elem(args, i4 + "    ", off32 ? "atw(po, vo)" : "(po + vo)");
     s << i4 << "}\n";
     s << walk_y(i4, lr, yp);
     s << i2 << "    }\n" << i2 << "}\n" << in << "}\n";
@@ -723,7 +734,7 @@ static std::string emit_tiled(const Plan& p, const std::string& name)
     TileView v{"R", "Cn", "lr", "lc", [](size_t j) { return "L" + std::to_string(j); },
                [](size_t j) { return "ld" + std::to_string(j); }};
     auto prefetch = [&](const std::string& in, const std::string& a, const std::string& b) {
-        return gen ? tile_prefetch_gen(p, tp, in, a, b, v, "ldnt") : tile_prefetch_sq(p, tp, in, a, b, v, "ldnt");
+        return gen ? tile_prefetch_gen(p, tp, in, a, b, v, "ldnt", p.tile_off32) : tile_prefetch_sq(p, tp, in, a, b, v, "ldnt");
     };
     auto elem = [&](const std::string& args, const std::string& in, const std::string& addr) {
         if (ew)
@@ -739,7 +750,7 @@ static std::string emit_tiled(const Plan& p, const std::string& name)
     s << "        if (nj < tc)\n" << prefetch("            ", "ni", "nj");
     if (gen)
         s << tile_compute_gen(p, tp, "        ", "ti", "tj", "R", "Cn", "lr", "lc", ew ? "O" : "", stype(p.out_dtype), "ldo",
-                              elem);
+                              p.tile_off32, elem);
     else
         s << tile_compute_sq(p, tp, "        ", "ti", "tj", "R", "Cn", ew ? "O" : "", stype(p.out_dtype), "ldo", elem);
     s << "        ti = ni;\n        tj = nj;\n";
@@ -961,7 +972,7 @@ std::string batch_kernel_source(const Plan& py, const Plan* pr, bool has_out, in
             TileView w = v;
             w.lr = std::to_string(lr);
             w.lc = std::to_string(lc);
-            return tile_prefetch_gen(py, tp, i2, a1, a2, w, LDF);
+            return tile_prefetch_gen(py, tp, i2, a1, a2, w, LDF, true);
         });
     };
     s << prefetch("    ", "ti", "tj");
@@ -1011,7 +1022,7 @@ std::string batch_kernel_source(const Plan& py, const Plan* pr, bool has_out, in
         if (lr == 6 && lc == 6)
             return tile_compute_sq(py, tp, i2, "ti", "tj", "cR", "cCn", has_out ? "cO" : "", OS, "cR", elem);
         return tile_compute_gen(py, tp, i2, "ti", "tj", "cR", "cCn", std::to_string(lr), std::to_string(lc),
-                                has_out ? "cO" : "", OS, "cR", elem);
+                                has_out ? "cO" : "", OS, "cR", true, elem);
     });
     s << "        if (nsi != si) {\n";
     if (pr) {

@@ -135,6 +135,20 @@ CD void stnt(S* p, S v)
 #endif
 }
 
+/* element at a 32-bit element offset from a base (the byte offset is formed
+ * in 32 bits, so the access takes a scalar base and a vector offset) */
+template <class S>
+CD const S* at(const S* base, u32 off)
+{
+    return (const S*)((const char*)base + off * (u32)sizeof(S));
+}
+
+template <class S>
+CD S* atw(S* base, u32 off)
+{
+    return (S*)((char*)base + off * (u32)sizeof(S));
+}
+
 /* single-element load / store through the caches */
 template <class S>
 CD S ldpl(const S* p)

@@ -67,6 +67,7 @@ struct Plan {
     bool temp_needed;         // dim reduction of a tiled tree: materialise first
     bool tile_gen = false;    // tiled kind on a thin value: shape-adaptive tiles
     int tile_lr = 6, tile_lc = 6;  // tile shape 2^lr x 2^lc of the tiled kinds
+    bool tile_off32 = false;  // per-lane tile offsets fit in 32-bit byte offsets
     std::string body_sig;     // canonical description of the element function
 };
 

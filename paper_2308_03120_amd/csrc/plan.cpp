@@ -339,7 +339,18 @@ Plan make_plan(int red_op_in, int dim, const coot_expr* expr, const coot_operand
             P.kind = K_RED_ROW;
     }
     P.tile_gen = (P.kind == K_EW_TILED || P.kind == K_RED_TILED) && (P.rows < 64 || P.cols < 64);
-    if (P.tile_gen) coot_tile_shape(P.rows, P.cols, &P.tile_lr, &P.tile_lc);
+    if (P.tile_gen) {
+        coot_tile_shape(P.rows, P.cols, &P.tile_lr, &P.tile_lc);
+        // per-lane offset bounds (elements of at most 8 bytes) of the tile
+        // mappings: value order k = lines per step beyond the first, a
+        // transposed read either order
+        const int lr = P.tile_lr, lc = P.tile_lc;
+        const int64_t ky = lr <= 6 ? (64 >> lr) : 0;
+        const int64_t kt = std::max<int64_t>(lc <= 6 ? (64 >> lc) : 0, lr <= 6 ? (1 << lr) : 64);
+        int64_t bound = P.red_op < 0 ? 64 + ky * out->ld : 64;
+        for (const Read& r : P.reads) bound = std::max(bound, 64 + (r.trans ? kt : ky) * r.ld);
+        P.tile_off32 = bound < (int64_t(1) << 29);
+    }
     if (P.red_op >= 0 && (P.red_op == COOT_RED_ACCU || P.red_op == COOT_RED_SUM || P.red_op == COOT_RED_DOT) &&
         P.nodes[P.root].op == COOT_SCHUR) {
         P.product_form = true;
