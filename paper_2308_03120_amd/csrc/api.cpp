@@ -248,11 +248,15 @@ static Geometry geometry(const Plan& p, const LaunchCfg& c)
         const int64_t units = p.rows / p.ve + p.rows % p.ve;
         int64_t target = (int64_t)g_state.cus * 1024;
         int64_t q = std::max<int64_t>(1, ceil_div(target, std::max<int64_t>(1, units)));
-        q = std::min<int64_t>(q, std::min<int64_t>(std::max<int64_t>(1, p.cols), 65536));
+        // every split walks at least 64 columns (partials stay a small
+        // fraction of the data)
+        q = std::min<int64_t>(q, std::min<int64_t>(std::max<int64_t>(1, p.cols / 64), 65536));
         G.splits = q;
         G.grid = std::max<int64_t>(1, std::min(ceil_div(units * q, c.block), cap));
         if (q > 1) {
-            G.comb_grid = std::min<int64_t>(p.rows, (int64_t)g_state.cus * 16);
+            // the combine kernel takes a block per row from 256 splits on, else a thread per row
+            G.comb_grid = q >= 256 ? std::min<int64_t>(p.rows, (int64_t)g_state.cus * 16)
+                                   : std::max<int64_t>(1, std::min<int64_t>(ceil_div(p.rows, 256), (int64_t)g_state.cus * 16));
             G.part_bytes = (size_t)(p.rows * q) * 16;
         }
         break;

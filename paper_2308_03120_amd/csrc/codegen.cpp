@@ -220,6 +220,27 @@ static std::string combine_and_write(const Plan& p, const std::string& first, co
     return s.str();
 }
 
+// the same, done by the calling thread alone
+static std::string combine_and_write_seq(const Plan& p, const std::string& first, const std::string& count,
+                                         const std::string& stride, const std::string& j)
+{
+    std::ostringstream s;
+    if (red_is_sum(p.red_op)) {
+        s << "{ const double v = combine_sums_seq((const double*)a.part, " << first << ", " << count << ", " << stride
+          << "); " << put_value(p, j, p.red_op == COOT_RED_NORM2 ? "__builtin_sqrt(v)" : "v") << " }";
+    } else {
+        const char* mx = red_is_max(p.red_op) ? "true" : "false";
+        s << "{ const AccI<double, " << mx << "> cr = combine_idx_seq<" << mx << ">((const double*)a.part, " << first
+          << ", " << count << ", " << stride << "); ";
+        if (p.red_op == COOT_RED_INDEX_MIN || p.red_op == COOT_RED_INDEX_MAX)
+            s << "put_u64(a.res, " << j << ", cr.i);";
+        else
+            s << put_value(p, j, "(cr.i < 0 ? __builtin_nan(\"\") : cr.v)");
+        s << " }";
+    }
+    return s.str();
+}
+
 // --- common declarations ----------------------------------------------------
 static std::string decl_reads(const Plan& p, bool restrict_ok)
 {
@@ -850,7 +871,7 @@ static std::string emit_row(const Plan& p, const std::string& name)
         s << "        if (g < RV) {\n";
         s << "            " << acc_type(p) << " av[" << VE << "];\n";
         s << "#pragma unroll\n            for (int k = 0; k < " << VE << "; ++k) av[k].init();\n";
-        s << "            for (i64 c = q; c < a.cols; c += a.splits) {\n";
+        s << "#pragma unroll 8\n            for (i64 c = q; c < a.cols; c += a.splits) {\n";
         for (size_t j = 0; j < p.reads.size(); ++j)
             s << "                " << stype(p.reads[j].dtype) << " r" << j << "[" << VE << "];\n                ldv<"
               << stype(p.reads[j].dtype) << ", " << VE << ">(L" << j << ", g * " << VE << " + c * ld" << j << ", r" << j
@@ -874,21 +895,26 @@ static std::string emit_row(const Plan& p, const std::string& name)
     s << "        if (a.splits == 1) { " << write_direct(p, "r") << " } else { " << put_partial(p, "q * a.rows + r")
       << " }\n";
     s << "    }\n}\n";
-    // combine: one block per row, splits in order
+    // combine, splits in order: a block per row when the splits are many, a
+    // thread per row otherwise
     s << "extern \"C\" __global__ void __launch_bounds__(256) " << name << "_comb(const coot_kargs a)\n{\n";
-    s << "    for (i64 r = blockIdx.x; r < a.rows; r += gridDim.x) {\n        "
-      << combine_and_write(p, "r", "a.splits", "a.rows", "r") << "\n    }\n}\n";
+    s << "    if (a.splits >= 256) {\n";
+    s << "        for (i64 r = blockIdx.x; r < a.rows; r += gridDim.x) {\n            "
+      << combine_and_write(p, "r", "a.splits", "a.rows", "r") << "\n        }\n";
+    s << "        return;\n    }\n";
+    s << "    for (i64 r = (i64)blockIdx.x * blockDim.x + threadIdx.x; r < a.rows; r += (i64)gridDim.x * blockDim.x) {\n        "
+      << combine_and_write_seq(p, "r", "a.splits", "a.rows", "r") << "\n    }\n}\n";
     return s.str();
 }
 
-// --- batched kernel: one persistent launch over many items ---------------------
-// Every block owns a list of whole items (a longest-first schedule computed on
-// the host, so the blocks finish together).  Per item, the block walks the
-// 64x64 tiles of Y in order, evaluates the tree (reads transposed through
+// --- batched kernels: one persistent tile pass over many items -----------------
+// Every block runs a list of tasks (at most four consecutive tiles of one item;
+// a longest-first schedule computed on the host, so the blocks finish
+// together).  Per tile the block evaluates the tree (reads transposed through
 // LDS), stores Y and folds the reduction tree of Y into compensated
-// accumulators; one block reduction per item gives r_i.  No item is shared
-// between blocks, so there is no cross-block traffic and r_i does not depend
-// on timing.
+// accumulators; one block reduction per task gives a partial of r_i, and the
+// _comb kernel adds an item's partials in task order.  Tasks depend only on
+// item shapes, so r_i does not depend on the grid or on timing.
 std::string batch_kernel_source(const Plan& py, const Plan* pr, bool has_out, int out_dtype, int red_dtype,
                                 const std::vector<int>& read_slot, std::string* name_out)
 {

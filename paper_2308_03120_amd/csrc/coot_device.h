@@ -388,6 +388,34 @@ CD AccI<double, MAX> combine_idx(const double* part, i64 first, i64 count, i64 s
     return block_reduce(a, lds_id);
 }
 
+/* the same combines done by one thread, partials in order */
+CD double combine_sums_seq(const double* part, i64 first, i64 count, i64 stride)
+{
+    AccKD a;
+    a.init();
+    for (i64 t = 0; t < count; ++t) {
+        const double* p = part + 2 * (first + t * stride);
+        a.add(p[0]);
+        a.add(p[1]);
+    }
+    return a.s + a.c;
+}
+
+template <bool MAX>
+CD AccI<double, MAX> combine_idx_seq(const double* part, i64 first, i64 count, i64 stride)
+{
+    AccI<double, MAX> a;
+    a.init();
+    for (i64 t = 0; t < count; ++t) {
+        const double* p = part + 2 * (first + t * stride);
+        AccI<double, MAX> o;
+        o.v = p[0];
+        o.i = __builtin_bit_cast(i64, p[1]);
+        a.merge(o);
+    }
+    return a;
+}
+
 /* write a reduction value / index to the output buffer */
 CD void put_f32(void* out, i64 j, double v) { ((float*)out)[j] = (float)v; }
 CD void put_f64(void* out, i64 j, double v) { ((double*)out)[j] = v; }

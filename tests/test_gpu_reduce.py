@@ -162,6 +162,18 @@ def test_thin_transposed_reductions(g, r, c):
     check_sel("index_max", t, [A64, B64])
 
 
+@pytest.mark.parametrize("shape", [(524288, 4), (1000, 5000), (3, 100000), (4097, 17), (8, 524288), (300, 200000)])
+def test_row_reductions_narrow_and_split(g, shape):
+    """Per-row reductions: narrow rows in one pass; few long rows split over
+    column ranges, the splits combined per row in order by one thread."""
+    A = mat(g, shape, "f32")
+    check_sum("sum", X, [A], dim=1)
+    check_sel("index_max", X, [A], 1)
+    check_sel("min", X, [A], 1)
+    D = mat(g, shape, "f64")
+    check_sum("sum", X % X, [D], dim=1, tol=1e-13)
+
+
 def test_dim_reduction_with_ld_view(g):
     A = mat(g, (300, 50), "f32")
     dA = dev(A, ld=333)
