@@ -102,10 +102,12 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--unfused-steps", type=int, default=5)
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--workload", default="scale", choices=["scale", "costmodel", "batched", "precision"],
+    ap.add_argument("--workload", default="scale",
+                    choices=["scale", "costmodel", "batched", "precision", "tiled", "small"],
                     help="scale (default): the 2^28-element FP32/FP64 calls; costmodel: learned launch "
                          "configuration over 6,000 random trees; batched: 10,000 matrices in one launch; "
-                         "precision: 16384^2 BF16/FP16 sums and dots")
+                         "precision: 16384^2 BF16/FP16 sums and dots; tiled: transposed reads (64x64 and "
+                         "shape-adaptive tiles); small: the 1000x1000 FP32 calls, warm and cold")
     ap.add_argument("--out-dir", default=os.path.join(ROOT, "gpurun_out"),
                     help="where the cost-model workload writes its corpus table and weights")
     ap.add_argument("--trees", type=int, default=6000)
@@ -145,6 +147,10 @@ def main():
         return batched_workload(args, np, torch, synth, coot)
     if args.workload == "precision":
         return precision_workload(args, np, torch, synth, coot)
+    if args.workload == "tiled":
+        return tiled_workload(args, np, torch, synth, coot)
+    if args.workload == "small":
+        return small_workload(args, np, torch, synth, coot)
     steps = []
     bufs = []
     for dt in ("f32", "f64"):
@@ -420,15 +426,7 @@ def precision_workload(args, np, torch, synth, coot):
         torch.cuda.synchronize()
         for name, fn, nb in calls:
             for pw in (False, True):
-                ts = []
-                for _ in range(21):
-                    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-                    a.record()
-                    fn(pw)
-                    b.record()
-                    torch.cuda.synchronize()
-                    ts.append(a.elapsed_time(b))
-                us = sorted(ts)[10] * 1e3  # median
+                us = event_stats(torch, lambda: fn(pw))[0]
                 res[f"{name}_{dt}_{'pairwise' if pw else 'kahan'}"] = {
                     "us": round(us, 2), "GBps": round(nb * A.numel() / (us * 1e-6) / 1e9, 1)}
         del A, B
@@ -438,6 +436,100 @@ def precision_workload(args, np, torch, synth, coot):
            "data": "synthetic: |x| = exp(3z), z~N(0,1) clipped to [1e-4, 1e4], random signs, 16384^2",
            "per_call": res}
     print(json.dumps(out), flush=True)
+
+
+def event_stats(torch, fn, reps=21, between=None):
+    """median, min and p90 in microseconds of single-call HIP-event timings.  A
+    short spin on the GPU (no memory traffic) is queued before the start event,
+    so the host's preparation of the call overlaps it and the interval is the
+    device's time for the call."""
+    fn()
+    torch.cuda.synchronize()
+    ts = []
+    for _ in range(reps):
+        if between is not None:
+            between()
+        torch.cuda._sleep(200000)
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        fn()
+        b.record()
+        torch.cuda.synchronize()
+        ts.append(a.elapsed_time(b) * 1e3)
+    ts.sort()
+    return ts[len(ts) // 2], ts[0], ts[int(0.9 * (len(ts) - 1))]
+
+
+def tiled_workload(args, np, torch, synth, coot):
+    """Transposed reads: Y = trans(A) + 0.5*B and accu(trans(A) % B) on square and thin values."""
+    x, y = synth.leaves(2)
+    res = {}
+    cases = (("square_16384x16384_f32", 16384, 16384, torch.float32),
+             ("square_16384x8192_f64", 16384, 8192, torch.float64),
+             ("thin_2x67108864_f32", 2, 1 << 26, torch.float32),
+             ("thin_8388608x12_f32", 1 << 23, 12, torch.float32))
+    for name, r, c, tdt in cases:
+        # Y is r x c; A is c x r (read transposed), B is r x c
+        A = torch.rand(r, c, dtype=tdt, device="cuda").t()   # column-major c x r
+        B = torch.rand(c, r, dtype=tdt, device="cuda").t()   # column-major r x c
+        Y = torch.empty(c, r, dtype=tdt, device="cuda").t()
+        es = A.element_size()
+        for call, fn, bpe in (("add", lambda: coot.eval(synth.trans(x) + 0.5 * y, [A, B], Y), 3),
+                              ("accu", lambda: coot.reduce("accu", synth.trans(x) % y, [A, B]), 2)):
+            med, mn, p90 = event_stats(torch, fn)
+            gbs = bpe * es * r * c / (med * 1e-6) / 1e9
+            res[f"{call}_{name}"] = {"us_median": round(med, 1), "us_min": round(mn, 1), "us_p90": round(p90, 1),
+                                     "GBps": round(gbs, 1), "frac_of_peak": round(gbs / PEAK_GBS, 4)}
+        del A, B, Y
+        torch.cuda.empty_cache()
+    gb = [v["GBps"] for v in res.values()]
+    print(json.dumps({"metric": "transposed-read kernels, effective GB/s", "value": min(gb),
+                      "unit": "GB/s (slowest case)", "n_gpus": 1, "higher_is_better": True, "dtype": "f32,f64",
+                      "data": "synthetic: torch.rand on the device", "per_call": res}), flush=True)
+
+
+def small_workload(args, np, torch, synth, coot):
+    """The 1000 x 1000 FP32 calls: device time (events; warm = inputs in the 256 MB
+    last-level cache, cold = a 512 MiB write between calls) and the paper-style host
+    wall clock around call + synchronise (the host's preparation included); fused
+    and unfused."""
+    mats = synth.cfg1_inputs()
+    names = "ABCD"
+    dev = [torch.from_numpy(np.ascontiguousarray(mats[k].data.T)).cuda().t() for k in names]
+    t = synth.cfg1_trees()
+    Y = torch.empty(1000, 1000, device="cuda").t()
+    scratch = torch.empty(1 << 27, device="cuda")
+
+    def flush():
+        scratch.fill_(1.0)
+
+    calls = (("Y", lambda u: coot.eval(t["Y"], dev, Y, unfused=u), 20),
+             ("accu_AB", lambda u: coot.reduce("accu", t["accu_AB"], dev, unfused=u), 8),
+             ("sum_A_dim0", lambda u: coot.reduce("sum", t["sumA"], dev, dim=0, unfused=u), 4),
+             ("index_max_absB", lambda u: coot.reduce("index_max", t["absB"], dev, unfused=u), 4))
+    res = {}
+    for name, fn, bpe in calls:
+        for u in (False, True):
+            warm = event_stats(torch, lambda: fn(u))
+            cold = event_stats(torch, lambda: fn(u), between=flush)
+            fn(u)
+            torch.cuda.synchronize()
+            walls = []
+            for _ in range(21):
+                t0 = time.perf_counter()
+                fn(u)
+                torch.cuda.synchronize()
+                walls.append((time.perf_counter() - t0) * 1e6)
+            walls.sort()
+            res[f"{name}_{'unfused' if u else 'fused'}"] = {
+                "us_warm_median": round(warm[0], 1), "us_cold_median": round(cold[0], 1),
+                "us_wall_median": round(walls[10], 1), "GBps_warm": round(bpe * 1e6 / (warm[0] * 1e-6) / 1e9, 1)}
+    tot_f = sum(v["us_wall_median"] for k, v in res.items() if k.endswith("_fused"))
+    tot_u = sum(v["us_wall_median"] for k, v in res.items() if k.endswith("_unfused"))
+    print(json.dumps({"metric": "1000x1000 FP32 calls, host wall clock per call set (call + synchronise)",
+                      "value": round(tot_f, 1), "unit": "us", "higher_is_better": False, "n_gpus": 1, "dtype": "f32",
+                      "data": "synthetic: seeded U[-1,1] (D: U[-4,4]), 1000x1000",
+                      "speedup_vs_unfused": round(tot_u / tot_f, 3), "per_call": res}), flush=True)
 
 
 def kernel_names(coot, synth):

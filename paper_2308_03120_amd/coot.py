@@ -12,6 +12,7 @@ column.  Expression trees are sequences of nodes with ``op``, ``a``, ``b``,
 """
 from __future__ import annotations
 
+import collections
 import ctypes as C
 import os
 from typing import Optional, Sequence
@@ -112,6 +113,13 @@ def lib():
         if not os.path.exists(LIB_PATH):
             raise ImportError(f"{LIB_PATH} is missing: build it with paper_2308_03120_amd.build.build() "
                               "(there is no CPU fallback)")
+        # The library and torch must share one HIP runtime (the binding passes
+        # torch's streams and memory): load torch's first, so that the
+        # library's libamdhip64.so.7 dependency resolves to it.
+        try:
+            import torch  # noqa: F401
+        except ImportError:
+            pass
         L = C.CDLL(LIB_PATH)
         P = C.POINTER
         vp, i64, i32 = C.c_void_p, C.c_int64, C.c_int
@@ -198,9 +206,28 @@ def fake_operand(n_rows: int, n_cols: int, dtype: str = "f32", ld: Optional[int]
     return Operand(ptr, n_rows, n_cols, ld if ld is not None else max(1, n_rows), DTYPE_CODES[dtype], flags)
 
 
+# Converted node arrays of recently used tree objects (trees are immutable once
+# built).  The entry holds the tree itself, so its id cannot be reused while
+# cached.
+_NODE_CACHE: "collections.OrderedDict[int, tuple]" = collections.OrderedDict()
+_NODE_CACHE_MAX = 512
+
+
 def _nodes(tree):
     if hasattr(tree, "postfix"):
-        tree = tree.postfix()
+        hit = _NODE_CACHE.get(id(tree))
+        if hit is not None and hit[0] is tree:
+            _NODE_CACHE.move_to_end(id(tree))
+            return hit[1]
+        arr = _convert(tree.postfix())
+        _NODE_CACHE[id(tree)] = (tree, arr)
+        if len(_NODE_CACHE) > _NODE_CACHE_MAX:
+            _NODE_CACHE.popitem(last=False)
+        return arr
+    return _convert(tree)
+
+
+def _convert(tree):
     arr = (Node * len(tree))()
     for i, n in enumerate(tree):
         if isinstance(n, (tuple, list)):

@@ -422,7 +422,7 @@ static int run_unfused(int red_op, int dim, const coot_expr* expr, const coot_op
 
 static int do_eval(const coot_expr* expr, const coot_operand* ops, int n_ops, const coot_operand* out, hipStream_t st)
 {
-    Plan p = make_plan(-1, -1, expr, ops, n_ops, out);
+    Plan p = make_plan_cached(-1, -1, expr, ops, n_ops, out);
     ensure_init();
     if (expr->flags & COOT_EXPR_UNFUSED) return run_unfused(-1, -1, expr, ops, n_ops, out, st);
     if (p.n == 0) return COOT_OK;
@@ -433,7 +433,7 @@ static int do_eval(const coot_expr* expr, const coot_operand* ops, int n_ops, co
 static int do_reduce(int red_op, int dim, const coot_expr* expr, const coot_operand* ops, int n_ops,
                      const coot_operand* out, hipStream_t st)
 {
-    Plan p = make_plan(red_op, dim, expr, ops, n_ops, out);
+    Plan p = make_plan_cached(red_op, dim, expr, ops, n_ops, out);
     ensure_init();
     if (expr->flags & COOT_EXPR_UNFUSED) return run_unfused(red_op, dim, expr, ops, n_ops, out, st);
     const int64_t n_out = p.dim < 0 ? 1 : (p.dim == 0 ? p.cols : p.rows);

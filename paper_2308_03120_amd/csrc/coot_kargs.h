@@ -40,10 +40,13 @@ COOT_HD void coot_tile_shape(long long R, long long Cn, int* lr, int* lc)
     }
 }
 
-/* LDS row stride of a 2^lr x 2^lc tile (conflict-free column reads) */
+/* LDS row stride of a 2^lr x 2^lc tile.  LDS banks are resolved per 32
+ * lanes: a read in the value's order puts 32/2^lr rows of 2^lr elements on
+ * those lanes, so the stride is 32/2^lr modulo 32 (conflict-free); tiles of
+ * 64 or more rows read one row per lane and take an odd stride. */
 COOT_HD int coot_tile_stride(int lr, int lc)
 {
-    return lr < 6 ? (1 << lc) + (64 >> lr) : (lc == 0 ? 1 : (1 << lc) + 1);
+    return lr < 6 ? (1 << lc) + (32 >> lr > 0 ? 32 >> lr : 1) : (lc == 0 ? 1 : (1 << lc) + 1);
 }
 #define COOT_TILE_LDS 4160
 

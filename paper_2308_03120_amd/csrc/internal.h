@@ -74,6 +74,9 @@ struct Plan {
 // Validate and plan.  Throws Error.
 Plan make_plan(int red_op, int dim, const coot_expr* expr, const coot_operand* ops, int n_ops,
                const coot_operand* out);
+// make_plan memoised on everything the plan depends on (per-call entry points)
+Plan make_plan_cached(int red_op, int dim, const coot_expr* expr, const coot_operand* ops, int n_ops,
+                      const coot_operand* out);
 
 struct LaunchCfg {
     int ept, block, split;

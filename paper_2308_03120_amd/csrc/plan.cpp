@@ -18,6 +18,8 @@
 #include <functional>
 #include <map>
 #include <sstream>
+#include <unordered_map>
+#include <mutex>
 #include <tuple>
 
 #include "internal.h"
@@ -161,10 +163,11 @@ Plan make_plan(int red_op_in, int dim, const coot_expr* expr, const coot_operand
     std::vector<char> slot_checked(n_ops > 0 ? n_ops : 1, 0);
     for (int i = 0; i < nn; ++i) {
         const coot_node& N = expr->nodes[i];
-        std::string at = "node " + std::to_string(i);
-        if (N.reserved != 0) fail(COOT_ERR_BAD_TREE, at + ": reserved must be 0");
+        // message prefix, built only when a check fails
+        auto at = [i]() { return "node " + std::to_string(i); };
+        if (N.reserved != 0) fail(COOT_ERR_BAD_TREE, at() + ": reserved must be 0");
         if (N.op == COOT_LEAF) {
-            if (N.a < 0 || N.a >= n_ops) fail(COOT_ERR_BAD_TREE, at + ": operand slot out of range");
+            if (N.a < 0 || N.a >= n_ops) fail(COOT_ERR_BAD_TREE, at() + ": operand slot out of range");
             const coot_operand& o = ops[N.a];
             if (!slot_checked[N.a]) {
                 std::string w = "operand " + std::to_string(N.a);
@@ -176,22 +179,22 @@ Plan make_plan(int red_op_in, int dim, const coot_expr* expr, const coot_operand
             continue;
         }
         bool bin = is_binary(N.op), sc = is_scalar(N.op), un = is_unary(N.op);
-        if (!bin && !sc && !un && N.op != COOT_TRANS && N.op != COOT_CONV) fail(COOT_ERR_BAD_TREE, at + ": unknown opcode");
-        if (N.a < 0 || N.a >= i) fail(COOT_ERR_BAD_TREE, at + ": child a must be an earlier node");
+        if (!bin && !sc && !un && N.op != COOT_TRANS && N.op != COOT_CONV) fail(COOT_ERR_BAD_TREE, at() + ": unknown opcode");
+        if (N.a < 0 || N.a >= i) fail(COOT_ERR_BAD_TREE, at() + ": child a must be an earlier node");
         Info A = info[N.a];
         if (bin) {
-            if (N.b < 0 || N.b >= i) fail(COOT_ERR_BAD_TREE, at + ": child b must be an earlier node");
+            if (N.b < 0 || N.b >= i) fail(COOT_ERR_BAD_TREE, at() + ": child b must be an earlier node");
             Info B = info[N.b];
             if (A.rows != B.rows || A.cols != B.cols)
-                fail(COOT_ERR_SHAPE, at + ": operand shapes " + shape_str(A.rows, A.cols) + " and " +
+                fail(COOT_ERR_SHAPE, at() + ": operand shapes " + shape_str(A.rows, A.cols) + " and " +
                                          shape_str(B.rows, B.cols) + " differ");
-            if (A.prec != B.prec) fail(COOT_ERR_DTYPE, at + ": mixed FP32/FP64 operands need an explicit conversion");
+            if (A.prec != B.prec) fail(COOT_ERR_DTYPE, at() + ": mixed FP32/FP64 operands need an explicit conversion");
             info[i] = A;
         } else if (N.op == COOT_CONV) {
-            if (!is_value_dtype(N.b)) fail(COOT_ERR_BAD_TREE, at + ": conversion target must be a value dtype");
+            if (!is_value_dtype(N.b)) fail(COOT_ERR_BAD_TREE, at() + ": conversion target must be a value dtype");
             info[i] = {A.rows, A.cols, N.b == COOT_F64 ? 64 : 32};
         } else {
-            if (N.b != -1) fail(COOT_ERR_BAD_TREE, at + ": b must be -1 for a unary or scalar node");
+            if (N.b != -1) fail(COOT_ERR_BAD_TREE, at() + ": b must be -1 for a unary or scalar node");
             if (N.op == COOT_TRANS)
                 info[i] = {A.cols, A.rows, A.prec};
             else
@@ -376,16 +379,99 @@ Plan make_plan(int red_op_in, int dim, const coot_expr* expr, const coot_operand
     }
 
     // --- canonical text of the element function (part of the kernel key)
-    std::ostringstream s;
-    for (const Read& r : P.reads) s << "r" << dtype_name(r.dtype) << (r.trans ? "T" : "S") << ";";
+    std::string sig;
+    sig.reserve(32 + 48 * P.nodes.size());
+    char buf[96];
+    for (const Read& r : P.reads) {
+        sig += 'r';
+        sig += dtype_name(r.dtype);
+        sig += r.trans ? "T;" : "S;";
+    }
     for (const PNode& n : P.nodes) {
         uint64_t kb;
         std::memcpy(&kb, &n.k, 8);
-        s << n.op << "," << n.a << "," << n.b << "," << n.prec << "," << n.conv << "," << hex64(kb) << ";";
+        snprintf(buf, sizeof buf, "%d,%d,%d,%d,%d,%016llx;", n.op, n.a, n.b, n.prec, n.conv, (unsigned long long)kb);
+        sig += buf;
     }
-    s << "root" << P.root;
-    P.body_sig = s.str();
+    sig += "root" + std::to_string(P.root);
+    P.body_sig = std::move(sig);
     return P;
+}
+
+// ------------------------------------------------------------- plan cache
+// make_plan for the per-call entry points, memoised.  The key holds every
+// input the plan depends on: the tree, the shapes, types, leading dimensions
+// and flags of the operands and the output, each pointer's 16-byte alignment
+// (vector width) and whether it is NULL, and each operand's relation to the
+// output's storage (overlapping, same base) that decides aliasing.  A call
+// that fails its checks is never cached.
+namespace {
+std::mutex g_pc_mu;
+std::unordered_map<std::string, Plan> g_pc;
+const size_t kPlanCacheMax = 4096;
+
+template <class T>
+void put(std::string& k, const T& v)
+{
+    k.append(reinterpret_cast<const char*>(&v), sizeof v);
+}
+
+// a descriptor whose extent can be computed without overflow
+bool sane(const coot_operand& o)
+{
+    const int64_t lim = int64_t(1) << 40;
+    return o.n_rows >= 0 && o.n_cols >= 0 && o.ld >= 1 && o.ld >= o.n_rows && o.n_rows <= lim && o.n_cols <= lim &&
+           o.ld <= lim && (is_value_dtype(o.dtype) || o.dtype == COOT_U64);
+}
+}  // namespace
+
+Plan make_plan_cached(int red_op, int dim, const coot_expr* expr, const coot_operand* ops, int n_ops,
+                      const coot_operand* out)
+{
+    if (!expr || !expr->nodes || expr->n_nodes <= 0 || expr->n_nodes > 4096 || n_ops < 0 || n_ops > 4096 ||
+        (n_ops > 0 && !ops) || !out)
+        return make_plan(red_op, dim, expr, ops, n_ops, out);  // the full checks report the error
+    std::string k;
+    k.reserve(64 + (size_t)expr->n_nodes * sizeof(coot_node) + (size_t)(n_ops + 1) * 48);
+    put(k, red_op);
+    put(k, dim);
+    put(k, expr->flags);
+    put(k, expr->cfg);
+    put(k, n_ops);
+    put(k, expr->n_nodes);
+    k.append(reinterpret_cast<const char*>(expr->nodes), (size_t)expr->n_nodes * sizeof(coot_node));
+    const bool out_ok = sane(*out) && !(out->flags & COOT_OPERAND_HOST);
+    uint64_t olo = 0, ohi = 0;
+    if (out_ok) extent(*out, out->dtype, &olo, &ohi);
+    auto desc = [&](const coot_operand& o, bool rel) {
+        put(k, o.n_rows);
+        put(k, o.n_cols);
+        put(k, o.ld);
+        put(k, o.dtype);
+        put(k, o.flags);
+        uint8_t a = (uint8_t)((uintptr_t)o.ptr & 15) | (o.ptr ? 0 : 0x80);
+        if (rel && out_ok && ohi > olo && sane(o)) {
+            uint64_t lo, hi;
+            extent(o, o.dtype, &lo, &hi);
+            if (!(hi <= lo || hi <= olo || ohi <= lo)) a |= 0x20;
+            if (o.ptr == out->ptr) a |= 0x40;
+        } else if (rel) {
+            a |= 0x10;  // relation not computed: never equal to a computed one
+        }
+        put(k, a);
+    };
+    for (int s = 0; s < n_ops; ++s) desc(ops[s], true);
+    desc(*out, false);
+    {
+        std::lock_guard<std::mutex> lk(g_pc_mu);
+        auto it = g_pc.find(k);
+        if (it != g_pc.end()) return it->second;
+    }
+    Plan p = make_plan(red_op, dim, expr, ops, n_ops, out);
+    std::lock_guard<std::mutex> lk(g_pc_mu);
+    if (g_pc.size() >= kPlanCacheMax) g_pc.clear();
+    g_pc.emplace(std::move(k), p);
+    return p;
 }
 
 // ----------------------------------------------------------- configurations

@@ -241,3 +241,49 @@ def test_every_config_gives_same_bits(g, cfg):
     t = leaf(0) % leaf(1) + 0.75
     em = oracle.evaluate(t.postfix(), ms, "emu")
     assert same(run_eval(t, ms, cfg=cfg), em)
+
+
+def test_plan_cache_keeps_pointer_dependent_checks(g):
+    """Repeated calls reuse their plan; every decision that depends on the
+    pointers (aliasing with the output, vector width from alignment) is part of
+    the reuse key, so a cached success never hides an error or a misaligned
+    operand."""
+    A, B = mats_like(g, [(96, 80), (80, 96)], "f32")
+    x, y = leaves(2)
+    t = trans(x) + 0.5 * y                     # reads A transposed, B straight
+    em = oracle.evaluate(t.postfix(), [A, B], "emu")
+    dA, dB = dev(A), dev(B)
+    for _ in range(2):
+        O = empty(80, 96, "f32")
+        coot.eval(t, [dA, dB], O)
+        torch.cuda.synchronize()
+        assert same(host(O), em)
+        # in place on the straight operand: allowed
+        dB2 = dev(B)
+        coot.eval(t, [dA, dB2], dB2)
+        torch.cuda.synchronize()
+        assert same(host(dB2), em)
+        # an output overlapping the operand read transposed: refused, before and
+        # after cached successes with the same shapes
+        buf = torch.zeros(96 * 80 + 96 * 80, device="cuda")
+        dA2 = buf[:96 * 80].view(80, 96).t()           # A: 96 x 80 column-major
+        dA2.copy_(dA)
+        Ov = buf[40:40 + 80 * 96].view(96, 80).t()     # 80 x 96, overlapping A's storage
+        with pytest.raises(coot.CootError) as e:
+            coot.eval(t, [dA2, dB], Ov)
+        assert e.value.code == -4, e.value.code   # COOT_ERR_ALIAS
+        O2 = buf[96 * 80:].view(96, 80).t()            # disjoint: fine
+        coot.eval(t, [dA2, dB], O2)
+        torch.cuda.synchronize()
+        assert same(host(O2), em)
+    # flat kernel: aligned first, then the same shapes one element off 16-byte alignment
+    a = synth.Mat(np.asfortranarray(g.uniform(-1, 1, (1001, 3)).astype(np.float32)), "f32")
+    b = synth.Mat(np.asfortranarray(g.uniform(-1, 1, (1001, 3)).astype(np.float32)), "f32")
+    t2 = x % y - 2.5
+    em2 = oracle.evaluate(t2.postfix(), [a, b], "emu")
+    for off in (0, 1, 0, 3):
+        da, db = dev(a, offset=off), dev(b)
+        O = empty(1001, 3, "f32", offset=off)
+        coot.eval(t2, [da, db], O)
+        torch.cuda.synchronize()
+        assert same(host(O), em2), off
