@@ -28,12 +28,15 @@ OPS = {
     "scal_plus": 5, "scal_minus_post": 6, "scal_minus_pre": 7, "scal_times": 8,
     "scal_div_post": 9, "scal_div_pre": 10,
     "exp": 11, "log": 12, "sqrt": 13, "abs": 14, "trans": 15, "conv": 16,
+    "gt": 17, "lt": 18, "ge": 19, "le": 20, "eq": 21, "ne": 22,
+    "scal_gt": 23, "scal_lt": 24, "scal_ge": 25, "scal_le": 26, "scal_eq": 27, "scal_ne": 28,
 }
 TYPES = {"f32": 0, "f64": 1, "f16": 2, "bf16": 3}
 MODES = {"exact": 0, "emu": 1}
 REDS = {
     "accu": 0, "sum": 1, "dot": 2, "norm1": 3, "norm2": 4, "norminf": 5, "normneginf": 6,
     "min": 7, "max": 8, "index_min": 9, "index_max": 10,
+    "mean": 11, "var": 12, "stddev": 13, "count": 14, "all": 15, "any": 16,
 }
 ERRORS = {-1: "bad tree", -2: "shape mismatch", -5: "empty input", -9: "out of memory"}
 
@@ -177,7 +180,7 @@ def evaluate_at(tree, mats, lin: np.ndarray, mode: str = "exact") -> np.ndarray:
     return out[: lin.size]
 
 
-SUM_LIKE = ("accu", "sum", "dot", "norm1", "norm2")
+SUM_LIKE = ("accu", "sum", "dot", "norm1", "norm2", "mean", "var", "stddev")
 
 
 def reduce(op: str, tree, mats, dim: int = -1, mode: str = None):

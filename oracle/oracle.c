@@ -12,6 +12,10 @@
  *   - trans, exp, log, sqrt, abs (Table 7 "trans", "misc");
  *   - accu, dot, norm with p = 1, 2, "inf", "-inf", "fro" (Table 5);
  *   - sum/min/max along dim 0 (per column) and dim 1 (per row) (Table 6);
+ *   - relational expressions A < x, A > B ... giving 1 or 0 per element, and
+ *     all / any / the count of nonzero elements over them (Table 5; the
+ *     counting example of Section 3);
+ *   - mean, var and stddev over all elements or along a dim (Table 6);
  *   - delayed evaluation by post-order "apply" of each node into a temporary
  *     (Section 7: unwrap<T1> calls op_type::apply recursively);
  *   - type conversion as an explicit node (Section 7: mtOp / mtop_conv_to).
@@ -44,6 +48,8 @@ enum {
     OR_SCAL_PLUS, OR_SCAL_MINUS_POST, OR_SCAL_MINUS_PRE, OR_SCAL_TIMES,
     OR_SCAL_DIV_POST, OR_SCAL_DIV_PRE,
     OR_EXP, OR_LOG, OR_SQRT, OR_ABS, OR_TRANS, OR_CONV,
+    OR_GT, OR_LT, OR_GE, OR_LE, OR_EQ, OR_NE,                         /* a ? b */
+    OR_SCAL_GT, OR_SCAL_LT, OR_SCAL_GE, OR_SCAL_LE, OR_SCAL_EQ, OR_SCAL_NE,  /* a ? k */
     OR_NOPS
 };
 
@@ -53,7 +59,8 @@ enum { MODE_EXACT = 0, MODE_EMU = 1 };
 
 enum {
     RD_ACCU = 0, RD_SUM, RD_DOT, RD_NORM1, RD_NORM2, RD_NORMINF, RD_NORMNEGINF,
-    RD_MIN, RD_MAX, RD_INDEX_MIN, RD_INDEX_MAX
+    RD_MIN, RD_MAX, RD_INDEX_MIN, RD_INDEX_MAX,
+    RD_MEAN, RD_VAR, RD_STDDEV, RD_COUNT, RD_ALL, RD_ANY
 };
 
 /* error codes */
@@ -141,8 +148,12 @@ double oracle_widen16(int dtype, uint16_t bits)
 }
 
 /* ---- tree structure ---------------------------------------------------- */
-static int is_binary(int op) { return op >= OR_PLUS && op <= OR_DIV; }
-static int is_scalar(int op) { return op >= OR_SCAL_PLUS && op <= OR_SCAL_DIV_PRE; }
+static int is_binary(int op) { return (op >= OR_PLUS && op <= OR_DIV) || (op >= OR_GT && op <= OR_NE); }
+static int is_scalar(int op)
+{
+    return (op >= OR_SCAL_PLUS && op <= OR_SCAL_DIV_PRE) || (op >= OR_SCAL_GT && op <= OR_SCAL_NE);
+}
+static int is_relational(int op) { return op >= OR_GT && op <= OR_SCAL_NE; }
 
 typedef struct {
     int64_t rows, cols;
@@ -210,6 +221,20 @@ static double apply_op(int op, double a, double b, double k)
     case OR_LOG: return log(a);
     case OR_SQRT: return sqrt(a);
     case OR_ABS: return fabs(a);
+    /* relational: 1 where the comparison holds, else 0; IEEE comparisons, so
+     * a NaN operand gives 0, except for != which gives 1 */
+    case OR_GT: return a > b ? 1.0 : 0.0;
+    case OR_LT: return a < b ? 1.0 : 0.0;
+    case OR_GE: return a >= b ? 1.0 : 0.0;
+    case OR_LE: return a <= b ? 1.0 : 0.0;
+    case OR_EQ: return a == b ? 1.0 : 0.0;
+    case OR_NE: return a != b ? 1.0 : 0.0;
+    case OR_SCAL_GT: return a > k ? 1.0 : 0.0;
+    case OR_SCAL_LT: return a < k ? 1.0 : 0.0;
+    case OR_SCAL_GE: return a >= k ? 1.0 : 0.0;
+    case OR_SCAL_LE: return a <= k ? 1.0 : 0.0;
+    case OR_SCAL_EQ: return a == k ? 1.0 : 0.0;
+    case OR_SCAL_NE: return a != k ? 1.0 : 0.0;
     }
     return NAN;
 }
@@ -287,6 +312,11 @@ int oracle_eval(const or_node* nd, int nn, const or_leaf* lv, int nl, int mode,
                         case OR_SQRT: s = sqrt(fabs(a)) + sa / (2.0 * sqrt(fabs(a))); break;
                         case OR_EXP: s = exp(a) * (1.0 + sa); break;
                         case OR_LOG: s = fabs(log(a)) + sa / fabs(a); break;
+                        default:
+                            /* relational: the result is exact for the operands
+                             * it is given; its magnitude is at most 1 */
+                            if (is_relational(N->op)) s = 1.0;
+                            break;
                         }
                     }
                 }
@@ -431,6 +461,13 @@ static int is_sum_like(int op)
     return op == RD_ACCU || op == RD_SUM || op == RD_DOT || op == RD_NORM1 || op == RD_NORM2;
 }
 
+/* selections have no value on an empty input */
+static int is_selection(int op)
+{
+    return op == RD_MIN || op == RD_MAX || op == RD_INDEX_MIN || op == RD_INDEX_MAX || op == RD_NORMINF ||
+           op == RD_NORMNEGINF;
+}
+
 int oracle_reduce(int rop, int dim, const or_node* nd, int nn, const or_leaf* lv, int nl,
                   int mode, double* vals, int64_t* idx, double* abs_sum)
 {
@@ -442,7 +479,7 @@ int oracle_reduce(int rop, int dim, const or_node* nd, int nn, const or_leaf* lv
     int dot_form = is_sum_like(rop) && rop != RD_NORM1 && rop != RD_NORM2 && nd[root].op == OR_SCHUR;
     if (rop == RD_DOT && !dot_form) return E_TREE;
     int64_t n = R * C;
-    if (n == 0 && !is_sum_like(rop)) return E_EMPTY;
+    if (n == 0 && is_selection(rop)) return E_EMPTY;
 
     double *va = NULL, *vb = NULL;
     if (dot_form) {
@@ -470,6 +507,12 @@ int oracle_reduce(int rop, int dim, const or_node* nd, int nn, const or_leaf* lv
         for (int64_t t = 0; t < len; ++t) {
             int64_t j = dim < 0 ? t : (dim == 0 ? t + o * R : o + t * R);
             double v = va[j];
+            if (rop == RD_MEAN || rop == RD_VAR || rop == RD_STDDEV) {
+                acc_add(&S, v);
+                acc_add(&Sa, fabs(v));
+                continue;
+            }
+            if (rop == RD_COUNT || rop == RD_ALL || rop == RD_ANY) continue;
             if (is_sum_like(rop)) {
                 if (dot_form) {
                     acc_add_product(&S, v, vb[j]);
@@ -499,6 +542,39 @@ int oracle_reduce(int rop, int dim, const or_node* nd, int nn, const or_leaf* lv
             vals[o] = rop == RD_NORM2 ? sqrt(s) : s;
             if (idx) idx[o] = 0;
             if (abs_sum) abs_sum[o] = acc_value(&Sa);
+        } else if (rop == RD_MEAN || rop == RD_VAR || rop == RD_STDDEV) {
+            /* two passes: the mean (compensated sum / count), then the sum of
+             * squared deviations from it; var divides by count - 1 (the
+             * unbiased estimate); one element gives 0, none gives NaN */
+            double mean = len > 0 ? acc_value(&S) / (double)len : NAN;
+            if (rop == RD_MEAN) {
+                vals[o] = mean;
+                if (abs_sum) abs_sum[o] = len > 0 ? acc_value(&Sa) / (double)len : 0.0;
+            } else {
+                acc2 M = {0.0, 0.0};
+                for (int64_t t = 0; t < len; ++t) {
+                    int64_t j = dim < 0 ? t : (dim == 0 ? t + o * R : o + t * R);
+                    double d = va[j] - mean;
+                    acc_add_product(&M, d, d);
+                }
+                double m2 = acc_value(&M);
+                double var = len > 1 ? m2 / (double)(len - 1) : (len == 1 ? 0.0 : NAN);
+                vals[o] = rop == RD_STDDEV ? sqrt(var) : var;
+                if (abs_sum) abs_sum[o] = m2;
+            }
+            if (idx) idx[o] = 0;
+        } else if (rop == RD_COUNT || rop == RD_ALL || rop == RD_ANY) {
+            /* count of nonzero elements (NaN is nonzero); all: every element
+             * nonzero (true for an empty input); any: at least one */
+            int64_t cnt = 0;
+            for (int64_t t = 0; t < len; ++t) {
+                int64_t j = dim < 0 ? t : (dim == 0 ? t + o * R : o + t * R);
+                if (va[j] != 0.0) ++cnt;
+            }
+            int64_t r = rop == RD_COUNT ? cnt : (rop == RD_ALL ? (cnt == len) : (cnt > 0));
+            vals[o] = (double)r;
+            if (idx) idx[o] = r;
+            if (abs_sum) abs_sum[o] = 0.0;
         } else {
             vals[o] = besti < 0 ? NAN : best;
             if (idx) idx[o] = besti < 0 ? 0 : besti;

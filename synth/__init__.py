@@ -150,6 +150,23 @@ class E:
     def __rtruediv__(self, o):
         return E("scal_div_pre", (self,), o)
 
+    # relational expressions (1 where true, else 0): A < x, A > B ... (Table 5,
+    # Section 3's counting example).  k > A is A < k.  == and != are the
+    # functions eq() and ne(), so that trees keep ordinary identity comparison.
+    def __gt__(self, o):
+        return E("gt", (self, o)) if isinstance(o, E) else E("scal_gt", (self,), o)
+
+    def __lt__(self, o):
+        return E("lt", (self, o)) if isinstance(o, E) else E("scal_lt", (self,), o)
+
+    def __ge__(self, o):
+        return E("ge", (self, o)) if isinstance(o, E) else E("scal_ge", (self,), o)
+
+    def __le__(self, o):
+        return E("le", (self, o)) if isinstance(o, E) else E("scal_le", (self,), o)
+
+    __hash__ = object.__hash__
+
     def t(self):
         return E("trans", (self,))
 
@@ -198,6 +215,16 @@ def abs_(x: E) -> E:
 
 def trans(x: E) -> E:
     return E("trans", (x,))
+
+
+def eq(a: E, b) -> E:
+    """1 where a == b (b a tree or a scalar), else 0"""
+    return E("eq", (a, b)) if isinstance(b, E) else E("scal_eq", (a,), b)
+
+
+def ne(a: E, b) -> E:
+    """1 where a != b (b a tree or a scalar), else 0"""
+    return E("ne", (a, b)) if isinstance(b, E) else E("scal_ne", (a,), b)
 
 
 def conv(x: E, dtype: str) -> E:
