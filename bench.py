@@ -103,11 +103,12 @@ def main():
     ap.add_argument("--unfused-steps", type=int, default=5)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--workload", default="scale",
-                    choices=["scale", "costmodel", "batched", "precision", "tiled", "small"],
+                    choices=["scale", "costmodel", "batched", "precision", "tiled", "small", "stats"],
                     help="scale (default): the 2^28-element FP32/FP64 calls; costmodel: learned launch "
                          "configuration over 6,000 random trees; batched: 10,000 matrices in one launch; "
                          "precision: 16384^2 BF16/FP16 sums and dots; tiled: transposed reads (64x64 and "
-                         "shape-adaptive tiles); small: the 1000x1000 FP32 calls, warm and cold")
+                         "shape-adaptive tiles); small: the 1000x1000 FP32 calls, warm and cold; stats: mean, "
+                         "var, stddev, count / all / any of relational trees")
     ap.add_argument("--out-dir", default=os.path.join(ROOT, "gpurun_out"),
                     help="where the cost-model workload writes its corpus table and weights")
     ap.add_argument("--trees", type=int, default=6000)
@@ -151,6 +152,8 @@ def main():
         return tiled_workload(args, np, torch, synth, coot)
     if args.workload == "small":
         return small_workload(args, np, torch, synth, coot)
+    if args.workload == "stats":
+        return stats_workload(args, np, torch, synth, coot)
     steps = []
     bufs = []
     for dt in ("f32", "f64"):
@@ -530,6 +533,50 @@ def small_workload(args, np, torch, synth, coot):
                       "value": round(tot_f, 1), "unit": "us", "higher_is_better": False, "n_gpus": 1, "dtype": "f32",
                       "data": "synthetic: seeded U[-1,1] (D: U[-4,4]), 1000x1000",
                       "speedup_vs_unfused": round(tot_u / tot_f, 3), "per_call": res}), flush=True)
+
+
+def stats_workload(args, np, torch, synth, coot):
+    """Statistics and predicate reductions on the 2^28-element FP32 and FP64
+    vectors of the scale workload and per column of a 16384^2 FP32 matrix,
+    against the plain sum of the same data; count(x > 0.3) also unfused
+    (predicate materialised, then summed)."""
+    x = synth.leaf(0)
+    res = {}
+    for dt, tdt in (("f32", torch.float32), ("f64", torch.float64)):
+        d = synth.cfg2_inputs(dt, n=N)
+        X = torch.from_numpy(d["x"]).cuda()
+        del d
+        nb = X.element_size() * N
+        calls = (("accu", lambda: coot.reduce("accu", x, [X])),
+                 ("mean", lambda: coot.reduce("mean", x, [X])),
+                 ("var", lambda: coot.reduce("var", x, [X])),
+                 ("stddev", lambda: coot.reduce("stddev", x, [X])),
+                 ("count_gt", lambda: coot.reduce("count", x > 0.3, [X])),
+                 ("all_gt", lambda: coot.reduce("all", x > -10.0, [X])),
+                 ("any_gt", lambda: coot.reduce("any", x > 7.9, [X])),
+                 ("count_gt_unfused", lambda: coot.reduce("count", x > 0.3, [X], unfused=True)))
+        for name, fn in calls:
+            med, mn, p90 = event_stats(torch, fn)
+            res[f"{name}_{dt}"] = {"us_median": round(med, 1), "us_min": round(mn, 1), "us_p90": round(p90, 1),
+                                   "GBps": round(nb / (med * 1e-6) / 1e9, 1)}
+        del X
+        torch.cuda.empty_cache()
+    A = torch.rand(16384, 16384, device="cuda").t()
+    nb = 4 * A.numel()
+    for name, fn in (("colsum", lambda: coot.reduce("sum", x, [A], dim=0)),
+                     ("colmean", lambda: coot.reduce("mean", x, [A], dim=0)),
+                     ("colvar", lambda: coot.reduce("var", x, [A], dim=0)),
+                     ("rowvar", lambda: coot.reduce("var", x, [A], dim=1)),
+                     ("colcount_gt", lambda: coot.reduce("count", x > 0.5, [A], dim=0))):
+        med, mn, p90 = event_stats(torch, fn)
+        res[f"{name}_16384x16384_f32"] = {"us_median": round(med, 1), "us_min": round(mn, 1),
+                                          "us_p90": round(p90, 1), "GBps": round(nb / (med * 1e-6) / 1e9, 1)}
+    del A
+    fused = [v["GBps"] for k, v in res.items() if "unfused" not in k]
+    print(json.dumps({"metric": "statistics and predicate reductions, effective GB/s", "value": min(fused),
+                      "unit": "GB/s (slowest fused call)", "n_gpus": 1, "higher_is_better": True,
+                      "dtype": "f32,f64", "data": "synthetic: seeded N(0,1) vectors; torch.rand matrix",
+                      "per_call": res}), flush=True)
 
 
 def kernel_names(coot, synth):

@@ -103,7 +103,23 @@ enum {
     COOT_SQRT = 22,
     COOT_ABS = 23,
     COOT_TRANS = 30,          /* trans(a): (r, c) -> (c, r) */
-    COOT_CONV = 31            /* conv_to<b>(a): round a to dtype b (coot_dtype) */
+    COOT_CONV = 31,           /* conv_to<b>(a): round a to dtype b (coot_dtype) */
+    /* relational expressions (Table 5: all(A < x), "other relational
+     * expressions"; Section 3: A > 0.3): 1 where the comparison holds, else
+     * 0, in the node's compute type.  IEEE comparisons: a NaN operand gives 0,
+     * except for != which gives 1. */
+    COOT_GT = 40,             /* a > b */
+    COOT_LT = 41,             /* a < b */
+    COOT_GE = 42,             /* a >= b */
+    COOT_LE = 43,             /* a <= b */
+    COOT_EQ = 44,             /* a == b */
+    COOT_NE = 45,             /* a != b */
+    COOT_SCAL_GT = 50,        /* a > k (k < a) */
+    COOT_SCAL_LT = 51,        /* a < k (k > a) */
+    COOT_SCAL_GE = 52,        /* a >= k */
+    COOT_SCAL_LE = 53,        /* a <= k */
+    COOT_SCAL_EQ = 54,        /* a == k */
+    COOT_SCAL_NE = 55         /* a != k */
 };
 
 /* One node.  `a` and `b` are indices of EARLIER nodes of the same array
@@ -183,7 +199,24 @@ enum {
     COOT_RED_MIN = 7,
     COOT_RED_MAX = 8,
     COOT_RED_INDEX_MIN = 9,
-    COOT_RED_INDEX_MAX = 10
+    COOT_RED_INDEX_MAX = 10,
+    /* statistics (Table 6): mean, and the variance with the unbiased n - 1
+     * normalisation and its square root, over all elements (dim -1) or per
+     * column (dim 0) / per row (dim 1).  One element gives variance 0, an
+     * empty input NaN (also for the mean).  The variance is accumulated in
+     * FP64 for every storage type: per thread as sums of deviations from the
+     * thread's first element, merged pairwise (Chan, Golub and LeVeque) in a
+     * fixed order.  Outputs F32 or F64. */
+    COOT_RED_MEAN = 11,
+    COOT_RED_VAR = 12,
+    COOT_RED_STDDEV = 13,
+    /* predicates (Table 5): the number of nonzero elements (NaN counts as
+     * nonzero), 1 if all elements are nonzero (also for an empty input),
+     * 1 if any is.  Outputs U64.  all(A < x) is COOT_RED_ALL of the tree
+     * A < x. */
+    COOT_RED_COUNT = 14,
+    COOT_RED_ALL = 15,
+    COOT_RED_ANY = 16
 };
 #define COOT_RED_PAIRWISE 0x100
 

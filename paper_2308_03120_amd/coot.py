@@ -35,11 +35,15 @@ OPS = {
     "scal_plus": 10, "scal_minus_post": 11, "scal_minus_pre": 12, "scal_times": 13,
     "scal_div_post": 14, "scal_div_pre": 15,
     "exp": 20, "log": 21, "sqrt": 22, "abs": 23, "trans": 30, "conv": 31,
+    "gt": 40, "lt": 41, "ge": 42, "le": 43, "eq": 44, "ne": 45,
+    "scal_gt": 50, "scal_lt": 51, "scal_ge": 52, "scal_le": 53, "scal_eq": 54, "scal_ne": 55,
 }
 REDS = {
     "accu": 0, "sum": 1, "dot": 2, "norm1": 3, "norm2": 4, "norminf": 5, "normneginf": 6,
     "min": 7, "max": 8, "index_min": 9, "index_max": 10,
+    "mean": 11, "var": 12, "stddev": 13, "count": 14, "all": 15, "any": 16,
 }
+U64_RESULTS = ("index_min", "index_max", "count", "all", "any")
 RED_PAIRWISE = 0x100
 OPERAND_HOST = 1
 EXPR_UNFUSED = 1
@@ -298,7 +302,7 @@ def eval(tree, operands: Sequence, out, cfg=None, unfused: bool = False, stream=
 def reduce(op, tree, operands: Sequence, out=None, dim: int = -1, pairwise: bool = False, cfg=None,
            unfused: bool = False, out_dtype=None, stream=None):
     """Reduction of the tree's value.  Allocates ``out`` on the device if not given
-    (float32/float64 by the tree's precision, int64 for indices)."""
+    (float32/float64 by the tree's precision; int64 for indices, counts, all and any)."""
     torch = _torch()
     e = expr(tree, cfg, unfused)
     arr, n = _ops(operands)
@@ -306,7 +310,7 @@ def reduce(op, tree, operands: Sequence, out=None, dim: int = -1, pairwise: bool
         opname = op if isinstance(op, str) else {v: k for k, v in REDS.items()}[op]
         rows, cols, prec = _root_shape(tree, operands)
         n_out = 1 if dim < 0 else (cols if dim == 0 else rows)
-        if opname.startswith("index"):
+        if opname in U64_RESULTS:
             dt = torch.int64
         else:
             dt = out_dtype or (torch.float64 if prec == 64 else torch.float32)

@@ -236,7 +236,7 @@ static Geometry geometry(const Plan& p, const LaunchCfg& c)
         G.grid = std::max<int64_t>(1, std::min(ceil_div(p.cols * S * 64, c.block), cap));
         if (S > 1) {
             G.comb_grid = std::min<int64_t>(p.cols, (int64_t)g_state.cus * 16);
-            G.part_bytes = (size_t)(p.cols * S) * 16;
+            G.part_bytes = (size_t)(p.cols * S) * red_partial_bytes(p.red_op);
         }
         break;
     }
@@ -257,12 +257,12 @@ static Geometry geometry(const Plan& p, const LaunchCfg& c)
             // the combine kernel takes a block per row from 256 splits on, else a thread per row
             G.comb_grid = q >= 256 ? std::min<int64_t>(p.rows, (int64_t)g_state.cus * 16)
                                    : std::max<int64_t>(1, std::min<int64_t>(ceil_div(p.rows, 256), (int64_t)g_state.cus * 16));
-            G.part_bytes = (size_t)(p.rows * q) * 16;
+            G.part_bytes = (size_t)(p.rows * q) * red_partial_bytes(p.red_op);
         }
         break;
     }
     }
-    if (p.kind == K_RED_FLAT || p.kind == K_RED_TILED) G.part_bytes = (size_t)G.grid * 16;
+    if (p.kind == K_RED_FLAT || p.kind == K_RED_TILED) G.part_bytes = (size_t)G.grid * red_partial_bytes(p.red_op);
     return G;
 }
 
@@ -391,7 +391,7 @@ static int run_unfused(int red_op, int dim, const coot_expr* expr, const coot_op
         mini[m++] = coot_node{COOT_LEAF, 0, -1, 0, 0.0};
         mops[nops++] = val[N.a];
         int bidx = -1;
-        if (N.op >= COOT_PLUS && N.op <= COOT_DIV) {
+        if (op_is_binary(N.op)) {
             mini[m++] = coot_node{COOT_LEAF, 1, -1, 0, 0.0};
             mops[nops++] = val[N.b];
             bidx = 1;

@@ -136,7 +136,7 @@ std::vector<int> slot_parities(const coot_expr* e, int n_slots)
         int m = mask[i];
         if (N.op == COOT_TRANS) m = ((m & 1) << 1) | ((m >> 1) & 1);
         if (N.a >= 0 && N.a < i) mask[N.a] |= m;
-        if (N.op >= COOT_PLUS && N.op <= COOT_DIV && N.b >= 0 && N.b < i) mask[N.b] |= m;
+        if (op_is_binary(N.op) && N.b >= 0 && N.b < i) mask[N.b] |= m;
     }
     return slot;
 }

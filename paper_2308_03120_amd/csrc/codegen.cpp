@@ -89,6 +89,8 @@ static std::string emit_eval(const Plan& p, bool pair, const std::string& pfx = 
         std::string a = n.a >= 0 ? "t" + std::to_string(n.a) : "";
         std::string b = n.b >= 0 ? "t" + std::to_string(n.b) : "";
         std::string k = lit(n.k, n.prec);
+        // a relational node: 1 or 0 in the node's type
+        auto rel = [&](const std::string& c) { return "((" + c + ") ? (" + std::string(T) + ")1 : (" + T + ")0)"; };
         std::string e;
         switch (n.op) {
         case COOT_LEAF: e = "l" + std::to_string(n.a); break;
@@ -106,6 +108,18 @@ static std::string emit_eval(const Plan& p, bool pair, const std::string& pfx = 
         case COOT_LOG: e = std::string(f ? "logf(" : "log(") + a + ")"; break;
         case COOT_SQRT: e = std::string(f ? "sqrtf(" : "sqrt(") + a + ")"; break;
         case COOT_ABS: e = std::string(f ? "__builtin_fabsf(" : "__builtin_fabs(") + a + ")"; break;
+        case COOT_GT: e = rel(a + " > " + b); break;
+        case COOT_LT: e = rel(a + " < " + b); break;
+        case COOT_GE: e = rel(a + " >= " + b); break;
+        case COOT_LE: e = rel(a + " <= " + b); break;
+        case COOT_EQ: e = rel(a + " == " + b); break;
+        case COOT_NE: e = rel(a + " != " + b); break;
+        case COOT_SCAL_GT: e = rel(a + " > " + k); break;
+        case COOT_SCAL_LT: e = rel(a + " < " + k); break;
+        case COOT_SCAL_GE: e = rel(a + " >= " + k); break;
+        case COOT_SCAL_LE: e = rel(a + " <= " + k); break;
+        case COOT_SCAL_EQ: e = rel(a + " == " + k); break;
+        case COOT_SCAL_NE: e = rel(a + " != " + k); break;
         case COOT_CONV: {
             const int cp = p.nodes[n.a].prec;
             switch (n.conv) {
@@ -127,21 +141,35 @@ static std::string emit_eval(const Plan& p, bool pair, const std::string& pfx = 
 }
 
 // --- reduction helpers ------------------------------------------------------
+// Sum-like reductions share the compensated accumulators: sums and norms,
+// the mean (a sum divided once at the end), and the predicate counts (count,
+// all, any: a sum of 0/1 terms, exact).  The variance has its own
+// accumulator; the rest are selections (value and index).
 static bool red_is_sum(int r)
 {
-    return r == COOT_RED_ACCU || r == COOT_RED_SUM || r == COOT_RED_DOT || r == COOT_RED_NORM1 || r == COOT_RED_NORM2;
+    return r == COOT_RED_ACCU || r == COOT_RED_SUM || r == COOT_RED_DOT || r == COOT_RED_NORM1 || r == COOT_RED_NORM2 ||
+           r == COOT_RED_MEAN || r == COOT_RED_COUNT || r == COOT_RED_ALL || r == COOT_RED_ANY;
 }
+
+static bool red_is_var(int r) { return r == COOT_RED_VAR || r == COOT_RED_STDDEV; }
 
 static bool red_is_max(int r) { return r == COOT_RED_MAX || r == COOT_RED_INDEX_MAX || r == COOT_RED_NORMINF; }
 
 static std::string acc_type(const Plan& p)
 {
     const int rp = p.nodes[p.root].prec;
+    if (red_is_var(p.red_op)) return "AccV";
     if (red_is_sum(p.red_op)) {
         if (rp == 64) return "AccKD";
         return p.pairwise ? "AccPF" : "AccKF";
     }
     return std::string("AccI<") + ctype(rp) + (red_is_max(p.red_op) ? ", true>" : ", false>");
+}
+
+// number of elements behind one result (the mean's divisor, all's target)
+static std::string red_len(const Plan& p)
+{
+    return p.dim < 0 ? "(double)a.n" : (p.dim == 0 ? "(double)a.rows" : "(double)a.cols");
 }
 
 static std::string accumulate_into(const Plan& p, const std::string& args, const std::string& gi);
@@ -166,7 +194,13 @@ static std::string accumulate_into(const Plan& p, const std::string& args, const
     switch (p.red_op) {
     case COOT_RED_ACCU:
     case COOT_RED_SUM:
-    case COOT_RED_DOT: return "acc.add(x_eval(" + args + "));";
+    case COOT_RED_DOT:
+    case COOT_RED_MEAN: return "acc.add(x_eval(" + args + "));";
+    case COOT_RED_COUNT:
+    case COOT_RED_ALL:
+    case COOT_RED_ANY: return "acc.add(x_eval(" + args + ") != (" + C + ")0 ? (" + C + ")1 : (" + C + ")0);";
+    case COOT_RED_VAR:
+    case COOT_RED_STDDEV: return "acc.add((double)x_eval(" + args + "));";
     case COOT_RED_NORM1: return "acc.add(" + fab + "(x_eval(" + args + ")));";
     case COOT_RED_NORM2: return "{ const " + C + " t = x_eval(" + args + "); acc.add_prod(t, t); }";
     case COOT_RED_NORMINF:
@@ -180,20 +214,37 @@ static std::string put_value(const Plan& p, const std::string& where, const std:
     return std::string(p.out_dtype == COOT_F64 ? "put_f64(" : "put_f32(") + "a.res, " + where + ", " + v + ");";
 }
 
+// statement writing result j from the combined FP64 sum v of a sum-like reduction
+static std::string put_sum_result(const Plan& p, const std::string& j, const std::string& v)
+{
+    switch (p.red_op) {
+    case COOT_RED_NORM2: return put_value(p, j, "__builtin_sqrt(" + v + ")");
+    case COOT_RED_MEAN: return put_value(p, j, "(" + v + ") / " + red_len(p));
+    case COOT_RED_COUNT: return "put_u64(a.res, " + j + ", (i64)(" + v + "));";
+    case COOT_RED_ALL: return "put_u64(a.res, " + j + ", (" + v + ") == " + red_len(p) + " ? 1 : 0);";
+    case COOT_RED_ANY: return "put_u64(a.res, " + j + ", (" + v + ") > 0.0 ? 1 : 0);";
+    default: return put_value(p, j, v);
+    }
+}
+
+// statement writing result j from a combined variance accumulator
+static std::string put_var_result(const Plan& p, const std::string& j, const std::string& acc)
+{
+    return put_value(p, j, p.red_op == COOT_RED_STDDEV ? "__builtin_sqrt(" + acc + ".var())" : acc + ".var()");
+}
+
 // statements writing result `j` straight from a per-thread/wave accumulator
 static std::string write_direct(const Plan& p, const std::string& j)
 {
-    if (red_is_sum(p.red_op)) {
-        std::string v = "(acc.hi() + acc.lo())";
-        if (p.red_op == COOT_RED_NORM2) v = "__builtin_sqrt" + v;
-        return put_value(p, j, v);
-    }
+    if (red_is_var(p.red_op)) return put_var_result(p, j, "acc");
+    if (red_is_sum(p.red_op)) return put_sum_result(p, j, "(acc.hi() + acc.lo())");
     if (p.red_op == COOT_RED_INDEX_MIN || p.red_op == COOT_RED_INDEX_MAX) return "put_u64(a.res, " + j + ", acc.i);";
     return put_value(p, j, "(acc.i < 0 ? __builtin_nan(\"\") : (double)acc.v)");
 }
 
 static std::string put_partial(const Plan& p, const std::string& slot)
 {
+    if (red_is_var(p.red_op)) return "put_var_partial((double*)a.part, " + slot + ", acc);";
     if (red_is_sum(p.red_op)) return "put_sum_partial((double*)a.part, " + slot + ", acc.hi(), acc.lo());";
     return "put_idx_partial((double*)a.part, " + slot + ", (double)acc.v, acc.i);";
 }
@@ -203,10 +254,12 @@ static std::string combine_and_write(const Plan& p, const std::string& first, co
                                      const std::string& stride, const std::string& j)
 {
     std::ostringstream s;
-    if (red_is_sum(p.red_op)) {
+    if (red_is_var(p.red_op)) {
+        s << "{ const AccV cv = combine_var((const double*)a.part, " << first << ", " << count << ", " << stride
+          << "); if (threadIdx.x == 0) " << put_var_result(p, j, "cv") << " }";
+    } else if (red_is_sum(p.red_op)) {
         s << "{ const double v = combine_sums((const double*)a.part, " << first << ", " << count << ", " << stride
-          << "); if (threadIdx.x == 0) "
-          << put_value(p, j, p.red_op == COOT_RED_NORM2 ? "__builtin_sqrt(v)" : "v") << " }";
+          << "); if (threadIdx.x == 0) " << put_sum_result(p, j, "v") << " }";
     } else {
         s << "{ const AccI<double, " << (red_is_max(p.red_op) ? "true" : "false") << "> cr = combine_idx<"
           << (red_is_max(p.red_op) ? "true" : "false") << ">((const double*)a.part, " << first << ", " << count << ", "
@@ -225,9 +278,12 @@ static std::string combine_and_write_seq(const Plan& p, const std::string& first
                                          const std::string& stride, const std::string& j)
 {
     std::ostringstream s;
-    if (red_is_sum(p.red_op)) {
+    if (red_is_var(p.red_op)) {
+        s << "{ const AccV cv = combine_var_seq((const double*)a.part, " << first << ", " << count << ", " << stride
+          << "); " << put_var_result(p, j, "cv") << " }";
+    } else if (red_is_sum(p.red_op)) {
         s << "{ const double v = combine_sums_seq((const double*)a.part, " << first << ", " << count << ", " << stride
-          << "); " << put_value(p, j, p.red_op == COOT_RED_NORM2 ? "__builtin_sqrt(v)" : "v") << " }";
+          << "); " << put_sum_result(p, j, "v") << " }";
     } else {
         const char* mx = red_is_max(p.red_op) ? "true" : "false";
         s << "{ const AccI<double, " << mx << "> cr = combine_idx_seq<" << mx << ">((const double*)a.part, " << first
@@ -883,8 +939,10 @@ static std::string emit_row(const Plan& p, const std::string& name)
         s << "#pragma unroll\n            for (int k = 0; k < " << VE << "; ++k) {\n";
         s << "                const i64 r = g * " << VE << " + k;\n";
         std::string wd = write_direct(p, "r"), pp = put_partial(p, "q * a.rows + r");
-        for (auto* str : {&wd, &pp})
+        for (auto* str : {&wd, &pp}) {
             for (size_t pos; (pos = str->find("acc.")) != std::string::npos;) str->replace(pos, 4, "av[k].");
+            for (size_t pos; (pos = str->find(", acc)")) != std::string::npos;) str->replace(pos, 6, ", av[k])");
+        }
         s << "                if (a.splits == 1) { " << wd << " } else { " << pp << " }\n";
         s << "            }\n            continue;\n        }\n";
     }

@@ -258,6 +258,62 @@ struct AccKD {
     CD double lo() const { return c; }
 };
 
+/* Variance accumulator, FP64 for every storage type: the count c, a shift k
+ * (the first value seen) and the sums of x - k and (x - k)^2, so that the
+ * cancellation in sum((x - mean)^2) is that of values near k.  Two states
+ * merge pairwise (Chan, Golub and LeVeque, "Updating formulae and a pairwise
+ * algorithm for computing sample variances", 1979): each is read as
+ * (count, mean, M2) and the merged state keeps its mean as the shift.  A NaN
+ * value propagates. */
+struct AccV {
+    double c, k, s, q;
+    CD void init() { c = 0.0; k = 0.0; s = 0.0; q = 0.0; }
+    CD void add(double x)
+    {
+        k = c == 0.0 ? x : k;
+        const double d = x - k;
+        s += d;
+        q += d * d;
+        c += 1.0;
+    }
+    CD double mean() const { return k + s / c; }
+    CD double m2() const
+    {
+        const double m = q - s * (s / c);
+        return m < 0.0 ? 0.0 : m;
+    }
+    CD void merge(const AccV& o)
+    {
+        if (o.c == 0.0) return;
+        if (c == 0.0) {
+            *this = o;
+            return;
+        }
+        const double n = c + o.c, ma = mean(), mb = o.mean(), d = mb - ma;
+        const double M = (m2() + o.m2()) + d * d * (c * o.c / n);
+        k = ma + d * (o.c / n);
+        s = 0.0;
+        q = M;
+        c = n;
+    }
+    CD void shfl(int off)
+    {
+        AccV o;
+        o.c = __shfl_xor(c, off, 64);
+        o.k = __shfl_xor(k, off, 64);
+        o.s = __shfl_xor(s, off, 64);
+        o.q = __shfl_xor(q, off, 64);
+        merge(o);
+    }
+    /* unbiased (n - 1) variance; 0 for one value, NaN for none */
+    CD double var() const
+    {
+        if (c == 0.0) return __builtin_nan("");
+        if (c < 2.0) return 0.0;
+        return m2() / (c - 1.0);
+    }
+};
+
 /* Extremum with its index: NaN skipped, ties to the lowest index, i < 0
  * means "nothing seen yet". */
 template <class C, bool MAX>
@@ -354,6 +410,45 @@ CD void put_idx_partial(double* part, i64 slot, double v, i64 i)
 {
     part[2 * slot] = v;
     part[2 * slot + 1] = __builtin_bit_cast(double, i);
+}
+
+/* variance partials: 4 doubles per slot */
+CD void put_var_partial(double* part, i64 slot, const AccV& a)
+{
+    double* p = part + 4 * slot;
+    p[0] = a.c;
+    p[1] = a.k;
+    p[2] = a.s;
+    p[3] = a.q;
+}
+
+CD AccV var_partial(const double* part, i64 slot)
+{
+    const double* p = part + 4 * slot;
+    AccV a;
+    a.c = p[0];
+    a.k = p[1];
+    a.s = p[2];
+    a.q = p[3];
+    return a;
+}
+
+/* merge `count` variance partials (first, stride) in a fixed order */
+CD AccV combine_var(const double* part, i64 first, i64 count, i64 stride)
+{
+    __shared__ AccV lds_v[16];
+    AccV a;
+    a.init();
+    for (i64 t = threadIdx.x; t < count; t += blockDim.x) a.merge(var_partial(part, first + t * stride));
+    return block_reduce(a, lds_v);
+}
+
+CD AccV combine_var_seq(const double* part, i64 first, i64 count, i64 stride)
+{
+    AccV a;
+    a.init();
+    for (i64 t = 0; t < count; ++t) a.merge(var_partial(part, first + t * stride));
+    return a;
 }
 
 /* FP64 compensated combine of `count` sum partials starting at `first`,

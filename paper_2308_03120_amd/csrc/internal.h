@@ -49,6 +49,27 @@ struct PNode {
     int64_t rows, cols;
 };
 
+// node classes shared by the planner, the generator and the baselines
+inline bool op_is_binary(int op) { return (op >= COOT_PLUS && op <= COOT_DIV) || (op >= COOT_GT && op <= COOT_NE); }
+inline bool op_is_scalar(int op)
+{
+    return (op >= COOT_SCAL_PLUS && op <= COOT_SCAL_DIV_PRE) || (op >= COOT_SCAL_GT && op <= COOT_SCAL_NE);
+}
+// reductions whose result is a value index (u64): indices, counts, all, any
+inline bool red_has_u64_out(int r)
+{
+    return r == COOT_RED_INDEX_MIN || r == COOT_RED_INDEX_MAX || r == COOT_RED_COUNT || r == COOT_RED_ALL ||
+           r == COOT_RED_ANY;
+}
+// selections: no value on an empty input
+inline bool red_is_selection(int r)
+{
+    return r == COOT_RED_MIN || r == COOT_RED_MAX || r == COOT_RED_INDEX_MIN || r == COOT_RED_INDEX_MAX ||
+           r == COOT_RED_NORMINF || r == COOT_RED_NORMNEGINF;
+}
+// per-record bytes of a reduction partial
+inline int red_partial_bytes(int r) { return (r == COOT_RED_VAR || r == COOT_RED_STDDEV) ? 32 : 16; }
+
 struct Plan {
     std::vector<PNode> nodes;
     std::vector<Read> reads;

@@ -52,13 +52,9 @@ const char* dtype_name(int dt)
     return "?";
 }
 
-static bool is_binary(int op) { return op >= COOT_PLUS && op <= COOT_DIV; }
-static bool is_scalar(int op) { return op >= COOT_SCAL_PLUS && op <= COOT_SCAL_DIV_PRE; }
+static bool is_binary(int op) { return op_is_binary(op); }
+static bool is_scalar(int op) { return op_is_scalar(op); }
 static bool is_unary(int op) { return op == COOT_EXP || op == COOT_LOG || op == COOT_SQRT || op == COOT_ABS; }
-static bool is_sum_like(int r)
-{
-    return r == COOT_RED_ACCU || r == COOT_RED_SUM || r == COOT_RED_DOT || r == COOT_RED_NORM1 || r == COOT_RED_NORM2;
-}
 
 uint64_t fnv1a(const std::string& s)
 {
@@ -148,7 +144,7 @@ Plan make_plan(int red_op_in, int dim, const coot_expr* expr, const coot_operand
         if (red_op_in & ~(0xff | COOT_RED_PAIRWISE)) fail(COOT_ERR_ARG, "unknown reduction flags");
         P.red_op = red_op_in & 0xff;
         P.pairwise = (red_op_in & COOT_RED_PAIRWISE) != 0;
-        if (P.red_op > COOT_RED_INDEX_MAX) fail(COOT_ERR_ARG, "unknown reduction");
+        if (P.red_op > COOT_RED_ANY) fail(COOT_ERR_ARG, "unknown reduction");
         if (dim < -1 || dim > 1) fail(COOT_ERR_ARG, "dim must be -1, 0 or 1");
         P.dim = dim;
         bool scalar_only = P.red_op == COOT_RED_ACCU || P.red_op == COOT_RED_DOT || P.red_op == COOT_RED_NORM1 ||
@@ -217,17 +213,16 @@ Plan make_plan(int red_op_in, int dim, const coot_expr* expr, const coot_operand
                                      shape_str(P.rows, P.cols));
         P.out_dtype = out->dtype;
     } else {
-        bool sel = !is_sum_like(P.red_op);
-        if (sel && P.n == 0) fail(COOT_ERR_EMPTY, "min/max/index of an empty object");
+        if (red_is_selection(P.red_op) && P.n == 0) fail(COOT_ERR_EMPTY, "min/max/index of an empty object");
         if (P.red_op == COOT_RED_DOT && expr->nodes[nn - 1].op != COOT_SCHUR)
             fail(COOT_ERR_BAD_TREE, "dot: the root must be an element-wise product of the two operands");
         int64_t n_out = P.dim < 0 ? 1 : (P.dim == 0 ? P.cols : P.rows);
         if (out->n_rows * out->n_cols != n_out || (out->n_rows != 1 && out->n_cols != 1))
             fail(COOT_ERR_SHAPE, "out must be a vector of " + std::to_string(n_out) + " elements");
         if (out->n_cols > 1 && out->ld != 1) fail(COOT_ERR_ARG, "out: a row vector result must have ld = 1");
-        bool idx = P.red_op == COOT_RED_INDEX_MIN || P.red_op == COOT_RED_INDEX_MAX;
-        if (idx && out->dtype != COOT_U64) fail(COOT_ERR_DTYPE, "out: index results are u64");
-        if (!idx && out->dtype != COOT_F32 && out->dtype != COOT_F64) fail(COOT_ERR_DTYPE, "out: values are f32 or f64");
+        const bool u64 = red_has_u64_out(P.red_op);
+        if (u64 && out->dtype != COOT_U64) fail(COOT_ERR_DTYPE, "out: index, count, all and any results are u64");
+        if (!u64 && out->dtype != COOT_F32 && out->dtype != COOT_F64) fail(COOT_ERR_DTYPE, "out: values are f32 or f64");
         P.out_dtype = out->dtype;
     }
 
