@@ -30,6 +30,9 @@ OPS = {
     "exp": 11, "log": 12, "sqrt": 13, "abs": 14, "trans": 15, "conv": 16,
     "gt": 17, "lt": 18, "ge": 19, "le": 20, "eq": 21, "ne": 22,
     "scal_gt": 23, "scal_lt": 24, "scal_ge": 25, "scal_le": 26, "scal_eq": 27, "scal_ne": 28,
+    "scal_pow": 29, "log10": 30, "log2": 31, "exp2": 32, "square": 33, "floor": 34, "ceil": 35, "round": 36,
+    "trunc": 37, "sign": 38, "cos": 39, "sin": 40, "tan": 41, "acos": 42, "asin": 43, "atan": 44, "cosh": 45,
+    "sinh": 46, "tanh": 47,
 }
 TYPES = {"f32": 0, "f64": 1, "f16": 2, "bf16": 3}
 MODES = {"exact": 0, "emu": 1}

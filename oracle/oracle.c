@@ -16,6 +16,8 @@
  *     all / any / the count of nonzero elements over them (Table 5; the
  *     counting example of Section 3);
  *   - mean, var and stddev over all elements or along a dim (Table 6);
+ *   - the misc and trig element-wise functions (Table 7: pow, log10,
+ *     square, cos, sin, tan, acos, asin, atan, ...);
  *   - delayed evaluation by post-order "apply" of each node into a temporary
  *     (Section 7: unwrap<T1> calls op_type::apply recursively);
  *   - type conversion as an explicit node (Section 7: mtOp / mtop_conv_to).
@@ -50,6 +52,9 @@ enum {
     OR_EXP, OR_LOG, OR_SQRT, OR_ABS, OR_TRANS, OR_CONV,
     OR_GT, OR_LT, OR_GE, OR_LE, OR_EQ, OR_NE,                         /* a ? b */
     OR_SCAL_GT, OR_SCAL_LT, OR_SCAL_GE, OR_SCAL_LE, OR_SCAL_EQ, OR_SCAL_NE,  /* a ? k */
+    OR_SCAL_POW,                                                        /* a^k */
+    OR_LOG10, OR_LOG2, OR_EXP2, OR_SQUARE, OR_FLOOR, OR_CEIL, OR_ROUND, OR_TRUNC, OR_SIGN,
+    OR_COS, OR_SIN, OR_TAN, OR_ACOS, OR_ASIN, OR_ATAN, OR_COSH, OR_SINH, OR_TANH,
     OR_NOPS
 };
 
@@ -151,7 +156,7 @@ double oracle_widen16(int dtype, uint16_t bits)
 static int is_binary(int op) { return (op >= OR_PLUS && op <= OR_DIV) || (op >= OR_GT && op <= OR_NE); }
 static int is_scalar(int op)
 {
-    return (op >= OR_SCAL_PLUS && op <= OR_SCAL_DIV_PRE) || (op >= OR_SCAL_GT && op <= OR_SCAL_NE);
+    return (op >= OR_SCAL_PLUS && op <= OR_SCAL_DIV_PRE) || (op >= OR_SCAL_GT && op <= OR_SCAL_POW);
 }
 static int is_relational(int op) { return op >= OR_GT && op <= OR_SCAL_NE; }
 
@@ -235,6 +240,26 @@ static double apply_op(int op, double a, double b, double k)
     case OR_SCAL_LE: return a <= k ? 1.0 : 0.0;
     case OR_SCAL_EQ: return a == k ? 1.0 : 0.0;
     case OR_SCAL_NE: return a != k ? 1.0 : 0.0;
+    case OR_SCAL_POW: return pow(a, k);
+    case OR_LOG10: return log10(a);
+    case OR_LOG2: return log2(a);
+    case OR_EXP2: return exp2(a);
+    case OR_SQUARE: return a * a;
+    case OR_FLOOR: return floor(a);
+    case OR_CEIL: return ceil(a);
+    case OR_ROUND: return round(a);   /* halfway cases away from zero */
+    case OR_TRUNC: return trunc(a);
+    /* sign: 1 for positive, -1 for negative; zeros and NaN are returned as they are */
+    case OR_SIGN: return a > 0.0 ? 1.0 : (a < 0.0 ? -1.0 : a);
+    case OR_COS: return cos(a);
+    case OR_SIN: return sin(a);
+    case OR_TAN: return tan(a);
+    case OR_ACOS: return acos(a);
+    case OR_ASIN: return asin(a);
+    case OR_ATAN: return atan(a);
+    case OR_COSH: return cosh(a);
+    case OR_SINH: return sinh(a);
+    case OR_TANH: return tanh(a);
     }
     return NAN;
 }
@@ -312,6 +337,21 @@ int oracle_eval(const or_node* nd, int nn, const or_leaf* lv, int nl, int mode,
                         case OR_SQRT: s = sqrt(fabs(a)) + sa / (2.0 * sqrt(fabs(a))); break;
                         case OR_EXP: s = exp(a) * (1.0 + sa); break;
                         case OR_LOG: s = fabs(log(a)) + sa / fabs(a); break;
+                        /* first-order: |f(a)| + |f'(a)| S(a); functions that jump
+                         * (floor ... sign) may move by a whole step */
+                        case OR_SCAL_POW: s = fabs(pow(a, k)) * (1.0 + fabs(k) * sa / fabs(a)); break;
+                        case OR_LOG10: s = fabs(log10(a)) + sa / (fabs(a) * log(10.0)); break;
+                        case OR_LOG2: s = fabs(log2(a)) + sa / (fabs(a) * log(2.0)); break;
+                        case OR_EXP2: s = exp2(a) * (1.0 + sa * log(2.0)); break;
+                        case OR_SQUARE: s = sa * sa; break;
+                        case OR_FLOOR: case OR_CEIL: case OR_ROUND: case OR_TRUNC: s = sa + 1.0; break;
+                        case OR_SIGN: s = 1.0; break;
+                        case OR_COS: case OR_SIN: s = 1.0 + sa; break;
+                        case OR_TAN: s = fabs(tan(a)) + sa * (1.0 + tan(a) * tan(a)); break;
+                        case OR_ACOS: case OR_ASIN: s = fabs(apply_op(N->op, a, 0.0, 0.0)) + sa / sqrt(fabs(1.0 - a * a)); break;
+                        case OR_ATAN: s = fabs(atan(a)) + sa / (1.0 + a * a); break;
+                        case OR_COSH: case OR_SINH: s = cosh(a) * (1.0 + sa); break;
+                        case OR_TANH: s = fabs(tanh(a)) + sa; break;
                         default:
                             /* relational: the result is exact for the operands
                              * it is given; its magnitude is at most 1 */

@@ -217,6 +217,25 @@ def trans(x: E) -> E:
     return E("trans", (x,))
 
 
+# misc and trig functions (Table 7)
+def pow_(x: E, k: float) -> E:
+    return E("scal_pow", (x,), k)
+
+
+def _unary(name):
+    def f(x: E) -> E:
+        return E(name, (x,))
+
+    f.__name__ = name
+    return f
+
+
+log10, log2, exp2, square, floor, ceil, round_, trunc, sign = (
+    _unary(n) for n in ("log10", "log2", "exp2", "square", "floor", "ceil", "round", "trunc", "sign"))
+cos, sin, tan, acos, asin, atan, cosh, sinh, tanh = (
+    _unary(n) for n in ("cos", "sin", "tan", "acos", "asin", "atan", "cosh", "sinh", "tanh"))
+
+
 def eq(a: E, b) -> E:
     """1 where a == b (b a tree or a scalar), else 0"""
     return E("eq", (a, b)) if isinstance(b, E) else E("scal_eq", (a,), b)
