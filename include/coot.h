@@ -98,6 +98,7 @@ enum {
     COOT_SCAL_TIMES = 13,     /* a * k (= k * a) */
     COOT_SCAL_DIV_POST = 14,  /* a / k */
     COOT_SCAL_DIV_PRE = 15,   /* k / a */
+    COOT_SCAL_POW = 16,       /* pow(a, k) (Table 7 "misc") */
     COOT_EXP = 20,
     COOT_LOG = 21,
     COOT_SQRT = 22,
@@ -119,7 +120,30 @@ enum {
     COOT_SCAL_GE = 52,        /* a >= k */
     COOT_SCAL_LE = 53,        /* a <= k */
     COOT_SCAL_EQ = 54,        /* a == k */
-    COOT_SCAL_NE = 55         /* a != k */
+    COOT_SCAL_NE = 55,        /* a != k */
+    /* Table 7 "misc" and "trig" functions, in the node's compute type with the
+     * device's single- or double-precision math library (correctly rounded:
+     * square, floor, ceil, round, trunc, sign).  round: halfway cases away
+     * from zero.  sign: 1 for positive, -1 for negative, zeros and NaN
+     * returned unchanged. */
+    COOT_LOG10 = 60,
+    COOT_LOG2 = 61,
+    COOT_EXP2 = 62,
+    COOT_SQUARE = 63,
+    COOT_FLOOR = 64,
+    COOT_CEIL = 65,
+    COOT_ROUND = 66,
+    COOT_TRUNC = 67,
+    COOT_SIGN = 68,
+    COOT_COS = 70,
+    COOT_SIN = 71,
+    COOT_TAN = 72,
+    COOT_ACOS = 73,
+    COOT_ASIN = 74,
+    COOT_ATAN = 75,
+    COOT_COSH = 76,
+    COOT_SINH = 77,
+    COOT_TANH = 78
 };
 
 /* One node.  `a` and `b` are indices of EARLIER nodes of the same array

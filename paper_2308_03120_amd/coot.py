@@ -37,6 +37,9 @@ OPS = {
     "exp": 20, "log": 21, "sqrt": 22, "abs": 23, "trans": 30, "conv": 31,
     "gt": 40, "lt": 41, "ge": 42, "le": 43, "eq": 44, "ne": 45,
     "scal_gt": 50, "scal_lt": 51, "scal_ge": 52, "scal_le": 53, "scal_eq": 54, "scal_ne": 55,
+    "scal_pow": 16, "log10": 60, "log2": 61, "exp2": 62, "square": 63, "floor": 64, "ceil": 65, "round": 66,
+    "trunc": 67, "sign": 68, "cos": 70, "sin": 71, "tan": 72, "acos": 73, "asin": 74, "atan": 75, "cosh": 76,
+    "sinh": 77, "tanh": 78,
 }
 REDS = {
     "accu": 0, "sum": 1, "dot": 2, "norm1": 3, "norm2": 4, "norminf": 5, "normneginf": 6,

@@ -108,6 +108,27 @@ static std::string emit_eval(const Plan& p, bool pair, const std::string& pfx = 
         case COOT_LOG: e = std::string(f ? "logf(" : "log(") + a + ")"; break;
         case COOT_SQRT: e = std::string(f ? "sqrtf(" : "sqrt(") + a + ")"; break;
         case COOT_ABS: e = std::string(f ? "__builtin_fabsf(" : "__builtin_fabs(") + a + ")"; break;
+        case COOT_SCAL_POW: e = std::string(f ? "powf(" : "pow(") + a + ", " + k + ")"; break;
+        case COOT_LOG10: e = std::string(f ? "log10f(" : "log10(") + a + ")"; break;
+        case COOT_LOG2: e = std::string(f ? "log2f(" : "log2(") + a + ")"; break;
+        case COOT_EXP2: e = std::string(f ? "exp2f(" : "exp2(") + a + ")"; break;
+        case COOT_SQUARE: e = a + " * " + a; break;
+        case COOT_FLOOR: e = std::string(f ? "floorf(" : "floor(") + a + ")"; break;
+        case COOT_CEIL: e = std::string(f ? "ceilf(" : "ceil(") + a + ")"; break;
+        case COOT_ROUND: e = std::string(f ? "roundf(" : "round(") + a + ")"; break;
+        case COOT_TRUNC: e = std::string(f ? "truncf(" : "trunc(") + a + ")"; break;
+        case COOT_SIGN:
+            e = "(" + a + " > (" + T + ")0 ? (" + T + ")1 : (" + a + " < (" + T + ")0 ? (" + T + ")-1 : " + a + "))";
+            break;
+        case COOT_COS: e = std::string(f ? "cosf(" : "cos(") + a + ")"; break;
+        case COOT_SIN: e = std::string(f ? "sinf(" : "sin(") + a + ")"; break;
+        case COOT_TAN: e = std::string(f ? "tanf(" : "tan(") + a + ")"; break;
+        case COOT_ACOS: e = std::string(f ? "acosf(" : "acos(") + a + ")"; break;
+        case COOT_ASIN: e = std::string(f ? "asinf(" : "asin(") + a + ")"; break;
+        case COOT_ATAN: e = std::string(f ? "atanf(" : "atan(") + a + ")"; break;
+        case COOT_COSH: e = std::string(f ? "coshf(" : "cosh(") + a + ")"; break;
+        case COOT_SINH: e = std::string(f ? "sinhf(" : "sinh(") + a + ")"; break;
+        case COOT_TANH: e = std::string(f ? "tanhf(" : "tanh(") + a + ")"; break;
         case COOT_GT: e = rel(a + " > " + b); break;
         case COOT_LT: e = rel(a + " < " + b); break;
         case COOT_GE: e = rel(a + " >= " + b); break;

@@ -53,7 +53,12 @@ struct PNode {
 inline bool op_is_binary(int op) { return (op >= COOT_PLUS && op <= COOT_DIV) || (op >= COOT_GT && op <= COOT_NE); }
 inline bool op_is_scalar(int op)
 {
-    return (op >= COOT_SCAL_PLUS && op <= COOT_SCAL_DIV_PRE) || (op >= COOT_SCAL_GT && op <= COOT_SCAL_NE);
+    return (op >= COOT_SCAL_PLUS && op <= COOT_SCAL_POW) || (op >= COOT_SCAL_GT && op <= COOT_SCAL_NE);
+}
+inline bool op_is_unary(int op)
+{
+    return op == COOT_EXP || op == COOT_LOG || op == COOT_SQRT || op == COOT_ABS || (op >= COOT_LOG10 && op <= COOT_SIGN) ||
+           (op >= COOT_COS && op <= COOT_TANH);
 }
 // reductions whose result is a value index (u64): indices, counts, all, any
 inline bool red_has_u64_out(int r)

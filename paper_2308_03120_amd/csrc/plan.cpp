@@ -54,7 +54,7 @@ const char* dtype_name(int dt)
 
 static bool is_binary(int op) { return op_is_binary(op); }
 static bool is_scalar(int op) { return op_is_scalar(op); }
-static bool is_unary(int op) { return op == COOT_EXP || op == COOT_LOG || op == COOT_SQRT || op == COOT_ABS; }
+static bool is_unary(int op) { return op_is_unary(op); }
 
 uint64_t fnv1a(const std::string& s)
 {

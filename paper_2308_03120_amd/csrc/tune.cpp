@@ -57,6 +57,25 @@ void plan_features(const Plan& p, float* f)
         case COOT_SQRT: ++cnt_sqrt; flops += 8 * w64; break;
         case COOT_ABS: ++cnt_abs; flops += w64; break;
         case COOT_CONV: ++cnt_conv; flops += 2; break;
+        case COOT_SQUARE: ++cnt_mul; flops += w64; break;
+        case COOT_LOG10:
+        case COOT_LOG2: ++cnt_log; flops += 20 * w64; break;
+        case COOT_EXP2:
+        case COOT_SCAL_POW:
+        case COOT_COS:
+        case COOT_SIN:
+        case COOT_TAN:
+        case COOT_ACOS:
+        case COOT_ASIN:
+        case COOT_ATAN:
+        case COOT_COSH:
+        case COOT_SINH:
+        case COOT_TANH: ++cnt_exp; flops += 20 * w64; break;
+        case COOT_FLOOR:
+        case COOT_CEIL:
+        case COOT_ROUND:
+        case COOT_TRUNC:
+        case COOT_SIGN: ++cnt_abs; flops += w64; break;
         case COOT_LEAF: break;
         default: ++cnt_scal; flops += (n.op == COOT_SCAL_DIV_POST || n.op == COOT_SCAL_DIV_PRE ? 10 : 1) * w64; break;
         }
