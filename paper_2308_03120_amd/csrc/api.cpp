@@ -100,7 +100,7 @@ void ensure_init()
     init_device(d, 0);
 }
 
-Scratch& scratch_for(hipStream_t st, size_t part_bytes, size_t res_bytes, size_t n_counters)
+Scratch& scratch_for(hipStream_t st, size_t part_bytes, size_t res_bytes)
 {
     std::lock_guard<std::mutex> lk(g_state.mu);
     Scratch& s = g_state.scratch[st];
@@ -123,17 +123,6 @@ Scratch& scratch_for(hipStream_t st, size_t part_bytes, size_t res_bytes, size_t
         size_t want = std::max<size_t>(res_bytes, 4096);
         hipchk(hipMalloc(&s.res, want), "hipMalloc(result)");
         s.res_bytes = want;
-    }
-    if (s.n_counters < n_counters) {
-        if (s.counters) {
-            hipchk(hipStreamSynchronize(st), "hipStreamSynchronize");
-            (void)hipFree(s.counters);
-            s.counters = nullptr;
-        }
-        size_t want = std::max<size_t>(n_counters, 64);
-        hipchk(hipMalloc((void**)&s.counters, want * sizeof(unsigned)), "hipMalloc(counters)");
-        hipchk(hipMemset(s.counters, 0, want * sizeof(unsigned)), "hipMemset(counters)");
-        s.n_counters = want;
     }
     return s;
 }
@@ -292,7 +281,7 @@ static Kernel kernel_for(const Plan& p, const LaunchCfg& c)
     }
     std::string name;
     std::string src = kernel_source(p, c, &name, nullptr);
-    Kernel k = get_kernel(name, src, p.kind == K_RED_ROW || p.kind == K_RED_COL);
+    Kernel k = get_kernel(name, src, p.kind == K_RED_ROW || p.kind == K_RED_COL || p.kind == K_RED_FLAT || p.kind == K_RED_TILED);
     std::lock_guard<std::mutex> lk(g_sig_mu);
     g_sig_kernels[key] = k;
     return k;
@@ -327,12 +316,18 @@ void run_plan(const Plan& p, const LaunchCfg& cfg_in, const coot_operand* ops, c
     const int64_t n_out = p.dim < 0 ? 1 : (p.dim == 0 ? p.cols : p.rows);
     const bool host = (out->flags & COOT_OPERAND_HOST) != 0;
     const size_t res_bytes = (size_t)n_out * 8;
-    Scratch& s = scratch_for(st, G.part_bytes, host ? res_bytes : 0, 1);
+    Scratch& s = scratch_for(st, G.part_bytes, host ? res_bytes : 0);
     a.part = s.part;
-    a.counter = s.counters;
     a.res = host ? s.res : out->ptr;
-    launch(k.fn, G.grid, G.block, a, st);
-    if ((p.kind == K_RED_ROW || p.kind == K_RED_COL) && G.splits > 1) launch(k.fn2, G.comb_grid, 256, a, st);
+    if (p.kind == K_RED_FLAT || p.kind == K_RED_TILED) {
+        // pass 1 leaves one partial per block; pass 2 (one block) combines them
+        a.splits = G.grid;
+        launch(k.fn, G.grid, G.block, a, st);
+        launch(k.fn2, 1, 256, a, st);
+    } else {
+        launch(k.fn, G.grid, G.block, a, st);
+        if ((p.kind == K_RED_ROW || p.kind == K_RED_COL) && G.splits > 1) launch(k.fn2, G.comb_grid, 256, a, st);
+    }
     if (host) {
         hipchk(hipMemcpyAsync(out->ptr, s.res, res_bytes / 8 * (size_t)itemsize(out->dtype), hipMemcpyDeviceToHost, st),
                "hipMemcpyAsync");
@@ -481,7 +476,6 @@ int coot_finalize(void)
             for (auto& kv : g_state.scratch) {
                 if (kv.second.part) (void)hipFree(kv.second.part);
                 if (kv.second.res) (void)hipFree(kv.second.res);
-                if (kv.second.counters) (void)hipFree(kv.second.counters);
             }
             g_state.scratch.clear();
         }

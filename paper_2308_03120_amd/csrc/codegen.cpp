@@ -348,6 +348,28 @@ static std::string arglist(const Plan& p, F f)
 // store.  Reductions: a software pipeline of two register buffers, so the
 // loads of the next step are in flight while the current step is folded into
 // the compensated accumulators (two per thread, alternating by vector).
+// A selection fed by a stream whose indices only grow needs no tie test
+// against the earlier elements of that stream.
+static std::string increasing(const Plan& p, std::string acc)
+{
+    if (acc_type(p).compare(0, 4, "AccI") != 0) return acc;
+    for (size_t pos = 0; (pos = acc.find(".add(", pos)) != std::string::npos; pos += 9) acc.replace(pos, 5, ".add_inc(");
+    return acc;
+}
+
+// Pass 2 of the flat and tiled reductions: one block adds the a.splits
+// per-block partials of pass 1 in block order.  A kernel of its own rather
+// than a last-arriving block of pass 1, whose device-scope release in every
+// block writes back the L2 caches and costs tens of microseconds at the end
+// of each call.
+static std::string emit_partials_comb(const Plan& p, const std::string& name)
+{
+    std::ostringstream s;
+    s << "extern \"C\" __global__ void __launch_bounds__(256) " << name << "_comb(const coot_kargs a)\n{\n    "
+      << combine_and_write(p, "0", "a.splits", "1", "0") << "\n}\n";
+    return s.str();
+}
+
 static std::string emit_flat(const Plan& p, const LaunchCfg& c, const std::string& name)
 {
     const bool ew = p.kind == K_EW_FLAT;
@@ -362,10 +384,13 @@ static std::string emit_flat(const Plan& p, const LaunchCfg& c, const std::strin
     s << "    const i64 nv = a.n / " << VE << ";\n";
     s << "    const i64 bs = blockDim.x;\n";
     s << "    const i64 step = (i64)gridDim.x * bs * " << EPT << ";\n";
-    auto load = [&](const std::string& buf, const std::string& b) {
+    // guarded: every vector checks v < nv; unguarded: the caller knows the
+    // whole step is in range (straight-line loads, so the compiler can wait
+    // for exactly the loads a fold needs)
+    auto load = [&](const std::string& buf, const std::string& b, bool guarded = true) {
         std::ostringstream o;
         o << "#pragma unroll\n        for (int e = 0; e < " << EPT << "; ++e) {\n";
-        o << "            const i64 v = " << b << " + e * bs;\n            if (v < nv) {\n";
+        o << "            const i64 v = " << b << " + e * bs;\n            if (" << (guarded ? "v < nv" : "true") << ") {\n";
         for (size_t j = 0; j < p.reads.size(); ++j)
             o << "                ldv<" << stype(p.reads[j].dtype) << ", " << VE << ">(L" << j << ", v * " << VE << ", "
               << buf << j << "[e]);\n";
@@ -391,28 +416,37 @@ static std::string emit_flat(const Plan& p, const LaunchCfg& c, const std::strin
         s << "                stv<" << OS << ", " << VE << ">(O, v * " << VE << ", o);\n";
         s << "            }\n        }\n    }\n";
     } else {
-        auto fold = [&](const std::string& buf, const std::string& b) {
+        auto fold = [&](const std::string& buf, const std::string& b, bool guarded) {
             std::ostringstream o;
             std::string args = arglist(p, [&](int j) { return buf + std::to_string(j) + "[e][k]"; });
             o << "#pragma unroll\n        for (int e = 0; e < " << EPT << "; ++e) {\n";
-            o << "            const i64 v = " << b << " + e * bs;\n            if (v < nv) {\n";
+            o << "            const i64 v = " << b << " + e * bs;\n            if (" << (guarded ? "v < nv" : "true")
+              << ") {\n";
             o << "#pragma unroll\n                for (int k = 0; k < " << VE << "; ++k) { const i64 gi = v * " << VE
-              << " + k; (void)gi; if (e & 1) " << accumulate(p, args, "gi", "acc2") << " else "
-              << accumulate(p, args, "gi") << " }\n";
+              << " + k; (void)gi; if (e & 1) " << increasing(p, accumulate(p, args, "gi", "acc2")) << " else "
+              << increasing(p, accumulate(p, args, "gi")) << " }\n";
             o << "            }\n        }\n";
             return o.str();
         };
         s << decl("ra") << decl("rb");
         s << "    i64 base = (i64)blockIdx.x * bs * " << EPT << " + threadIdx.x;\n";
         s << "    {\n" << load("ra", "base") << "    }\n";
+        // a step whose next step is whole in range is whole in range too
+        auto stage = [&](const std::string& nxt, const std::string& cur, const std::string& b) {
+            std::ostringstream o;
+            o << "        if (" << b << " + " << (EPT - 1) << " * bs < nv) {\n";
+            o << load(nxt, b, false) << fold(cur, "base", false);
+            o << "        } else {\n";
+            o << load(nxt, b, true) << fold(cur, "base", true);
+            o << "        }\n";
+            return o.str();
+        };
         s << "    while (base < nv) {\n";
         s << "        const i64 nb = base + step;\n";
-        s << load("rb", "nb");
-        s << fold("ra", "base");
+        s << stage("rb", "ra", "nb");
         s << "        base = nb;\n        if (base >= nv) break;\n";
         s << "        const i64 nb2 = base + step;\n";
-        s << load("ra", "nb2");
-        s << fold("rb", "base");
+        s << stage("ra", "rb", "nb2");
         s << "        base = nb2;\n    }\n";
         s << "    acc.merge(acc2);\n";
     }
@@ -426,10 +460,9 @@ static std::string emit_flat(const Plan& p, const LaunchCfg& c, const std::strin
         s << "    __shared__ " << acc_type(p) << " lds_acc[8];\n";
         s << "    acc = block_reduce(acc, lds_acc);\n";
         s << "    if (threadIdx.x == 0) " << put_partial(p, "blockIdx.x") << "\n";
-        s << "    if (arrive_last(a.counter, gridDim.x)) {\n        "
-          << combine_and_write(p, "0", "gridDim.x", "1", "0") << "\n        counter_reset(a.counter);\n    }\n";
     }
     s << "}\n";
+    if (!ew) s << emit_partials_comb(p, name);
     return s.str();
 }
 
@@ -857,10 +890,9 @@ static std::string emit_tiled(const Plan& p, const std::string& name)
         s << "    __shared__ " << acc_type(p) << " lds_acc[4];\n";
         s << "    acc = block_reduce(acc, lds_acc);\n";
         s << "    if (threadIdx.x == 0) " << put_partial(p, "blockIdx.x") << "\n";
-        s << "    if (arrive_last(a.counter, gridDim.x)) {\n        "
-          << combine_and_write(p, "0", "gridDim.x", "1", "0") << "\n        counter_reset(a.counter);\n    }\n";
     }
     s << "}\n";
+    if (!ew) s << emit_partials_comb(p, name);
     return s.str();
 }
 

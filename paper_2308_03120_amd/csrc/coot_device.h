@@ -321,19 +321,32 @@ struct AccI {
     C v;
     i64 i;
     CD void init() { v = (C)0; i = -1; }
+    /* selections are written as selects, not branches: a per-element
+     * branch costs more than the compares it guards */
     CD bool better(C x, i64 j) const
     {
-        if (i < 0) return true;
-        if (MAX ? (x > v) : (x < v)) return true;
-        return x == v && j < i;
+        const bool gt = MAX ? (x > v) : (x < v);
+        return (i < 0) | gt | ((x == v) & (j < i));
     }
     CD void add(C x, i64 j)
     {
-        if (x == x && better(x, j)) { v = x; i = j; }
+        const bool t = (x == x) & better(x, j);
+        v = t ? x : v;
+        i = t ? j : i;
+    }
+    /* the same for a stream whose indices only grow (j above every index
+     * seen so far): a tie never replaces the earlier element */
+    CD void add_inc(C x, i64 j)
+    {
+        const bool t = (x == x) & ((i < 0) | (MAX ? (x > v) : (x < v)));
+        v = t ? x : v;
+        i = t ? j : i;
     }
     CD void merge(const AccI& o)
     {
-        if (o.i >= 0 && better(o.v, o.i)) { v = o.v; i = o.i; }
+        const bool t = (o.i >= 0) & better(o.v, o.i);
+        v = t ? o.v : v;
+        i = t ? o.i : i;
     }
     CD void shfl(int off)
     {
@@ -371,31 +384,6 @@ CD A block_reduce(A a, A* lds)
         a = b;
     }
     return a;
-}
-
-/* ------------------------------------------------------------------ */
-/* two-pass combine inside one launch: every block publishes one        */
-/* partial, the last block to arrive combines them all in block order.  */
-/* ------------------------------------------------------------------ */
-CD bool arrive_last(unsigned* counter, unsigned total)
-{
-    __shared__ unsigned s_last;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        /* release: this block's partial is visible before the count moves;
-         * only the last block acquires, below */
-        unsigned t = __hip_atomic_fetch_add(counter, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-        s_last = (t == total - 1u) ? 1u : 0u;
-    }
-    __syncthreads();
-    bool last = s_last != 0u;
-    if (last) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-    return last;
-}
-
-CD void counter_reset(unsigned* counter)
-{
-    if (threadIdx.x == 0) __hip_atomic_store(counter, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 /* partial slots are 16 bytes: sums (hi, lo) as two doubles; extrema

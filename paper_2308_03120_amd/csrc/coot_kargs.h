@@ -78,10 +78,10 @@ typedef struct coot_kargs {
     long long rows;                    /* shape of the tree's value */
     long long cols;
     long long n;                       /* rows * cols */
-    void* part;                        /* per-block partial accumulators */
-    unsigned int* counter;             /* blocks-done counter (last block combines) */
+    void* part;                        /* per-block (or per-split) partial accumulators */
     void* res;                         /* reduction result(s) */
-    long long splits;                  /* column splits of a per-row reduction */
+    long long splits;                  /* partials per result: pass-1 blocks of a flat or tiled
+                                          reduction, row segments or column splits otherwise */
     long long aux;
 } coot_kargs;
 

@@ -17,8 +17,6 @@ struct Scratch {
     size_t part_bytes = 0;
     void* res = nullptr;
     size_t res_bytes = 0;
-    unsigned* counters = nullptr;
-    size_t n_counters = 0;
 };
 
 struct State {
@@ -42,7 +40,7 @@ extern State g_state;
 
 void hipchk(hipError_t e, const char* what);
 void ensure_init();
-Scratch& scratch_for(hipStream_t st, size_t part_bytes, size_t res_bytes, size_t n_counters);
+Scratch& scratch_for(hipStream_t st, size_t part_bytes, size_t res_bytes);
 int64_t grid_cap(const LaunchCfg& c);
 void launch(hipFunction_t f, int64_t grid, int block, coot_kargs& a, hipStream_t st);
 void run_plan(const Plan& p, const LaunchCfg& cfg, const coot_operand* ops, const coot_operand* out, hipStream_t st);
