@@ -234,3 +234,56 @@ def widen16(dtype: str, bits: np.ndarray) -> np.ndarray:
     y = np.empty(bits.shape, np.float64)
     lib().oracle_widen16_array(TYPES[dtype], bits.ctypes.data_as(C.POINTER(C.c_uint16)), _dp(y), bits.size)
     return y
+
+
+# ---- generators (Table 1 fill/ones/zeros/eye, Table 4 eye/ones/zeros/linspace)
+# Dense operands with the values a memory-free generator leaf stands for.  Each
+# value is formed in FP64 as defined below, then stored (round to nearest even)
+# in the generator's element type, exactly like a value read from memory.
+def _stored(values: np.ndarray, dtype: str):
+    """(Fortran array in the storage representation, dtype) of FP64 values."""
+    v = np.asfortranarray(np.asarray(values, dtype=np.float64))
+    if dtype == "f64":
+        return v, dtype
+    r = round_to(dtype, v.reshape(-1, order="F")).reshape(v.shape, order="F")
+    if dtype == "f32":
+        return np.asfortranarray(r.astype(np.float32)), dtype
+    if dtype == "f16":
+        return np.asfortranarray(r.astype(np.float16).view(np.uint16)), dtype
+    # bfloat16: the rounded value is exact in float32 with 16 zero low bits
+    b = (r.astype(np.float32).view(np.uint32) >> 16).astype(np.uint16)
+    return np.asfortranarray(b), dtype
+
+
+def fill(rows: int, cols: int, k: float, dtype: str = "f32"):
+    """.fill(k) / ones / zeros: every element is k stored in the element type."""
+    return _stored(np.full((rows, cols), float(k)), dtype)
+
+
+def eye(rows: int, cols: int, dtype: str = "f32"):
+    """eye(rows, cols): 1 where the row index equals the column index, else 0
+    (a rectangular shape keeps the leading diagonal)."""
+    r = np.arange(rows).reshape(-1, 1)
+    c = np.arange(cols).reshape(1, -1)
+    return _stored((r == c).astype(np.float64), dtype)
+
+
+def linspace_values(start: float, end: float, n: int) -> np.ndarray:
+    """linspace(start, end, n) in FP64: x_i = start + i * d for i < n - 1 with
+    d = (end - start) / (n - 1), and the last element is end itself (the
+    vector includes both end points; n = 1 gives end)."""
+    if n <= 0:
+        return np.zeros(0)
+    x = np.empty(n)
+    if n > 1:
+        d = (float(end) - float(start)) / float(n - 1)
+        i = np.arange(n - 1, dtype=np.float64)
+        x[: n - 1] = float(start) + i * d
+    x[n - 1] = float(end)
+    return x
+
+
+def linspace(start: float, end: float, n: int, dtype: str = "f64", row: bool = False):
+    """linspace as an n x 1 column (or 1 x n row) operand stored in dtype."""
+    x = linspace_values(start, end, n)
+    return _stored(x.reshape(1, -1) if row else x.reshape(-1, 1), dtype)
