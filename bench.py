@@ -225,6 +225,12 @@ def main():
     torch.cuda.synchronize()
     ms_unfused = (time.perf_counter() - t1) / Ku * 1e3
 
+    # the plain-copy ceiling: the library's one-pass streaming 16-byte copy of
+    # the FP32 x (1 GiB read, 1 GiB written)
+    _, Xc, _, _, Zc = bufs[0]
+    copy_us = event_stats(torch, lambda: coot.copy(Zc, Xc))[0]
+    copy_gbs = 2 * Xc.numel() * Xc.element_size() / (copy_us * 1e-6) / 1e9
+
     # roofline of the dominant kernel (largest share of the step)
     dom_bytes = dict((n, b) for n, b, _ in steps)[dom]
     achieved = dom_bytes / (dom_us * 1e-6) / 1e9
@@ -269,6 +275,9 @@ def main():
                      "peak": PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / PEAK_GBS, 4), "traffic": traffic},
         "cpu_baseline": cpu,
+        "copy_ceiling": {"kernel": "coot_copy16", "bytes": 2 * Xc.numel() * Xc.element_size(),
+                         "us": round(copy_us, 2), "GBps": round(copy_gbs, 1),
+                         "dominant_frac_of_copy": round(achieved / copy_gbs, 4)},
     }
     print(json.dumps(out), flush=True)
 
@@ -466,7 +475,8 @@ def event_stats(torch, fn, reps=21, between=None):
 
 
 def tiled_workload(args, np, torch, synth, coot):
-    """Transposed reads: Y = trans(A) + 0.5*B and accu(trans(A) % B) on square and thin values."""
+    """Transposed reads: Y = trans(A) + 0.5*B and accu(trans(A) % B) on square and thin values;
+    generator and view calls (A + eye, a scaled submatrix, trace)."""
     x, y = synth.leaves(2)
     res = {}
     cases = (("square_16384x16384_f32", 16384, 16384, torch.float32),
@@ -487,7 +497,27 @@ def tiled_workload(args, np, torch, synth, coot):
                                      "GBps": round(gbs, 1), "frac_of_peak": round(gbs / PEAK_GBS, 4)}
         del A, B, Y
         torch.cuda.empty_cache()
-    gb = [v["GBps"] for v in res.values()]
+    # generator and view calls on a 16384^2 FP32 matrix: A + eye (reads A only,
+    # tiled: eye needs rows and columns), a submatrix view (rows 1..16383,
+    # columns 1..16383: a strided operand) scaled into a second view, and trace
+    # (16384 strided elements, one per cache line: latency, not bandwidth)
+    n = 16384
+    A = torch.rand(n, n, device="cuda").t()
+    Y = torch.empty(n, n, device="cuda").t()
+    X0 = synth.leaf(0)
+    for call, fn, nbytes in (("add_eye_16384x16384_f32", lambda: coot.eval(X0 + synth.leaf(1), [A, coot.eye(n, n)], Y),
+                              8 * n * n),
+                             ("scale_submat_16383x16383_f32",
+                              lambda: coot.eval(X0 * 2.0, [coot.submat(A, 1, 1, n - 1, n - 1)],
+                                                coot.submat(Y, 0, 0, n - 2, n - 2)), 8 * (n - 1) * (n - 1)),
+                             ("trace_16384x16384_f32", lambda: coot.trace(A), 4 * n)):
+        med, mn, p90 = event_stats(torch, fn)
+        gbs = nbytes / (med * 1e-6) / 1e9
+        res[call] = {"us_median": round(med, 1), "us_min": round(mn, 1), "us_p90": round(p90, 1),
+                     "GBps": round(gbs, 1), "frac_of_peak": round(gbs / PEAK_GBS, 4)}
+    del A, Y
+    torch.cuda.empty_cache()
+    gb = [v["GBps"] for k, v in res.items() if not k.startswith("trace")]
     print(json.dumps({"metric": "transposed-read kernels, effective GB/s", "value": min(gb),
                       "unit": "GB/s (slowest case)", "n_gpus": 1, "higher_is_better": True, "dtype": "f32,f64",
                       "data": "synthetic: torch.rand on the device", "per_call": res}), flush=True)

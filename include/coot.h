@@ -71,8 +71,30 @@ typedef enum coot_dtype {
 /* A column-major matrix: element (r, c) lives at ptr + (r + c*ld) elements.
  * ld >= n_rows (ld > n_rows describes a submatrix view, Table 1 ".rows",
  * ".cols", ".submat").  A vector is an n x 1 (Col) or 1 x n (Row) matrix.
- * An object with n_rows*n_cols == 0 is empty; ptr may then be NULL. */
-#define COOT_OPERAND_HOST 1u   /* outputs only: ptr is host memory (forces a sync) */
+ * An object with n_rows*n_cols == 0 is empty; ptr may then be NULL.
+ *
+ * Views (Table 1 submatrix views) are operands too: .submat(p, q, r, s) is
+ * ptr + (p + q*ld) with shape (r-p+1) x (s-q+1) and the parent's ld (.row,
+ * .col, .rows, .cols likewise); .diag(k) is a 1 x n operand at ptr + k*ld
+ * (k >= 0) or ptr - k (k < 0) whose ld is the parent's ld + 1, so element j
+ * is the parent's (j - min(k,0), j + max(k,0)).  A view may be an output.
+ *
+ * Generators (Table 1 .fill / .ones / .zeros / .eye; Table 4 eye, ones,
+ * zeros, linspace) are memory-free input operands: ptr NULL, ld =
+ * max(1, n_rows), dtype = the element type the values are stored in, and
+ * one COOT_OPERAND_GEN_* flag; gen[] holds the parameters.  Every value is
+ * formed in FP64 and stored once (round to nearest even) in dtype, as if
+ * read from memory:
+ *   GEN_FILL      every element gen[0] (ones: 1, zeros: 0)
+ *   GEN_EYE       1 where row == column, else 0 (any shape)
+ *   GEN_LINSPACE  a vector (n x 1 or 1 x n, n = n_rows*n_cols elements):
+ *                 x_i = gen[0] + i*d, d = (gen[1] - gen[0]) / (n - 1), for
+ *                 i < n - 1, and x_{n-1} = gen[1] (n = 1 gives gen[1])
+ * Generators are not accepted as outputs nor in batched evaluation. */
+#define COOT_OPERAND_HOST 1u           /* outputs only: ptr is host memory (forces a sync) */
+#define COOT_OPERAND_GEN_FILL 0x10u    /* inputs only: constant gen[0] */
+#define COOT_OPERAND_GEN_EYE 0x20u     /* inputs only: identity pattern */
+#define COOT_OPERAND_GEN_LINSPACE 0x40u /* inputs only: gen[0] .. gen[1] */
 
 typedef struct coot_operand {
     void* ptr;
@@ -81,6 +103,7 @@ typedef struct coot_operand {
     int64_t ld;
     int32_t dtype;     /* coot_dtype */
     uint32_t flags;    /* COOT_OPERAND_* */
+    double gen[2];     /* generator parameters (GEN_* flags only; else ignored) */
 } coot_operand;
 
 /* ---------------------------------------------------------- expressions -- */

@@ -49,6 +49,8 @@ REDS = {
 U64_RESULTS = ("index_min", "index_max", "count", "all", "any")
 RED_PAIRWISE = 0x100
 OPERAND_HOST = 1
+GEN_FILL, GEN_EYE, GEN_LINSPACE = 0x10, 0x20, 0x40
+ITEMSIZE = {F32: 4, F64: 8, F16: 2, BF16: 2, U64: 8}
 EXPR_UNFUSED = 1
 PRINT_INFO = 1
 TUNE_DEFAULT, TUNE_CACHE, TUNE_MODEL = 0, 1, 2
@@ -72,7 +74,7 @@ class CootError(RuntimeError):
 # ---- structs -------------------------------------------------------------
 class Operand(C.Structure):
     _fields_ = [("ptr", C.c_void_p), ("n_rows", C.c_int64), ("n_cols", C.c_int64), ("ld", C.c_int64),
-                ("dtype", C.c_int32), ("flags", C.c_uint32)]
+                ("dtype", C.c_int32), ("flags", C.c_uint32), ("gen", C.c_double * 2)]
 
 
 class Node(C.Structure):
@@ -213,6 +215,86 @@ def fake_operand(n_rows: int, n_cols: int, dtype: str = "f32", ld: Optional[int]
     return Operand(ptr, n_rows, n_cols, ld if ld is not None else max(1, n_rows), DTYPE_CODES[dtype], flags)
 
 
+# ---- generators and views (Table 1, Table 4) --------------------------------
+def _gen(rows: int, cols: int, dtype: str, flag: int, g0: float = 0.0, g1: float = 0.0) -> Operand:
+    o = Operand(None, int(rows), int(cols), max(1, int(rows)), DTYPE_CODES[dtype], flag)
+    o.gen[0] = float(g0)
+    o.gen[1] = float(g1)
+    return o
+
+
+def fill(rows: int, cols: int, k: float, dtype: str = "f32") -> Operand:
+    """Memory-free operand with every element k (stored once in dtype)."""
+    return _gen(rows, cols, dtype, GEN_FILL, k)
+
+
+def ones(rows: int, cols: int, dtype: str = "f32") -> Operand:
+    return fill(rows, cols, 1.0, dtype)
+
+
+def zeros(rows: int, cols: int, dtype: str = "f32") -> Operand:
+    return fill(rows, cols, 0.0, dtype)
+
+
+def eye(rows: int, cols: int, dtype: str = "f32") -> Operand:
+    """Memory-free operand: 1 where row == column, else 0."""
+    return _gen(rows, cols, dtype, GEN_EYE)
+
+
+def linspace(start: float, end: float, n: int, dtype: str = "f64", row: bool = False) -> Operand:
+    """Memory-free n x 1 (or 1 x n) vector from start to end inclusive."""
+    return _gen(1 if row else n, n if row else 1, dtype, GEN_LINSPACE, start, end)
+
+
+def _view(base: Operand, off: int, rows: int, cols: int, ld: int) -> Operand:
+    ptr = (base.ptr or 0) + off * ITEMSIZE[base.dtype]
+    return Operand(ptr if rows * cols > 0 else (base.ptr or None), rows, cols, ld, base.dtype, 0)
+
+
+def submat(t, p: int, q: int, r: int, s: int) -> Operand:
+    """.submat(p, q, r, s): rows p..r and columns q..s (inclusive) of t."""
+    b = operand(t)
+    if not (0 <= p <= r + 1 and r < b.n_rows and 0 <= q <= s + 1 and s < b.n_cols):
+        raise ValueError(f"submat({p}, {q}, {r}, {s}) outside {b.n_rows} x {b.n_cols}")
+    return _view(b, p + q * b.ld, r - p + 1, s - q + 1, b.ld)
+
+
+def rows(t, a: int, b: int) -> Operand:
+    o = operand(t)
+    return submat(o, a, 0, b, o.n_cols - 1)
+
+
+def cols(t, c: int, d: int) -> Operand:
+    o = operand(t)
+    return submat(o, 0, c, o.n_rows - 1, d)
+
+
+def row(t, i: int) -> Operand:
+    return rows(t, i, i)
+
+
+def col(t, j: int) -> Operand:
+    return cols(t, j, j)
+
+
+def diag(t, k: int = 0) -> Operand:
+    """.diag(k): the k-th diagonal of t as a 1 x n operand with ld + 1."""
+    b = operand(t)
+    r0, c0 = max(-k, 0), max(k, 0)
+    n = max(0, min(b.n_rows - r0, b.n_cols - c0))
+    return _view(b, r0 + c0 * b.ld, 1, n, b.ld + 1)
+
+
+def trace(t, out=None, stream=None):
+    """trace(A): sum of the leading diagonal (Table 5)."""
+    return reduce("accu", [("leaf", 0, -1, 0.0)], [diag(t)], out=out, stream=stream)
+
+
+def diagvec(t, out, k: int = 0, stream=None) -> None:
+    """diagvec(A, k): the k-th diagonal as an n x 1 column, written to out (Table 6)."""
+    eval([("leaf", 0, -1, 0.0), ("trans", 0, -1, 0.0)], [diag(t, k)], out, stream=stream)
+
+
 # Converted node arrays of recently used tree objects (trees are immutable once
 # built).  The entry holds the tree itself, so its id cannot be reused while
 # cached.
@@ -317,7 +399,7 @@ def reduce(op, tree, operands: Sequence, out=None, dim: int = -1, pairwise: bool
             dt = torch.int64
         else:
             dt = out_dtype or (torch.float64 if prec == 64 else torch.float32)
-        dev = operands[0].device if len(operands) else "cuda"
+        dev = next((t.device for t in operands if hasattr(t, "device")), "cuda")
         out = torch.empty(n_out, dtype=dt, device=dev)
     o = operand(out)
     _check(lib().coot_reduce(_red_code(op, pairwise), dim, C.byref(e), arr, n, C.byref(o),
@@ -332,9 +414,8 @@ def _root_shape(tree, operands):
     for n in nodes:
         op, a, b = (n.op, n.a, n.b) if not isinstance(n, (tuple, list)) else (n[0], n[1], n[2])
         if op == "leaf" or op == 0:
-            t = operands[a]
-            r, c = (t.shape[0], 1) if t.dim() == 1 else (t.shape[0], t.shape[1])
-            info.append((r, c, 64 if _dtype_code(t) == F64 else 32))
+            o = operand(operands[a])
+            info.append((o.n_rows, o.n_cols, 64 if o.dtype == F64 else 32))
         elif op in ("trans", 30):
             r, c, p = info[a]
             info.append((c, r, p))

@@ -64,6 +64,31 @@ static std::string lit(double k, int prec)
     return b;
 }
 
+// A generator's value at the element (gi_ linear index, gr_ row, gc_
+// column): formed in FP64, stored in the generator's element type, widened to
+// the node's precision.
+static std::string gen_value(const PNode& n)
+{
+    std::string v;
+    switch (n.a) {
+    case COOT_OPERAND_GEN_FILL: v = lit(n.k, 64); break;
+    case COOT_OPERAND_GEN_EYE: v = "(gr_ == gc_ ? 1.0 : 0.0)"; break;
+    default: {
+        // x_i = start + i*d for i < n - 1, end itself for the last element
+        const double d = n.gn > 1 ? (n.k2 - n.k) / (double)(n.gn - 1) : 0.0;
+        v = "(gi_ >= " + std::to_string(n.gn - 1) + " ? " + lit(n.k2, 64) + " : " + lit(n.k, 64) + " + (double)gi_ * " +
+            lit(d, 64) + ")";
+        break;
+    }
+    }
+    switch (n.conv) {
+    case COOT_F64: return v;
+    case COOT_F32: return "(float)" + v;
+    case COOT_F16: return "rnd_f16_d(" + v + ")";
+    default: return "rnd_bf16_d(" + v + ")";
+    }
+}
+
 // The element function: arguments are the widened values of the reads.
 // pair = true emits x_pair(...) returning the two children of the root
 // product instead of the product itself (exact TwoProduct in the reduction).
@@ -75,9 +100,11 @@ static std::string emit_eval(const Plan& p, bool pair, const std::string& pfx = 
         if (j) args << ", ";
         args << ctype(p.reads[j].dtype == COOT_F64 ? 64 : 32) << " l" << j;
     }
+    // generators that depend on the element take its linear index, row and column
+    if (p.gen_index) args << (p.reads.empty() ? "" : ", ") << "const i64 gi_, const i64 gr_, const i64 gc_";
     const int rp = p.nodes[p.root].prec;
     if (pair)
-        s << "CD void " << pfx << "_pair(" << args.str() << (p.reads.empty() ? "" : ", ") << ctype(rp) << "& pa, "
+        s << "CD void " << pfx << "_pair(" << args.str() << (args.str().empty() ? "" : ", ") << ctype(rp) << "& pa, "
           << ctype(rp) << "& pb)\n{\n";
     else
         s << "CD " << ctype(rp) << " " << pfx << "_eval(" << args.str() << ")\n{\n";
@@ -93,6 +120,7 @@ static std::string emit_eval(const Plan& p, bool pair, const std::string& pfx = 
         auto rel = [&](const std::string& c) { return "((" + c + ") ? (" + std::string(T) + ")1 : (" + T + ")0)"; };
         std::string e;
         switch (n.op) {
+        case PN_GEN: e = gen_value(n); break;
         case COOT_LEAF: e = "l" + std::to_string(n.a); break;
         case COOT_PLUS: e = a + " + " + b; break;
         case COOT_MINUS: e = a + " - " + b; break;
@@ -211,7 +239,7 @@ static std::string accumulate_into(const Plan& p, const std::string& args, const
     const std::string fab = rp == 64 ? "__builtin_fabs" : "__builtin_fabsf";
     const std::string C = ctype(rp);
     if (p.product_form)
-        return "{ " + C + " pa, pb; x_pair(" + args + (p.reads.empty() ? "" : ", ") + "pa, pb); acc.add_prod(pa, pb); }";
+        return "{ " + C + " pa, pb; x_pair(" + args + (args.empty() ? "" : ", ") + "pa, pb); acc.add_prod(pa, pb); }";
     switch (p.red_op) {
     case COOT_RED_ACCU:
     case COOT_RED_SUM:
@@ -331,15 +359,19 @@ static std::string decl_reads(const Plan& p, bool restrict_ok)
     return s.str();
 }
 
-// argument list from per-read expressions
+// argument list from per-read expressions; idx = "linear index, row, column"
+// of the element, passed when a generator needs them.  The flat kinds pass
+// (linear, linear, 0): they run eye only on a vector, where row == column
+// holds exactly at linear index 0.
 template <class F>
-static std::string arglist(const Plan& p, F f)
+static std::string arglist(const Plan& p, F f, const std::string& idx)
 {
     std::string s;
     for (size_t j = 0; j < p.reads.size(); ++j) {
         if (j) s += ", ";
         s += widen(p.reads[j].dtype, f((int)j));
     }
+    if (p.gen_index) s += (s.empty() ? "" : ", ") + idx;
     return s;
 }
 
@@ -409,7 +441,7 @@ static std::string emit_flat(const Plan& p, const LaunchCfg& c, const std::strin
         s << load("r", "base");
         s << "#pragma unroll\n        for (int e = 0; e < " << EPT << "; ++e) {\n";
         s << "            const i64 v = base + e * bs;\n            if (v < nv) {\n";
-        std::string args = arglist(p, [](int j) { return "r" + std::to_string(j) + "[e][k]"; });
+        std::string args = arglist(p, [](int j) { return "r" + std::to_string(j) + "[e][k]"; }, "v * " + std::to_string(VE) + " + k, v * " + std::to_string(VE) + " + k, 0");
         s << "                " << OS << " o[" << VE << "];\n";
         s << "#pragma unroll\n                for (int k = 0; k < " << VE << "; ++k) o[k] = "
           << narrow(p.out_dtype, rp, "x_eval(" + args + ")") << ";\n";
@@ -418,7 +450,7 @@ static std::string emit_flat(const Plan& p, const LaunchCfg& c, const std::strin
     } else {
         auto fold = [&](const std::string& buf, const std::string& b, bool guarded) {
             std::ostringstream o;
-            std::string args = arglist(p, [&](int j) { return buf + std::to_string(j) + "[e][k]"; });
+            std::string args = arglist(p, [&](int j) { return buf + std::to_string(j) + "[e][k]"; }, "gi, gi, 0");
             o << "#pragma unroll\n        for (int e = 0; e < " << EPT << "; ++e) {\n";
             o << "            const i64 v = " << b << " + e * bs;\n            if (" << (guarded ? "v < nv" : "true")
               << ") {\n";
@@ -451,7 +483,7 @@ static std::string emit_flat(const Plan& p, const LaunchCfg& c, const std::strin
         s << "    acc.merge(acc2);\n";
     }
     // tail elements that do not fill a vector
-    std::string targs = arglist(p, [](int j) { return "ldnt(L" + std::to_string(j) + " + i)"; });
+    std::string targs = arglist(p, [](int j) { return "ldnt(L" + std::to_string(j) + " + i)"; }, "i, i, 0");
     s << "    if (blockIdx.x == gridDim.x - 1)\n";
     s << "        for (i64 i = nv * " << VE << " + threadIdx.x; i < a.n; i += bs) ";
     if (ew) s << "stnt(O + i, (" << OS << ")(" << narrow(p.out_dtype, rp, "x_eval(" + targs + ")") << "));\n";
@@ -622,6 +654,7 @@ static std::string tile_compute_sq(const Plan& p, const TilePlan& tp, const std:
         if (j) args += ", ";
         args += tp.in_lds[j] ? "T" + std::to_string(j) + "[lane * 65 + jj]" : "cr" + std::to_string(j) + "[kk]";
     }
+    if (p.gen_index) args += (args.empty() ? "" : ", ") + ("ig + jg * " + R + ", ig, jg");
     s << per_elem(args, in + "                ", "po + lane");
     s << in << "            }\n";
     if (!out.empty()) s << in << "            po += 4 * " << ldo << ";\n";
@@ -828,6 +861,7 @@ static std::string tile_compute_gen(const Plan& p, const TilePlan& tp, const std
         if (j) args += ", ";
         args += tp.in_lds[j] ? "T" + std::to_string(j) + "[(ysr + yi) * sst + ysc + yj]" : "cr" + std::to_string(j) + "[kk]";
     }
+    if (p.gen_index) args += (args.empty() ? "" : ", ") + ("ig + jg * " + R + ", ig, jg");
     s << per_elem(args, i4 + "    ", off32 ? "atw(po, vo)" : "(po + vo)");
     s << i4 << "}\n";
     s << walk_y(i4, lr, yp);
@@ -929,11 +963,12 @@ static std::string emit_col(const Plan& p, const LaunchCfg& c, const std::string
     s << "                }\n            }\n";
     s << "#pragma unroll\n            for (int e = 0; e < " << EPT << "; ++e) {\n";
     s << "                const i64 v = base + e * 64;\n                if (v < nvr) {\n";
-    std::string args = arglist(p, [](int j) { return "r" + std::to_string(j) + "[e][k]"; });
+    std::string args = arglist(p, [](int j) { return "r" + std::to_string(j) + "[e][k]"; }, "gi + j * a.rows, gi, j");
     s << "#pragma unroll\n                    for (int k = 0; k < " << VE << "; ++k) { const i64 gi = rs0 + v * " << VE
       << " + k; (void)gi; " << accumulate(p, args, "gi") << " }\n";
     s << "                }\n            }\n        }\n";
-    std::string targs = arglist(p, [](int j) { return "ldnt(C" + std::to_string(j) + " + r)"; });
+    std::string targs = arglist(p, [](int j) { return "ldnt(C" + std::to_string(j) + " + r)"; },
+                                "(rs0 + r) + j * a.rows, rs0 + r, j");
     s << "        for (i64 r = nvr * " << VE << " + lane; r < rs1 - rs0; r += 64) { " << accumulate(p, targs, "(rs0 + r)")
       << " }\n";
     s << "        wave_reduce(acc);\n";
@@ -954,7 +989,8 @@ static std::string emit_colt(const Plan& p, const std::string& name)
     s << decl_reads(p, true);
     s << "    for (i64 j = (i64)blockIdx.x * blockDim.x + threadIdx.x; j < a.cols; j += (i64)gridDim.x * blockDim.x) {\n";
     s << "        " << acc_type(p) << " acc;\n        acc.init();\n";
-    std::string args = arglist(p, [](int j) { return "ldnt(L" + std::to_string(j) + " + r + j * ld" + std::to_string(j) + ")"; });
+    std::string args = arglist(p, [](int j) { return "ldnt(L" + std::to_string(j) + " + r + j * ld" + std::to_string(j) + ")"; },
+                               "r + j * a.rows, r, j");
     s << "        for (i64 r = 0; r < a.rows; ++r) { " << accumulate(p, args, "r") << " }\n";
     s << "        " << write_direct(p, "j") << "\n    }\n}\n";
     return s.str();
@@ -985,7 +1021,8 @@ static std::string emit_row(const Plan& p, const std::string& name)
             s << "                " << stype(p.reads[j].dtype) << " r" << j << "[" << VE << "];\n                ldv<"
               << stype(p.reads[j].dtype) << ", " << VE << ">(L" << j << ", g * " << VE << " + c * ld" << j << ", r" << j
               << ");\n";
-        std::string args = arglist(p, [](int j) { return "r" + std::to_string(j) + "[k]"; });
+        std::string args = arglist(p, [](int j) { return "r" + std::to_string(j) + "[k]"; },
+                                   "(g * " + std::to_string(VE) + " + k) + c * a.rows, g * " + std::to_string(VE) + " + k, c");
         s << "#pragma unroll\n                for (int k = 0; k < " << VE << "; ++k) { " << accumulate(p, args, "c", "av[k]")
           << " }\n";
         s << "            }\n";
@@ -1001,7 +1038,8 @@ static std::string emit_row(const Plan& p, const std::string& name)
     }
     s << "        const i64 r = RV * " << VE << " + (g - RV);\n";
     s << "        " << acc_type(p) << " acc;\n        acc.init();\n";
-    std::string args = arglist(p, [](int j) { return "ldnt(L" + std::to_string(j) + " + r + c * ld" + std::to_string(j) + ")"; });
+    std::string args = arglist(p, [](int j) { return "ldnt(L" + std::to_string(j) + " + r + c * ld" + std::to_string(j) + ")"; },
+                               "r + c * a.rows, r, c");
     s << "#pragma unroll 4\n        for (i64 c = q; c < a.cols; c += a.splits) { " << accumulate(p, args, "c") << " }\n";
     s << "        if (a.splits == 1) { " << write_direct(p, "r") << " } else { " << put_partial(p, "q * a.rows + r")
       << " }\n";

@@ -40,13 +40,20 @@ struct Read {
     int64_t ld;       // effective leading dimension
 };
 
+// A generator leaf (memory-free operand) in a plan: op = PN_GEN, a = the
+// COOT_OPERAND_GEN_* flag, conv = its element type, k / k2 = its parameters
+// (fill value; linspace start and end), gn = its element count.
+constexpr int PN_GEN = 1000;
+
 struct PNode {
-    int op;           // COOT_* opcode (never COOT_TRANS after planning)
+    int op;           // COOT_* opcode (never COOT_TRANS after planning), or PN_GEN
     int a, b;         // children (plan node indices); LEAF: a = read index
     double k;         // scalar (already rounded to the node's precision)
     int prec;         // 32 or 64
     int conv;         // COOT_CONV target dtype
     int64_t rows, cols;
+    double k2 = 0.0;  // PN_GEN: second parameter
+    int64_t gn = 0;   // PN_GEN: element count
 };
 
 // node classes shared by the planner, the generator and the baselines
@@ -94,6 +101,7 @@ struct Plan {
     bool tile_gen = false;    // tiled kind on a thin value: shape-adaptive tiles
     int tile_lr = 6, tile_lc = 6;  // tile shape 2^lr x 2^lc of the tiled kinds
     bool tile_off32 = false;  // per-lane tile offsets fit in 32-bit byte offsets
+    bool gen_index = false;   // a generator needs the element's index (eye, linspace)
     std::string body_sig;     // canonical description of the element function
 };
 

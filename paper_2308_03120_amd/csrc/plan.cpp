@@ -82,6 +82,9 @@ static std::string shape_str(int64_t r, int64_t c)
 
 static bool contiguous(const coot_operand& o) { return o.n_cols <= 1 || o.ld == o.n_rows; }
 
+static const uint32_t kGenFlags = COOT_OPERAND_GEN_FILL | COOT_OPERAND_GEN_EYE | COOT_OPERAND_GEN_LINSPACE;
+static bool is_gen(const coot_operand& o) { return (o.flags & kGenFlags) != 0; }
+
 // byte extent [lo, hi) of an operand's storage
 static void extent(const coot_operand& o, int dt, uint64_t* lo, uint64_t* hi)
 {
@@ -104,6 +107,16 @@ static void check_operand(const coot_operand& o, const char* what, bool output)
     if (o.ld < 1 || o.ld < o.n_rows) fail(COOT_ERR_ARG, std::string(what) + ": ld must be >= max(1, n_rows)");
     if (o.n_cols > 1 && o.ld > (int64_t)(INT64_MAX / 16) / o.n_cols) fail(COOT_ERR_ARG, std::string(what) + ": ld too large");
     int64_t n = o.n_rows * o.n_cols;
+    if (!output && is_gen(o)) {
+        // a generator: no memory, exactly one kind
+        const uint32_t g = o.flags & kGenFlags;
+        if ((o.flags & ~kGenFlags) || (g & (g - 1)))
+            fail(COOT_ERR_ARG, std::string(what) + ": one generator flag and no other flag");
+        if (o.ptr != nullptr) fail(COOT_ERR_ARG, std::string(what) + ": a generator has no memory (ptr must be NULL)");
+        if (g == COOT_OPERAND_GEN_LINSPACE && o.n_rows != 1 && o.n_cols != 1)
+            fail(COOT_ERR_SHAPE, std::string(what) + ": linspace is a vector (n x 1 or 1 x n)");
+        return;
+    }
     if (n > 0 && o.ptr == nullptr) fail(COOT_ERR_ARG, std::string(what) + ": NULL pointer with elements");
     if (!output && o.flags != 0) fail(COOT_ERR_ARG, std::string(what) + ": flags must be 0 for an input");
     if (output && (o.flags & ~COOT_OPERAND_HOST)) fail(COOT_ERR_ARG, std::string(what) + ": unknown flags");
@@ -228,7 +241,7 @@ Plan make_plan(int red_op_in, int dim, const coot_expr* expr, const coot_operand
 
     // --- exact rewrites: trans pushed to the operands, reads and subtrees merged
     std::map<std::pair<int, bool>, int> read_of;
-    std::map<std::tuple<int, int, int, uint64_t, int>, int> cse;
+    std::map<std::tuple<int, int, int, uint64_t, int, uint64_t, int64_t>, int> cse;
     std::map<std::pair<int, bool>, int> memo;
     std::function<int(int, bool)> rebuild = [&](int i, bool t) -> int {
         auto mk = memo.find({i, t});
@@ -246,7 +259,19 @@ Plan make_plan(int red_op_in, int dim, const coot_expr* expr, const coot_operand
             pn.prec = info[i].prec;
             pn.rows = t ? info[i].cols : info[i].rows;
             pn.cols = t ? info[i].rows : info[i].cols;
-            if (N.op == COOT_LEAF) {
+            if (N.op == COOT_LEAF && is_gen(ops[N.a])) {
+                // values from the element's index; eye and fill are their own
+                // transposes (shape swapped), a linspace vector has the same
+                // linear order either way
+                const coot_operand& o = ops[N.a];
+                pn.op = PN_GEN;
+                pn.a = (int)(o.flags & kGenFlags);
+                pn.conv = o.dtype;
+                pn.k = o.gen[0];
+                pn.k2 = o.gen[1];
+                pn.gn = o.n_rows * o.n_cols;
+                if (pn.a != COOT_OPERAND_GEN_FILL) P.gen_index = true;
+            } else if (N.op == COOT_LEAF) {
                 const coot_operand& o = ops[N.a];
                 bool tt = t;
                 int64_t ld = o.ld;
@@ -273,9 +298,10 @@ Plan make_plan(int red_op_in, int dim, const coot_expr* expr, const coot_operand
                 if (N.op == COOT_CONV) pn.conv = N.b;
                 if (is_scalar(N.op)) pn.k = pn.prec == 32 ? (double)(float)N.k : N.k;
             }
-            uint64_t kb;
+            uint64_t kb, kb2;
             std::memcpy(&kb, &pn.k, 8);
-            auto key = std::make_tuple(pn.op, pn.a, pn.b, kb, pn.conv);
+            std::memcpy(&kb2, &pn.k2, 8);
+            auto key = std::make_tuple(pn.op, pn.a, pn.b, kb, pn.conv, kb2, pn.gn);
             auto it = cse.find(key);
             if (it != cse.end()) {
                 res = it->second;
@@ -299,7 +325,7 @@ Plan make_plan(int red_op_in, int dim, const coot_expr* expr, const coot_operand
         P.alias_out = false;
         if (!(out->flags & COOT_OPERAND_HOST) && ohi > olo) {
             for (int s = 0; s < n_ops; ++s) {
-                if (!slot_checked[s]) continue;
+                if (!slot_checked[s] || is_gen(ops[s])) continue;
                 const coot_operand& o = ops[s];
                 uint64_t lo, hi;
                 extent(o, o.dtype, &lo, &hi);
@@ -322,6 +348,10 @@ Plan make_plan(int red_op_in, int dim, const coot_expr* expr, const coot_operand
         if (!r.trans && !(o.n_cols <= 1 || r.ld == P.rows || P.cols <= 1)) all_contig = false;
     }
     if (P.red_op < 0 && !(P.cols <= 1 || out->ld == P.rows)) all_contig = false;
+    // the flat kinds know only an element's linear index; eye needs its row
+    // and column, which the tiled kinds have
+    for (const PNode& n : P.nodes)
+        if (n.op == PN_GEN && n.a == COOT_OPERAND_GEN_EYE && P.rows > 1 && P.cols > 1) all_contig = false;
     P.temp_needed = false;
     P.product_form = false;
     P.prod_a = P.prod_b = -1;
@@ -383,9 +413,14 @@ Plan make_plan(int red_op_in, int dim, const coot_expr* expr, const coot_operand
         sig += r.trans ? "T;" : "S;";
     }
     for (const PNode& n : P.nodes) {
-        uint64_t kb;
+        uint64_t kb, kb2;
         std::memcpy(&kb, &n.k, 8);
-        snprintf(buf, sizeof buf, "%d,%d,%d,%d,%d,%016llx;", n.op, n.a, n.b, n.prec, n.conv, (unsigned long long)kb);
+        std::memcpy(&kb2, &n.k2, 8);
+        if (n.op == PN_GEN)
+            snprintf(buf, sizeof buf, "g%d,%d,%d,%016llx,%016llx,%lld;", n.a, n.prec, n.conv, (unsigned long long)kb,
+                     (unsigned long long)kb2, (long long)n.gn);
+        else
+            snprintf(buf, sizeof buf, "%d,%d,%d,%d,%d,%016llx;", n.op, n.a, n.b, n.prec, n.conv, (unsigned long long)kb);
         sig += buf;
     }
     sig += "root" + std::to_string(P.root);
@@ -444,6 +479,10 @@ Plan make_plan_cached(int red_op, int dim, const coot_expr* expr, const coot_ope
         put(k, o.ld);
         put(k, o.dtype);
         put(k, o.flags);
+        if (is_gen(o)) {
+            put(k, o.gen[0]);
+            put(k, o.gen[1]);
+        }
         uint8_t a = (uint8_t)((uintptr_t)o.ptr & 15) | (o.ptr ? 0 : 0x80);
         if (rel && out_ok && ohi > olo && sane(o)) {
             uint64_t lo, hi;

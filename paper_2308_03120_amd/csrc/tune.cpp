@@ -40,7 +40,7 @@ void plan_features(const Plan& p, float* f)
     for (size_t i = 0; i < p.nodes.size(); ++i) {
         const PNode& n = p.nodes[i];
         int d = 1;
-        if (n.op != COOT_LEAF) {
+        if (n.op != COOT_LEAF && n.op != PN_GEN) {
             ++n_ops;
             d = 1 + depth[n.a];
             if (n.b >= 0 && n.op != COOT_CONV) d = std::max(d, 1 + depth[n.b]);

@@ -87,6 +87,41 @@ def test_validation_errors():
     assert code(lambda: coot.validate("accu", -1, x, [A], F(1, 1, ptr=G + 8))) == -4  # result inside an operand
 
 
+def test_generator_and_view_validation():
+    """Generators (memory-free operands) and views are checked on the host."""
+    x, y = leaves(2)
+    A = F(10, 20, ptr=G)
+    O = F(10, 20, ptr=3 * G)
+    assert code(lambda: coot.validate(None, -1, x + y, [A, coot.eye(10, 20)], O)) == 0
+    assert code(lambda: coot.validate(None, -1, x + y, [A, coot.fill(10, 20, 0.5)], O)) == 0
+    assert code(lambda: coot.validate(None, -1, trans(y) + x, [A, coot.eye(20, 10)], O)) == 0
+    assert code(lambda: coot.validate(None, -1, x + y, [A, coot.eye(20, 10)], O)) == -2             # shape
+    assert code(lambda: coot.validate(None, -1, x + y, [A, coot.eye(10, 20, "f64")], O)) == -3      # precision
+    V = F(100, 1, ptr=G)
+    OV = F(100, 1, ptr=3 * G)
+    assert code(lambda: coot.validate(None, -1, x + y, [V, coot.linspace(0, 1, 100, "f32")], OV)) == 0
+    bad = coot.linspace(0, 1, 100, "f32")
+    bad.n_cols, bad.n_rows, bad.ld = 10, 10, 10
+    assert code(lambda: coot.validate(None, -1, x, [bad], O)) == -2                                   # linspace is a vector
+    g = coot.eye(10, 20)
+    g.ptr = G
+    assert code(lambda: coot.validate(None, -1, x, [g], O)) == -10                                    # generator with memory
+    g = coot.eye(10, 20)
+    g.flags |= coot.GEN_FILL
+    assert code(lambda: coot.validate(None, -1, x, [g], O)) == -10                                    # two kinds
+    assert code(lambda: coot.validate(None, -1, x + 1.0, [A], coot.eye(10, 20))) == -10              # not an output
+    # views: a diagonal is 1 x n with ld + 1, a submatrix keeps the parent's ld
+    M = F(10, 20, ptr=G)
+    d = coot.diag(M, 3)
+    assert (d.n_rows, d.n_cols, d.ld, d.ptr) == (1, 10, 11, G + 3 * 10 * 4)
+    d = coot.diag(M, -4)
+    assert (d.n_rows, d.n_cols, d.ld, d.ptr) == (1, 6, 11, G + 4 * 4)
+    s = coot.submat(M, 2, 3, 5, 9)
+    assert (s.n_rows, s.n_cols, s.ld, s.ptr) == (4, 7, 10, G + (2 + 3 * 10) * 4)
+    assert code(lambda: coot.validate(None, -1, x + 1.0, [s], s)) == 0                                # in place
+    assert code(lambda: coot.validate(None, -1, x + 1.0, [coot.submat(M, 2, 4, 5, 10)], s)) == -4    # overlap
+
+
 def test_bad_config_rejected():
     A = F(10, 20, ptr=G)
     O = F(10, 20, ptr=3 * G)
