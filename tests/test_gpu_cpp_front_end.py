@@ -1,0 +1,198 @@
+"""GPU parity of the C++ expression-template front end (include/coot.hpp, the
+paper's Section 7 interface): the cases in tests/cpp/front_end_cases.cpp run
+front-end expressions on device memory owned here, and the results are
+compared with the CPU oracle (same gates as the binding's tests) and, for the
+small workload, with the Python binding's own call of the same tree (the same
+fused kernel: identical bits)."""
+import ctypes as C
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+
+from gpu_util import dev, empty, host, need_gpu, same, torch
+
+pytestmark = pytest.mark.gpu
+
+from paper_2308_03120_amd import coot  # noqa: E402
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+FE = os.path.join(ROOT, "tests", "cpp", "libcoot_front_end_cases.so")
+vp, i64, dbl = C.c_void_p, C.c_int64, C.c_double
+
+
+@pytest.fixture(scope="module")
+def fe():
+    need_gpu()
+    coot.init(0)
+    coot.lib()
+    assert os.path.exists(FE), "tests/cpp/libcoot_front_end_cases.so is missing: run __graft_entry__.build()"
+    L = C.CDLL(FE)
+    L.fe_last_error.restype = C.c_char_p
+    sig = {"fe_small": [vp] * 5 + [i64, i64, vp, vp, vp, vp], "fe_in_place": [vp, vp, i64, vp],
+           "fe_views": [vp, i64, i64, i64, vp, i64, vp, vp], "fe_generators": [vp, i64, i64, vp, i64, dbl, dbl, vp, vp],
+           "fe_scalars": [vp, vp, i64, vp, vp], "fe_convert": [vp, vp, i64, i64, vp, vp, vp],
+           "fe_owned": [vp, i64, i64, vp, vp], "fe_shape_error": [vp, vp, vp]}
+    for name, args in sig.items():
+        getattr(L, name).argtypes = args
+    return L
+
+
+def stream():
+    return torch.cuda.current_stream().cuda_stream
+
+
+def ptr(t):
+    return t.data_ptr()
+
+
+def run(L, name, *args):
+    rc = getattr(L, name)(*args, stream())
+    assert rc == 0, L.fe_last_error().decode()
+
+
+@pytest.fixture(scope="module")
+def g():
+    return np.random.default_rng(9292)
+
+
+def test_small_workload(fe):
+    mats = synth.cfg1_inputs(67, 45)
+    names = "ABCD"
+    D = [dev(mats[k]) for k in names]
+    Y = empty(67, 45)
+    colsum = torch.empty(45, device="cuda")
+    s = torch.empty(1, device="cuda")
+    idx = torch.empty(1, dtype=torch.int64, device="cuda")
+    run(fe, "fe_small", *[ptr(t) for t in D], ptr(Y), 67, 45, ptr(colsum), ptr(s), ptr(idx))
+    trees = synth.cfg1_trees()
+    ops = [mats[k] for k in names]
+    # the binding's call of the same tree runs the same fused kernel
+    Y2 = empty(67, 45)
+    coot.eval(trees["Y"], D, Y2)
+    torch.cuda.synchronize()
+    assert same(host(Y), host(Y2))
+    ex, S = oracle.evaluate(trees["Y"].postfix(), ops, "exact", scale=True)
+    assert np.max(np.abs(host(Y) - ex) / np.maximum(S, 1e-300)) <= 1e-6
+    o, _, _ = oracle.reduce("accu", trees["accu_AB"].postfix(), ops)
+    assert abs(s.item() - o[0]) <= 1e-6 * abs(o[0])
+    oc, _, asum = oracle.reduce("sum", synth.leaf(0).postfix(), [mats["A"]], dim=0)
+    err = np.abs(colsum.double().cpu().numpy() - oc)
+    assert np.all((err <= 1e-6 * np.abs(oc)) | (err <= 1e-6 * asum))
+    _, oi, _ = oracle.reduce("index_max", trees["absB"].postfix(), ops, mode="emu")
+    assert idx.item() == oi[0]
+
+
+def test_in_place_updates(fe, g):
+    n = 300
+    A = g.uniform(-1, 1, (n, n)).astype(np.float32)
+    B = g.uniform(-1, 1, (n, n)).astype(np.float32)
+    dA, dB = dev(synth.Mat(np.asfortranarray(A), "f32")), dev(synth.Mat(np.asfortranarray(B), "f32"))
+    run(fe, "fe_in_place", ptr(dA), ptr(dB), n)
+    a = (A.T + np.float32(1.0)).astype(np.float32)
+    b = B + a
+    b = b * a
+    b = b * np.float32(0.5)
+    b = b - np.float32(1.0)
+    assert np.array_equal(host(dA), a.astype(np.float64))
+    assert np.array_equal(host(dB), b.astype(np.float64))
+
+
+@pytest.mark.parametrize("k", [0, 4, -3])
+def test_views(fe, g, k):
+    r, c = 50, 40
+    A = g.uniform(-1, 1, (r, c))
+    dA = dev(synth.Mat(np.asfortranarray(A), "f64"))
+    nd = np.diagonal(A, k).size
+    dv = torch.empty(nd, dtype=torch.float64, device="cuda")
+    t = torch.empty(1, dtype=torch.float64, device="cuda")
+    run(fe, "fe_views", ptr(dA), r, c, k, ptr(dv), nd, ptr(t))
+    W = A.copy()
+    W[np.arange(min(r, c)), np.arange(min(r, c))] += 1.0
+    W[1:4, 1:4] = 2.0 * W[0:3, 0:3].copy()        # the right side is read before the write
+    W[r - 1, :] = W[0, :] - W[1, :]
+    W[:, c - 1] = 7.0
+    got = host(dA)
+    assert np.array_equal(got, W)
+    assert np.array_equal(dv.cpu().numpy(), np.diagonal(W, k))
+    d = np.diagonal(W)
+    assert abs(t.item() - np.trace(W)) <= 1e-13 * np.sum(np.abs(d))
+
+
+def test_generators(fe):
+    r, c, n = 37, 29, 1001
+    Y = empty(r, c)
+    L = torch.empty(n, dtype=torch.float64, device="cuda")
+    H = np.empty((c, r), np.float32)                  # host, column-major r x c
+    run(fe, "fe_generators", ptr(Y), r, c, ptr(L), n, -1.25, 3.5, H.ctypes.data)
+    E = np.eye(r, c)
+    assert np.array_equal(host(Y), 3.0 * E + 1.0 + E)
+    assert np.array_equal(L.cpu().numpy(), oracle.linspace_values(-1.25, 3.5, n))
+    assert np.array_equal(H.T, E.astype(np.float32))
+
+
+def test_scalar_functions(fe, g):
+    n = 100003
+    x = g.uniform(-2, 2, n)
+    y = g.uniform(-2, 2, n)
+    res = torch.empty(14, dtype=torch.float64)        # host
+    dx, dy = dev(x), dev(y)
+    run(fe, "fe_scalars", ptr(dx), ptr(dy), n, res.data_ptr())
+    r = res.numpy()
+    X, Y = synth.Mat(np.asfortranarray(x.reshape(-1, 1)), "f64"), synth.Mat(np.asfortranarray(y.reshape(-1, 1)), "f64")
+    a, b = synth.leaves(2)
+
+    def close(v, op, tree, ops, tol=1e-13):
+        o, _, s = oracle.reduce(op, tree.postfix(), ops)
+        assert abs(v - o[0]) <= tol * max(abs(o[0]), s[0]), (op, v, o[0])
+
+    close(r[0], "dot", a % b, [X, Y])
+    close(r[1], "norm2", a, [X])
+    close(r[2], "norm1", a, [X])
+    assert r[3] == np.max(np.abs(x)) and r[4] == np.min(np.abs(x))
+    assert r[5] == x.max() and r[6] == np.min(x * y)
+    assert r[7] == np.argmin(x) and r[8] == np.argmax(x - y)
+    close(r[9], "mean", a, [X])
+    assert abs(r[10] - np.var(x, ddof=1)) <= 1e-12 * np.var(x, ddof=1)
+    assert r[11] == np.count_nonzero(x > 0.3)
+    assert r[12] == 1.0 and r[13] == 0.0
+
+
+def test_fused_conversion_and_dim_statistics(fe, g):
+    r, c = 300, 77
+    X = g.uniform(-1, 1, (r, c))
+    dX = dev(synth.Mat(np.asfortranarray(X), "f64"))
+    F = empty(r, c)
+    cm = torch.empty(c, device="cuda")
+    rv = torch.empty(r, device="cuda")
+    run(fe, "fe_convert", ptr(dX), ptr(F), r, c, ptr(cm), ptr(rv))
+    f = (2.0 * X + 1.0).astype(np.float32)            # one rounding, after the FP64 arithmetic
+    assert np.array_equal(host(F), f.astype(np.float64))
+    Fm = synth.Mat(np.asfortranarray(f), "f32")
+    om, _, sm = oracle.reduce("mean", synth.leaf(0).postfix(), [Fm], dim=0)
+    err = np.abs(cm.double().cpu().numpy() - om)
+    assert np.all((err <= 1e-6 * np.abs(om)) | (err <= 1e-6 * sm))
+    ov, _, _ = oracle.reduce("var", synth.leaf(0).postfix(), [Fm], dim=1)
+    assert np.all(np.abs(rv.double().cpu().numpy() - ov) <= 2e-7 * np.abs(ov))
+
+
+def test_owned_matrices(fe, g):
+    r, c = 23, 31
+    A = g.uniform(-1, 1, (r, c)).astype(np.float32)
+    Hin = np.asfortranarray(A)
+    H = np.empty((c, r), np.float32)
+    run(fe, "fe_owned", Hin.ctypes.data, r, c, H.ctypes.data)
+    b = A * np.float32(2.0) + np.float32(1.0)
+    want = b * A - A
+    assert np.array_equal(H.T, want)
+
+
+def test_errors_become_exceptions(fe):
+    A = torch.zeros(20, device="cuda")
+    B = torch.zeros(20, device="cuda")
+    rc = fe.fe_shape_error(ptr(A), ptr(B), stream())
+    assert rc == -1
+    assert "shape" in fe.fe_last_error().decode()
