@@ -34,7 +34,7 @@ OPS = {
     "trunc": 37, "sign": 38, "cos": 39, "sin": 40, "tan": 41, "acos": 42, "asin": 43, "atan": 44, "cosh": 45,
     "sinh": 46, "tanh": 47,
 }
-TYPES = {"f32": 0, "f64": 1, "f16": 2, "bf16": 3}
+TYPES = {"f32": 0, "f64": 1, "f16": 2, "bf16": 3, "i32": 5, "u32": 6}
 MODES = {"exact": 0, "emu": 1}
 REDS = {
     "accu": 0, "sum": 1, "dot": 2, "norm1": 3, "norm2": 4, "norminf": 5, "normneginf": 6,

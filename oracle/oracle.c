@@ -58,7 +58,7 @@ enum {
     OR_NOPS
 };
 
-enum { TY_F32 = 0, TY_F64 = 1, TY_F16 = 2, TY_BF16 = 3 };
+enum { TY_F32 = 0, TY_F64 = 1, TY_F16 = 2, TY_BF16 = 3, TY_I32 = 5, TY_U32 = 6 };
 
 enum { MODE_EXACT = 0, MODE_EMU = 1 };
 
@@ -114,8 +114,23 @@ static double leaf_at(const or_leaf* L, int64_t r, int64_t c)
     case TY_F64: return ((const double*)L->data)[off];
     case TY_F16: return widen_f16(((const uint16_t*)L->data)[off]);
     case TY_BF16: return widen_bf16(((const uint16_t*)L->data)[off]);
+    case TY_I32: return (double)((const int32_t*)L->data)[off];   /* exact in FP64 */
+    case TY_U32: return (double)((const uint32_t*)L->data)[off];
     }
     return NAN;
+}
+
+/* ---- conversion to a 32-bit integer type (reading of the paper's integer
+ * matrices: a value is converted by dropping its fraction (toward zero), then
+ * clamping to the type's range; NaN becomes 0).  lo and hi are the range
+ * ends, both exact in FP64. */
+static double to_integer(double x, double lo, double hi)
+{
+    if (isnan(x)) return 0.0;
+    double t = trunc(x);
+    if (t < lo) return lo;
+    if (t > hi) return hi;
+    return t;
 }
 
 /* ---- rounding to a storage type (round to nearest, ties to even) ------- */
@@ -143,6 +158,8 @@ double oracle_round_to(int dtype, double x)
     case TY_F32: return (double)(float)x;
     case TY_F16: return round_format(x, 10, -14, 65504.0);
     case TY_BF16: return round_format(x, 7, -126, ldexp(255.0, 120));  /* (2 - 2^-7) * 2^127 */
+    case TY_I32: return to_integer(x, -2147483648.0, 2147483647.0);
+    case TY_U32: return to_integer(x, 0.0, 4294967295.0);
     }
     return NAN;
 }
@@ -167,7 +184,8 @@ typedef struct {
 
 /* Shape and precision of every node.  Returns OK or an error code.
  * Precision rule (reading): F64 leaves compute in FP64; F32, F16 and BF16
- * leaves compute in FP32 (16-bit storage is widened exactly).  A binary node
+ * leaves compute in FP32 (16-bit storage is widened exactly); I32 and U32
+ * leaves widen exactly to FP64 and compute there.  A binary node
  * needs equal shapes and equal precision (Armadillo/Bandicoot need the same
  * element type on both sides; 16-bit and F32 data share FP32).  conv(t)
  * rounds to t and continues in FP64 if t is F64, else in FP32. */
@@ -181,7 +199,8 @@ static int infer(const or_node* nd, int nn, const or_leaf* lv, int nl, node_info
             const or_leaf* L = &lv[nd[i].a];
             info[i].rows = L->rows;
             info[i].cols = L->cols;
-            info[i].prec = L->dtype == TY_F64 ? 64 : 32;
+            /* 32-bit integers widen exactly to FP64 and compute there */
+            info[i].prec = (L->dtype == TY_F64 || L->dtype == TY_I32 || L->dtype == TY_U32) ? 64 : 32;
             continue;
         }
         if (op < 0 || op >= OR_NOPS) return E_TREE;
@@ -198,9 +217,9 @@ static int infer(const or_node* nd, int nn, const or_leaf* lv, int nl, node_info
             info[i].cols = A.rows;
             info[i].prec = A.prec;
         } else if (op == OR_CONV) {
-            if (nd[i].b < 0 || nd[i].b > TY_BF16) return E_TREE;
+            if (nd[i].b < 0 || nd[i].b > TY_U32 || nd[i].b == 4) return E_TREE;
             info[i] = A;
-            info[i].prec = nd[i].b == TY_F64 ? 64 : 32;
+            info[i].prec = (nd[i].b == TY_F64 || nd[i].b == TY_I32 || nd[i].b == TY_U32) ? 64 : 32;
         } else {
             info[i] = A;
         }

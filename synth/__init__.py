@@ -83,6 +83,12 @@ def store(draws: np.ndarray, dtype: str) -> np.ndarray:
         if draws.ndim == 2:
             return np.asarray(bits.reshape(draws.shape, order="F"), order="F")
         return bits.copy()
+    if dtype in ("i32", "u32"):
+        # integer draws only (the test inputs are integer-valued): stored exactly
+        info = np.iinfo(np.int32 if dtype == "i32" else np.uint32)
+        if not (np.all(draws == np.round(draws)) and np.all(draws >= info.min) and np.all(draws <= info.max)):
+            raise ValueError(f"{dtype} storage takes integer draws within range")
+        return np.asarray(draws.astype(np.int32 if dtype == "i32" else np.uint32), order=order)
     raise ValueError(dtype)
 
 
@@ -108,7 +114,7 @@ BINARY = ("plus", "minus", "schur", "div")
 SCALAR = ("scal_plus", "scal_minus_post", "scal_minus_pre", "scal_times",
           "scal_div_post", "scal_div_pre")
 ALL_OPS = ("leaf",) + BINARY + SCALAR + UNARY + ("conv",)
-CONV_TARGET = {"f32": 0, "f64": 1, "f16": 2, "bf16": 3}
+CONV_TARGET = {"f32": 0, "f64": 1, "f16": 2, "bf16": 3, "i32": 5, "u32": 6}
 
 
 class E:
