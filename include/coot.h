@@ -64,7 +64,12 @@ typedef enum coot_dtype {
     COOT_F64 = 1,
     COOT_F16 = 2,
     COOT_BF16 = 3,
-    COOT_U64 = 4
+    COOT_U64 = 4,
+    COOT_I32 = 5,   /* 32-bit integers (Section 2 element types): they widen   */
+    COOT_U32 = 6    /* exactly to FP64 and trees with them compute in FP64;    */
+                    /* a value converted to an integer type (an output or a    */
+                    /* conversion node) drops its fraction toward zero, is    */
+                    /* clamped to the type's range, and NaN becomes 0          */
 } coot_dtype;
 
 /* ------------------------------------------------------------- operands -- */

@@ -77,6 +77,19 @@ template <>
 struct dtype_of<double> {
     static constexpr int value = COOT_F64;
 };
+template <>
+struct dtype_of<int32_t> {
+    static constexpr int value = COOT_I32;
+};
+template <>
+struct dtype_of<uint32_t> {
+    static constexpr int value = COOT_U32;
+};
+
+// type of a reduction's result: integer trees reduce in FP64 (exact sums
+// below 2^53), floating-point trees in their own type
+template <class eT>
+using red_t = std::conditional_t<std::is_integral<eT>::value, double, eT>;
 
 // ------------------------------------------------------- flattening context
 // The postfix node array and operand table of one call.  A matrix read twice
@@ -259,8 +272,9 @@ R reduce_host(int red_op, const T1& X, int out_dt)
 // ------------------------------------------------------------------- Mat
 template <class eT>
 class Mat : public Base<eT, Mat<eT>> {
-    static_assert(std::is_same<eT, float>::value || std::is_same<eT, double>::value,
-                  "Mat<eT>: eT is float or double");
+    static_assert(std::is_same<eT, float>::value || std::is_same<eT, double>::value ||
+                      std::is_same<eT, int32_t>::value || std::is_same<eT, uint32_t>::value,
+                  "Mat<eT>: eT is float, double, int32_t or uint32_t");
 
 public:
     Mat() = default;
@@ -480,6 +494,14 @@ using fcolvec = Col<float>;
 using colvec = Col<double>;
 using frowvec = Row<float>;
 using rowvec = Row<double>;
+// 32-bit integer matrices: values widen exactly to FP64 for the arithmetic;
+// storing into them drops the fraction toward zero and clamps to the range
+using imat = Mat<int32_t>;
+using umat = Mat<uint32_t>;
+using ivec = Col<int32_t>;
+using uvec = Col<uint32_t>;
+using irowvec = Row<int32_t>;
+using urowvec = Row<uint32_t>;
 
 // --------------------------------------------------------------- subview
 // A view into a matrix: a strided operand (ptr, shape, ld) that is both a leaf
@@ -708,41 +730,42 @@ eOp<T1, COOT_SCAL_POW> pow(const Base<eT, T1>& a, S k)
 
 // ------------------------------------------------ scalar-valued functions
 template <class eT, class T1>
-eT accu(const Base<eT, T1>& X)
+red_t<eT> accu(const Base<eT, T1>& X)
 {
-    return detail::reduce_host<eT>(COOT_RED_ACCU, X.get_ref(), dtype_of<eT>::value);
+    return detail::reduce_host<red_t<eT>>(COOT_RED_ACCU, X.get_ref(), dtype_of<red_t<eT>>::value);
 }
 template <class eT, class T1, class T2>
-eT dot(const Base<eT, T1>& A, const Base<eT, T2>& B)
+red_t<eT> dot(const Base<eT, T1>& A, const Base<eT, T2>& B)
 {
-    return detail::reduce_host<eT>(COOT_RED_DOT, eGlue<T1, T2, COOT_SCHUR>(A.get_ref(), B.get_ref()),
-                                   dtype_of<eT>::value);
+    return detail::reduce_host<red_t<eT>>(COOT_RED_DOT, eGlue<T1, T2, COOT_SCHUR>(A.get_ref(), B.get_ref()),
+                                          dtype_of<red_t<eT>>::value);
 }
 // norm(X, p): p = 1 or 2, or "inf", "-inf", "fro" (Table 5)
 template <class eT, class T1>
-eT norm(const Base<eT, T1>& X, int p = 2)
+red_t<eT> norm(const Base<eT, T1>& X, int p = 2)
 {
     if (p != 1 && p != 2) throw std::runtime_error("coot: norm(X, p) takes p = 1 or 2");
-    return detail::reduce_host<eT>(p == 1 ? COOT_RED_NORM1 : COOT_RED_NORM2, X.get_ref(), dtype_of<eT>::value);
+    return detail::reduce_host<red_t<eT>>(p == 1 ? COOT_RED_NORM1 : COOT_RED_NORM2, X.get_ref(),
+                                          dtype_of<red_t<eT>>::value);
 }
 template <class eT, class T1>
-eT norm(const Base<eT, T1>& X, const char* p)
+red_t<eT> norm(const Base<eT, T1>& X, const char* p)
 {
     const std::string s(p);
     const int op = s == "inf" ? COOT_RED_NORMINF
                               : (s == "-inf" ? COOT_RED_NORMNEGINF : (s == "fro" ? COOT_RED_NORM2 : -1));
     if (op < 0) throw std::runtime_error("coot: norm(X, p) takes \"inf\", \"-inf\" or \"fro\"");
-    return detail::reduce_host<eT>(op, X.get_ref(), dtype_of<eT>::value);
+    return detail::reduce_host<red_t<eT>>(op, X.get_ref(), dtype_of<red_t<eT>>::value);
 }
 template <class eT, class T1>
-eT min(const Base<eT, T1>& X)
+red_t<eT> min(const Base<eT, T1>& X)
 {
-    return detail::reduce_host<eT>(COOT_RED_MIN, X.get_ref(), dtype_of<eT>::value);
+    return detail::reduce_host<red_t<eT>>(COOT_RED_MIN, X.get_ref(), dtype_of<red_t<eT>>::value);
 }
 template <class eT, class T1>
-eT max(const Base<eT, T1>& X)
+red_t<eT> max(const Base<eT, T1>& X)
 {
-    return detail::reduce_host<eT>(COOT_RED_MAX, X.get_ref(), dtype_of<eT>::value);
+    return detail::reduce_host<red_t<eT>>(COOT_RED_MAX, X.get_ref(), dtype_of<red_t<eT>>::value);
 }
 template <class eT, class T1>
 uword index_min(const Base<eT, T1>& X)
@@ -766,23 +789,23 @@ bool any(const Base<eT, T1>& X)
 }
 // statistics over all elements (the vector forms of Table 6)
 template <class eT, class T1>
-eT mean(const Base<eT, T1>& X)
+red_t<eT> mean(const Base<eT, T1>& X)
 {
-    return detail::reduce_host<eT>(COOT_RED_MEAN, X.get_ref(), dtype_of<eT>::value);
+    return detail::reduce_host<red_t<eT>>(COOT_RED_MEAN, X.get_ref(), dtype_of<red_t<eT>>::value);
 }
 template <class eT, class T1>
-eT var(const Base<eT, T1>& X)
+red_t<eT> var(const Base<eT, T1>& X)
 {
-    return detail::reduce_host<eT>(COOT_RED_VAR, X.get_ref(), dtype_of<eT>::value);
+    return detail::reduce_host<red_t<eT>>(COOT_RED_VAR, X.get_ref(), dtype_of<red_t<eT>>::value);
 }
 template <class eT, class T1>
-eT stddev(const Base<eT, T1>& X)
+red_t<eT> stddev(const Base<eT, T1>& X)
 {
-    return detail::reduce_host<eT>(COOT_RED_STDDEV, X.get_ref(), dtype_of<eT>::value);
+    return detail::reduce_host<red_t<eT>>(COOT_RED_STDDEV, X.get_ref(), dtype_of<red_t<eT>>::value);
 }
 // trace(A): the sum of the leading diagonal
 template <class eT>
-eT trace(const Mat<eT>& A)
+red_t<eT> trace(const Mat<eT>& A)
 {
     return accu(A.diag());
 }
@@ -792,10 +815,10 @@ eT trace(const Mat<eT>& A)
 // 1: per row -> n_rows x 1), Table 6; the result is a new matrix
 namespace detail {
 template <class eT, class T1>
-Mat<eT> reduce_dim(int red_op, const T1& X, int dim)
+Mat<red_t<eT>> reduce_dim(int red_op, const T1& X, int dim)
 {
     if (dim != 0 && dim != 1) throw std::runtime_error("coot: dim is 0 or 1");
-    Mat<eT> out(dim == 0 ? 1 : X.n_rows(), dim == 0 ? X.n_cols() : 1);
+    Mat<red_t<eT>> out(dim == 0 ? 1 : X.n_rows(), dim == 0 ? X.n_cols() : 1);
     Flat f;
     X.flatten(f);
     const coot_expr e = f.expr();
@@ -808,7 +831,7 @@ Mat<eT> reduce_dim(int red_op, const T1& X, int dim)
 
 #define COOT_DIMRED(NAME, CODE)                                                                 \
     template <class eT, class T1>                                                               \
-    Mat<eT> NAME(const Base<eT, T1>& X, int dim)                                                \
+    Mat<red_t<eT>> NAME(const Base<eT, T1>& X, int dim)                                         \
     {                                                                                           \
         return detail::reduce_dim<eT>(CODE, X.get_ref(), dim);                                  \
     }

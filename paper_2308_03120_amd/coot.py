@@ -28,8 +28,8 @@ ERRORS = {
     -1: "BAD_TREE", -2: "SHAPE", -3: "DTYPE", -4: "ALIAS", -5: "EMPTY", -6: "UNSUPPORTED",
     -7: "JIT", -8: "HIP", -9: "NOMEM", -10: "ARG", -11: "NOT_INIT",
 }
-F32, F64, F16, BF16, U64 = 0, 1, 2, 3, 4
-DTYPE_CODES = {"f32": F32, "f64": F64, "f16": F16, "bf16": BF16, "u64": U64}
+F32, F64, F16, BF16, U64, I32, U32 = 0, 1, 2, 3, 4, 5, 6
+DTYPE_CODES = {"f32": F32, "f64": F64, "f16": F16, "bf16": BF16, "u64": U64, "i32": I32, "u32": U32}
 OPS = {
     "leaf": 0, "plus": 1, "minus": 2, "schur": 3, "div": 4,
     "scal_plus": 10, "scal_minus_post": 11, "scal_minus_pre": 12, "scal_times": 13,
@@ -50,7 +50,7 @@ U64_RESULTS = ("index_min", "index_max", "count", "all", "any")
 RED_PAIRWISE = 0x100
 OPERAND_HOST = 1
 GEN_FILL, GEN_EYE, GEN_LINSPACE = 0x10, 0x20, 0x40
-ITEMSIZE = {F32: 4, F64: 8, F16: 2, BF16: 2, U64: 8}
+ITEMSIZE = {F32: 4, F64: 8, F16: 2, BF16: 2, U64: 8, I32: 4, U32: 4}
 EXPR_UNFUSED = 1
 PRINT_INFO = 1
 TUNE_DEFAULT, TUNE_CACHE, TUNE_MODEL = 0, 1, 2
@@ -183,7 +183,8 @@ def _torch():
 
 def _dtype_code(t) -> int:
     torch = _torch()
-    m = {torch.float32: F32, torch.float64: F64, torch.float16: F16, torch.bfloat16: BF16, torch.int64: U64}
+    m = {torch.float32: F32, torch.float64: F64, torch.float16: F16, torch.bfloat16: BF16, torch.int64: U64,
+         torch.int32: I32, torch.uint32: U32}
     if t.dtype not in m:
         raise TypeError(f"unsupported tensor dtype {t.dtype}")
     return m[t.dtype]
@@ -415,13 +416,13 @@ def _root_shape(tree, operands):
         op, a, b = (n.op, n.a, n.b) if not isinstance(n, (tuple, list)) else (n[0], n[1], n[2])
         if op == "leaf" or op == 0:
             o = operand(operands[a])
-            info.append((o.n_rows, o.n_cols, 64 if o.dtype == F64 else 32))
+            info.append((o.n_rows, o.n_cols, 64 if o.dtype in (F64, I32, U32) else 32))
         elif op in ("trans", 30):
             r, c, p = info[a]
             info.append((c, r, p))
         elif op in ("conv", 31):
             r, c, p = info[a]
-            info.append((r, c, 64 if b == F64 else 32))
+            info.append((r, c, 64 if b in (F64, I32, U32) else 32))
         else:
             info.append(info[a])
     return info[-1]

@@ -373,12 +373,12 @@ static int run_unfused(int red_op, int dim, const coot_expr* expr, const coot_op
             val[i] = ops[N.a];
             R[i] = ops[N.a].n_rows;
             C[i] = ops[N.a].n_cols;
-            prec[i] = ops[N.a].dtype == COOT_F64 ? 64 : 32;
+            prec[i] = dtype_prec(ops[N.a].dtype);
             continue;
         }
         R[i] = N.op == COOT_TRANS ? C[N.a] : R[N.a];
         C[i] = N.op == COOT_TRANS ? R[N.a] : C[N.a];
-        prec[i] = N.op == COOT_CONV ? (N.b == COOT_F64 ? 64 : 32) : prec[N.a];
+        prec[i] = N.op == COOT_CONV ? dtype_prec(N.b) : prec[N.a];
         bool last = i == nn - 1;
         coot_node mini[3];
         int m = 0, nops = 0;

@@ -163,8 +163,10 @@ BatchTrees plan_batch(const coot_batch* b)
     const bool has_red = b->red_expr != nullptr;
     if (!has_out && !has_red) fail(COOT_ERR_ARG, "batch: neither outputs nor a reduction requested");
     for (int s = 0; s < b->n_slots; ++s)
-        if (!is_value_dtype(b->slot_dtypes[s])) fail(COOT_ERR_DTYPE, "batch: slot dtype");
-    if (has_out && !is_value_dtype(b->out_dtype)) fail(COOT_ERR_DTYPE, "batch: out dtype");
+        if (!is_value_dtype(b->slot_dtypes[s]) || b->slot_dtypes[s] == COOT_I32 || b->slot_dtypes[s] == COOT_U32)
+            fail(COOT_ERR_DTYPE, "batch: slot dtype (f32, f64, f16 or bf16)");
+    if (has_out && (!is_value_dtype(b->out_dtype) || b->out_dtype == COOT_I32 || b->out_dtype == COOT_U32))
+        fail(COOT_ERR_DTYPE, "batch: out dtype (f32, f64, f16 or bf16)");
     if (has_red) {
         const int base = b->red_op & 0xff;
         if ((b->red_op & ~(0xff | COOT_RED_PAIRWISE)) ||

@@ -26,6 +26,8 @@ static const char* stype(int dt)
     switch (dt) {
     case COOT_F32: return "float";
     case COOT_F64: return "double";
+    case COOT_I32: return "int";
+    case COOT_U32: return "unsigned";
     default: return "u16";
     }
 }
@@ -34,6 +36,7 @@ static std::string widen(int dt, const std::string& e)
 {
     if (dt == COOT_F16) return "widen_f16(" + e + ")";
     if (dt == COOT_BF16) return "widen_bf16(" + e + ")";
+    if (dt == COOT_I32 || dt == COOT_U32) return "(double)(" + e + ")";
     return e;
 }
 
@@ -45,6 +48,8 @@ static std::string narrow(int out_dt, int prec, const std::string& e)
     case COOT_F64: return "(double)(" + e + ")";
     case COOT_F16: return (prec == 64 ? "bits_f16_d(" : "bits_f16(") + e + ")";
     case COOT_BF16: return (prec == 64 ? "bits_bf16_d(" : "bits_bf16(") + e + ")";
+    case COOT_I32: return "sat_i32((double)(" + e + "))";
+    case COOT_U32: return "sat_u32((double)(" + e + "))";
     }
     return e;
 }
@@ -85,6 +90,8 @@ static std::string gen_value(const PNode& n)
     case COOT_F64: return v;
     case COOT_F32: return "(float)" + v;
     case COOT_F16: return "rnd_f16_d(" + v + ")";
+    case COOT_I32: return "(double)sat_i32(" + v + ")";
+    case COOT_U32: return "(double)sat_u32(" + v + ")";
     default: return "rnd_bf16_d(" + v + ")";
     }
 }
@@ -98,7 +105,7 @@ static std::string emit_eval(const Plan& p, bool pair, const std::string& pfx = 
     std::ostringstream args;
     for (size_t j = 0; j < p.reads.size(); ++j) {
         if (j) args << ", ";
-        args << ctype(p.reads[j].dtype == COOT_F64 ? 64 : 32) << " l" << j;
+        args << ctype(dtype_prec(p.reads[j].dtype)) << " l" << j;
     }
     // generators that depend on the element take its linear index, row and column
     if (p.gen_index) args << (p.reads.empty() ? "" : ", ") << "const i64 gi_, const i64 gr_, const i64 gc_";
@@ -176,6 +183,8 @@ static std::string emit_eval(const Plan& p, bool pair, const std::string& pfx = 
             case COOT_F64: e = "(double)" + a; break;
             case COOT_F16: e = (cp == 64 ? "rnd_f16_d(" : "rnd_f16(") + a + ")"; break;
             case COOT_BF16: e = (cp == 64 ? "rnd_bf16_d(" : "rnd_bf16(") + a + ")"; break;
+            case COOT_I32: e = "(double)sat_i32((double)" + a + ")"; break;
+            case COOT_U32: e = "(double)sat_u32((double)" + a + ")"; break;
             }
             break;
         }
@@ -518,7 +527,7 @@ static TilePlan tile_plan(const Plan& p)
     int budget = 96 * 1024;
     for (size_t j = 0; j < p.reads.size(); ++j) {
         if (!p.reads[j].trans) continue;
-        int bytes = COOT_TILE_LDS * (p.reads[j].dtype == COOT_F64 ? 8 : 4);
+        int bytes = COOT_TILE_LDS * (dtype_prec(p.reads[j].dtype) == 64 ? 8 : 4);
         if (bytes <= budget) {
             t.in_lds[j] = true;
             budget -= bytes;
@@ -533,7 +542,7 @@ static std::string tile_shared_decls(const Plan& p, const TilePlan& tp, const st
     std::ostringstream s;
     for (size_t j = 0; j < p.reads.size(); ++j)
         if (tp.in_lds[j])
-            s << ind << "__shared__ " << ctype(p.reads[j].dtype == COOT_F64 ? 64 : 32) << " T" << j << "[COOT_TILE_LDS];\n";
+            s << ind << "__shared__ " << ctype(dtype_prec(p.reads[j].dtype)) << " T" << j << "[COOT_TILE_LDS];\n";
     return s.str();
 }
 
@@ -554,7 +563,7 @@ static std::string tile_regs(const Plan& p, const TilePlan& tp, const std::strin
 {
     std::ostringstream s;
     for (size_t j = 0; j < p.reads.size(); ++j) {
-        const std::string C = ctype(p.reads[j].dtype == COOT_F64 ? 64 : 32);
+        const std::string C = ctype(dtype_prec(p.reads[j].dtype));
         if (tp.in_lds[j]) s << ind << C << " pt" << j << "[16];\n";
         else s << ind << C << " pr" << j << "[16], cr" << j << "[16];\n";
     }
@@ -595,7 +604,7 @@ static std::string tile_prefetch_sq(const Plan& p, const TilePlan& tp, const std
     o << in << "#pragma unroll\n" << in << "    for (int kk = 0; kk < 16; ++kk) {\n";
     o << in << "        const int q = w + 4 * kk;\n";
     for (size_t j = 0; j < p.reads.size(); ++j) {
-        const std::string J = std::to_string(j), C = ctype(p.reads[j].dtype == COOT_F64 ? 64 : 32);
+        const std::string J = std::to_string(j), C = ctype(dtype_prec(p.reads[j].dtype));
         if (tp.in_lds[j])
             o << in << "        pt" << J << "[kk] = q < pri ? " << widen(p.reads[j].dtype, ldf + "(a" + J + " + lnc)") << " : (" << C
               << ")0;\n";
@@ -786,7 +795,7 @@ static std::string tile_prefetch_gen(const Plan& p, const TilePlan& tp, const st
         o << i4 << "const bool av = aok && (" << v.lc << " <= 6 ? ai < prr - asr : aj < pcc - asc);\n";
     }
     for (size_t j = 0; j < p.reads.size(); ++j) {
-        const std::string J = std::to_string(j), C = ctype(p.reads[j].dtype == COOT_F64 ? 64 : 32);
+        const std::string J = std::to_string(j), C = ctype(dtype_prec(p.reads[j].dtype));
         if (tp.in_lds[j])
             o << i4 << "pt" << J << "[kk] = au ? " << widen(p.reads[j].dtype, ldf + "(" + lane_addr("a" + J, "av", "v" + J, off32) + ")")
               << " : (" << C << ")0;\n";

@@ -61,6 +61,21 @@ CD float rnd_f16(float f) { return widen_f16(bits_f16(f)); }
 CD float rnd_bf16_d(double d) { return widen_bf16(bits_bf16_d(d)); }
 CD float rnd_f16_d(double d) { return widen_f16(bits_f16_d(d)); }
 
+/* FP64 -> 32-bit integer: the fraction dropped toward zero, the result
+ * clamped to the type's range, NaN -> 0 */
+CD int sat_i32(double x)
+{
+    if (x != x) return 0;
+    x = __builtin_trunc(x);
+    return x <= -2147483648.0 ? (int)0x80000000u : (x >= 2147483647.0 ? 0x7fffffff : (int)x);
+}
+CD unsigned sat_u32(double x)
+{
+    if (x != x) return 0u;
+    x = __builtin_trunc(x);
+    return x <= 0.0 ? 0u : (x >= 4294967295.0 ? 0xffffffffu : (unsigned)x);
+}
+
 /* ------------------------------------------------------------------ */
 /* vector loads / stores of VE consecutive elements                     */
 /* ------------------------------------------------------------------ */

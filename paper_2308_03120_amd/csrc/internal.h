@@ -19,7 +19,10 @@ struct Error {
 void set_error(int code, const std::string& msg);
 
 int itemsize(int dtype);
-bool is_value_dtype(int dtype);  // F32, F64, F16, BF16
+bool is_value_dtype(int dtype);  // F32, F64, F16, BF16, I32, U32
+// compute precision of a tree leaf stored as dtype: FP64 for F64 and the
+// 32-bit integers (exact), FP32 for F32 and the 16-bit floats
+inline int dtype_prec(int dt) { return (dt == COOT_F64 || dt == COOT_I32 || dt == COOT_U32) ? 64 : 32; }
 const char* dtype_name(int dtype);
 
 // ----------------------------------------------------------------- planning

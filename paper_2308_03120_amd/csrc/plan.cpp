@@ -34,11 +34,16 @@ int itemsize(int dt)
     case COOT_F16: return 2;
     case COOT_BF16: return 2;
     case COOT_U64: return 8;
+    case COOT_I32: return 4;
+    case COOT_U32: return 4;
     }
     return 0;
 }
 
-bool is_value_dtype(int dt) { return dt == COOT_F32 || dt == COOT_F64 || dt == COOT_F16 || dt == COOT_BF16; }
+bool is_value_dtype(int dt)
+{
+    return dt == COOT_F32 || dt == COOT_F64 || dt == COOT_F16 || dt == COOT_BF16 || dt == COOT_I32 || dt == COOT_U32;
+}
 
 const char* dtype_name(int dt)
 {
@@ -48,6 +53,8 @@ const char* dtype_name(int dt)
     case COOT_F16: return "f16";
     case COOT_BF16: return "bf16";
     case COOT_U64: return "u64";
+    case COOT_I32: return "i32";
+    case COOT_U32: return "u32";
     }
     return "?";
 }
@@ -181,10 +188,10 @@ Plan make_plan(int red_op_in, int dim, const coot_expr* expr, const coot_operand
             if (!slot_checked[N.a]) {
                 std::string w = "operand " + std::to_string(N.a);
                 check_operand(o, w.c_str(), false);
-                if (!is_value_dtype(o.dtype)) fail(COOT_ERR_DTYPE, w + ": dtype must be f32, f64, f16 or bf16");
+                if (!is_value_dtype(o.dtype)) fail(COOT_ERR_DTYPE, w + ": dtype must be f32, f64, f16, bf16, i32 or u32");
                 slot_checked[N.a] = 1;
             }
-            info[i] = {o.n_rows, o.n_cols, o.dtype == COOT_F64 ? 64 : 32};
+            info[i] = {o.n_rows, o.n_cols, dtype_prec(o.dtype)};
             continue;
         }
         bool bin = is_binary(N.op), sc = is_scalar(N.op), un = is_unary(N.op);
@@ -201,7 +208,7 @@ Plan make_plan(int red_op_in, int dim, const coot_expr* expr, const coot_operand
             info[i] = A;
         } else if (N.op == COOT_CONV) {
             if (!is_value_dtype(N.b)) fail(COOT_ERR_BAD_TREE, at() + ": conversion target must be a value dtype");
-            info[i] = {A.rows, A.cols, N.b == COOT_F64 ? 64 : 32};
+            info[i] = {A.rows, A.cols, dtype_prec(N.b)};
         } else {
             if (N.b != -1) fail(COOT_ERR_BAD_TREE, at() + ": b must be -1 for a unary or scalar node");
             if (N.op == COOT_TRANS)
@@ -220,7 +227,7 @@ Plan make_plan(int red_op_in, int dim, const coot_expr* expr, const coot_operand
     check_operand(*out, "out", true);
     if (P.red_op < 0) {
         if (out->flags & COOT_OPERAND_HOST) fail(COOT_ERR_ARG, "out: element-wise results must be device memory");
-        if (!is_value_dtype(out->dtype)) fail(COOT_ERR_DTYPE, "out: dtype must be f32, f64, f16 or bf16");
+        if (!is_value_dtype(out->dtype)) fail(COOT_ERR_DTYPE, "out: dtype must be f32, f64, f16, bf16, i32 or u32");
         if (out->n_rows != P.rows || out->n_cols != P.cols)
             fail(COOT_ERR_SHAPE, "out is " + shape_str(out->n_rows, out->n_cols) + ", the expression is " +
                                      shape_str(P.rows, P.cols));

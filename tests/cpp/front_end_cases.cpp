@@ -144,6 +144,24 @@ int fe_owned(const float* Hin, int64_t r, int64_t c, float* H, void* stream)
     });
 }
 
+// 32-bit integer vectors a, b (n elements): F = conv_to<fvec>(2*a + b) fused;
+// Q = a / b stored as integers (truncating division); U = a - b stored
+// unsigned (negative values clamp to 0); s[0] = accu(a), s[1] = max(a % b)
+int fe_integers(int32_t* A, int32_t* B, int64_t n, float* F, int32_t* Q, uint32_t* U, double* s, void* stream)
+{
+    return guard(stream, [&] {
+        ivec a(A, n), b(B, n);
+        fvec f(F, n);
+        f = conv_to<fvec>::from(a * 2 + b);
+        ivec q(Q, n);
+        q = a / b;
+        uvec u(U, n);
+        u = conv_to<uvec>::from(a - b);
+        s[0] = accu(a);
+        s[1] = max(a % b);
+    });
+}
+
 // an error crosses as an exception: adding matrices of different shapes
 int fe_shape_error(float* A, float* B, void* stream)
 {

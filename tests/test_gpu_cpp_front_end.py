@@ -35,7 +35,8 @@ def fe():
     sig = {"fe_small": [vp] * 5 + [i64, i64, vp, vp, vp, vp], "fe_in_place": [vp, vp, i64, vp],
            "fe_views": [vp, i64, i64, i64, vp, i64, vp, vp], "fe_generators": [vp, i64, i64, vp, i64, dbl, dbl, vp, vp],
            "fe_scalars": [vp, vp, i64, vp, vp], "fe_convert": [vp, vp, i64, i64, vp, vp, vp],
-           "fe_owned": [vp, i64, i64, vp, vp], "fe_shape_error": [vp, vp, vp]}
+           "fe_owned": [vp, i64, i64, vp, vp], "fe_shape_error": [vp, vp, vp],
+           "fe_integers": [vp, vp, i64, vp, vp, vp, vp, vp]}
     for name, args in sig.items():
         getattr(L, name).argtypes = args
     return L
@@ -196,3 +197,27 @@ def test_errors_become_exceptions(fe):
     rc = fe.fe_shape_error(ptr(A), ptr(B), stream())
     assert rc == -1
     assert "shape" in fe.fe_last_error().decode()
+
+
+def test_integer_vectors(fe, g):
+    """imat / ivec through the front end (Section 7's conv_to of an integer
+    expression, fused): integers widen exactly to FP64, stores truncate and
+    clamp."""
+    n = 100001
+    a = g.integers(-2 ** 20, 2 ** 20, n).astype(np.int32)
+    b = g.integers(-2 ** 10, 2 ** 10, n).astype(np.int32)
+    b[b == 0] = 3
+    dA = torch.from_numpy(a).cuda()
+    dB = torch.from_numpy(b).cuda()
+    F = torch.empty(n, device="cuda")
+    Q = torch.empty(n, dtype=torch.int32, device="cuda")
+    U = torch.empty(n, dtype=torch.int32, device="cuda")          # u32 bits
+    s = torch.empty(2, dtype=torch.float64)
+    run(fe, "fe_integers", ptr(dA), ptr(dB), n, ptr(F), ptr(Q), ptr(U), s.data_ptr())
+    a64, b64 = a.astype(np.int64), b.astype(np.int64)
+    assert np.array_equal(F.cpu().numpy(), (2 * a64 + b64).astype(np.float32))
+    q = np.trunc(a64 / b64).astype(np.int64)                    # exact: |a| < 2^21
+    assert np.array_equal(Q.cpu().numpy().astype(np.int64), q)
+    assert np.array_equal(U.cpu().numpy().view(np.uint32).astype(np.int64), np.maximum(a64 - b64, 0))
+    assert s[0].item() == float(a64.sum())
+    assert s[1].item() == float((a64 * b64).max())
