@@ -342,11 +342,13 @@ int coot_precompile_end(int kernels_per_module);
  * red_op of red_expr evaluated on Y_i (red_expr's slot 0 is Y_i itself; only
  * the sum-like red_ops ACCU, SUM(dim -1), DOT, NORM1, NORM2 are allowed) is
  * written to red_out[i] (red_dtype F32 or F64).  Each item's 64x64 tiles are
- * cut into tasks of at most 4 tiles; tasks are assigned to blocks longest
- * first, on the host; each task leaves a compensated partial, and the combine
+ * cut into tasks of at most 4 tiles; on the host, items are spread over the
+ * XCDs (each with its own L2) and each XCD's tasks over its blocks, longest
+ * first, so that tiles sharing cache lines run under one L2; each task
+ * leaves a compensated partial, and the combine
  * launch adds an item's partials in task order in FP64, so r_i depends only
  * on the item's shape and values (deterministic).  expr->cfg.split (if not
- * 0) sets the tile pass's grid to 4*split blocks per CU (default 2).  The
+ * 0) sets the tile pass's grid to 4*split blocks per CU (default 4).  The
  * plan copies the tables to the device and, unless COOT_BATCH_NO_GRAPH is
  * set, captures the launches in a hipGraph that coot_batch_run replays.  The caller keeps every pointer valid while the
  * plan lives. */

@@ -73,6 +73,9 @@ static void init_device(int device, unsigned flags)
     g_state.cus = prop.multiProcessorCount > 0 ? prop.multiProcessorCount : 256;
     g_state.name = prop.name;
     g_state.arch = prop.gcnArchName;
+    // gfx950 (MI355X): 8 XCDs of 32 CUs, each with its own L2; the dispatcher
+    // hands consecutive workgroups to the XCDs in turn
+    g_state.xcds = g_state.arch.compare(0, 6, "gfx950") == 0 ? 8 : 1;
     g_state.hbm = prop.totalGlobalMem;
     g_state.clock_khz = prop.clockRate;
     // temporaries of the unfused and materialising paths come from the

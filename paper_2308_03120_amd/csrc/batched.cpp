@@ -93,23 +93,51 @@ void free_plan(coot_batch_plan* p)
 // Longest-processing-time-first assignment of tasks to blocks: the costliest
 // remaining task goes to the least loaded block (ties: lowest block).  Cost of
 // a task: its tiles plus a fixed share for its partial reduction.
-void lpt_schedule(const std::vector<coot_batch_task_d>& tasks, int64_t n_blocks, std::vector<int>* order,
-                  std::vector<int>* first)
+//
+// XCD-aware: the blocks of XCD x are x, x + X, x + 2X, ... (X = xcds), and
+// each XCD has its own L2.  Neighbouring tiles of a matrix share the cache
+// lines at their edges, so a matrix's tasks all go to one XCD: matrices are
+// first spread over the XCDs by LPT on their total cost, then each XCD's
+// tasks over its own blocks by LPT.
+void lpt_schedule(const std::vector<coot_batch_task_d>& tasks, int64_t n_items, int64_t n_blocks, int xcds,
+                  std::vector<int>* order, std::vector<int>* first)
 {
     const int64_t n = (int64_t)tasks.size();
-    std::vector<int> idx((size_t)n);
-    for (int64_t i = 0; i < n; ++i) idx[(size_t)i] = (int)i;
     auto cost = [&](int i) { return (double)(tasks[(size_t)i].t1 - tasks[(size_t)i].t0) + 0.25; };
-    std::stable_sort(idx.begin(), idx.end(), [&](int a, int b) { return cost(a) > cost(b); });
     typedef std::pair<double, int64_t> Load;
-    std::priority_queue<Load, std::vector<Load>, std::greater<Load>> heap;
-    for (int64_t b = 0; b < n_blocks; ++b) heap.push(Load(0.0, b));
+    const int64_t X = (xcds > 1 && n_blocks % xcds == 0) ? xcds : 1;
+    // matrices -> XCDs
+    std::vector<double> icost((size_t)std::max<int64_t>(n_items, 1), 0.0);
+    for (int64_t i = 0; i < n; ++i) icost[(size_t)tasks[(size_t)i].item] += cost((int)i);
+    std::vector<int> items((size_t)n_items);
+    for (int64_t i = 0; i < n_items; ++i) items[(size_t)i] = (int)i;
+    std::stable_sort(items.begin(), items.end(), [&](int a, int b) { return icost[(size_t)a] > icost[(size_t)b]; });
+    std::vector<int64_t> xcd_of((size_t)std::max<int64_t>(n_items, 1), 0);
+    {
+        std::priority_queue<Load, std::vector<Load>, std::greater<Load>> heap;
+        for (int64_t x = 0; x < X; ++x) heap.push(Load(0.0, x));
+        for (int i : items) {
+            Load l = heap.top();
+            heap.pop();
+            xcd_of[(size_t)i] = l.second;
+            heap.push(Load(l.first + icost[(size_t)i], l.second));
+        }
+    }
+    // each XCD's tasks -> its blocks
     std::vector<std::vector<int>> per((size_t)n_blocks);
-    for (int i : idx) {
-        Load l = heap.top();
-        heap.pop();
-        per[(size_t)l.second].push_back(i);
-        heap.push(Load(l.first + cost(i), l.second));
+    for (int64_t x = 0; x < X; ++x) {
+        std::vector<int> idx;
+        for (int64_t i = 0; i < n; ++i)
+            if (xcd_of[(size_t)tasks[(size_t)i].item] == x) idx.push_back((int)i);
+        std::stable_sort(idx.begin(), idx.end(), [&](int a, int b) { return cost(a) > cost(b); });
+        std::priority_queue<Load, std::vector<Load>, std::greater<Load>> heap;
+        for (int64_t b = x; b < n_blocks; b += X) heap.push(Load(0.0, b));
+        for (int i : idx) {
+            Load l = heap.top();
+            heap.pop();
+            per[(size_t)l.second].push_back(i);
+            heap.push(Load(l.first + cost(i), l.second));
+        }
     }
     order->clear();
     first->assign((size_t)n_blocks + 1, 0);
@@ -296,11 +324,13 @@ int coot_batch_create(const coot_batch* b, void* stream, coot_batch_plan** out_p
                     if (!d.out && d.rows * d.cols > 0) fail(COOT_ERR_ARG, "batch: NULL output pointer");
                 }
             }
-            // 4 blocks of 256 threads per CU per unit of the tree's split setting (default 2)
-            const int split = b->expr->cfg.split > 0 ? b->expr->cfg.split : 2;
+            // 4 blocks of 256 threads per CU per unit of the tree's split setting
+            // (default 4: with each matrix's tasks kept on one XCD, shorter
+            // per-block task lists balance better)
+            const int split = b->expr->cfg.split > 0 ? b->expr->cfg.split : 4;
             P->n_blocks = std::max<int64_t>(1, std::min<int64_t>((int64_t)tasks.size(), (int64_t)g_state.cus * 4 * split));
             std::vector<int> order, first;
-            lpt_schedule(tasks, P->n_blocks, &order, &first);
+            lpt_schedule(tasks, P->n_items, P->n_blocks, g_state.xcds, &order, &first);
             auto up = [](void** dst, const void* src, size_t bytes) {
                 hipchk(hipMalloc(dst, std::max<size_t>(bytes, 16)), "hipMalloc(batch table)");
                 if (bytes) hipchk(hipMemcpy(*dst, src, bytes, hipMemcpyHostToDevice), "hipMemcpy(batch table)");

@@ -23,6 +23,7 @@ struct State {
     bool init = false;
     int device = -1;
     int cus = 256;
+    int xcds = 8;         // L2 domains: consecutive block indices go to them in turn
     std::string name, arch;
     size_t hbm = 0;
     int clock_khz = 0;
