@@ -442,7 +442,18 @@ CD AccV combine_var(const double* part, i64 first, i64 count, i64 stride)
     __shared__ AccV lds_v[16];
     AccV a;
     a.init();
-    for (i64 t = threadIdx.x; t < count; t += blockDim.x) a.merge(var_partial(part, first + t * stride));
+    const i64 bd = blockDim.x;
+    for (i64 t = threadIdx.x; t < count; t += 4 * bd) {
+        AccV o[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const i64 tu = t + u * bd;
+            o[u] = var_partial(part, first + (tu < count ? tu : t) * stride);
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+            if (t + u * bd < count) a.merge(o[u]);
+    }
     return block_reduce(a, lds_v);
 }
 
@@ -450,7 +461,14 @@ CD AccV combine_var_seq(const double* part, i64 first, i64 count, i64 stride)
 {
     AccV a;
     a.init();
-    for (i64 t = 0; t < count; ++t) a.merge(var_partial(part, first + t * stride));
+    for (i64 t = 0; t < count; t += 4) {
+        AccV o[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) o[u] = var_partial(part, first + (t + u < count ? t + u : t) * stride);
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+            if (t + u < count) a.merge(o[u]);
+    }
     return a;
 }
 
@@ -461,10 +479,24 @@ CD double combine_sums(const double* part, i64 first, i64 count, i64 stride)
     __shared__ AccKD lds_kd[16];
     AccKD a;
     a.init();
-    for (i64 t = threadIdx.x; t < count; t += blockDim.x) {
-        const double* p = part + 2 * (first + t * stride);
-        a.add(p[0]);
-        a.add(p[1]);
+    // four partials per thread are loaded before any is added (one memory
+    // latency instead of four); the thread still adds them in index order
+    const i64 bd = blockDim.x;
+    for (i64 t = threadIdx.x; t < count; t += 4 * bd) {
+        double h[4], l[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const i64 tu = t + u * bd;
+            const double* p = part + 2 * (first + (tu < count ? tu : t) * stride);
+            h[u] = p[0];
+            l[u] = p[1];
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+            if (t + u * bd < count) {
+                a.add(h[u]);
+                a.add(l[u]);
+            }
     }
     a = block_reduce(a, lds_kd);
     return a.s + a.c;
@@ -476,12 +508,19 @@ CD AccI<double, MAX> combine_idx(const double* part, i64 first, i64 count, i64 s
     __shared__ AccI<double, MAX> lds_id[16];
     AccI<double, MAX> a;
     a.init();
-    for (i64 t = threadIdx.x; t < count; t += blockDim.x) {
-        const double* p = part + 2 * (first + t * stride);
-        AccI<double, MAX> o;
-        o.v = p[0];
-        o.i = __builtin_bit_cast(i64, p[1]);
-        a.merge(o);
+    const i64 bd = blockDim.x;
+    for (i64 t = threadIdx.x; t < count; t += 4 * bd) {
+        AccI<double, MAX> o[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const i64 tu = t + u * bd;
+            const double* p = part + 2 * (first + (tu < count ? tu : t) * stride);
+            o[u].v = p[0];
+            o[u].i = __builtin_bit_cast(i64, p[1]);
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+            if (t + u * bd < count) a.merge(o[u]);
     }
     return block_reduce(a, lds_id);
 }
@@ -491,10 +530,21 @@ CD double combine_sums_seq(const double* part, i64 first, i64 count, i64 stride)
 {
     AccKD a;
     a.init();
-    for (i64 t = 0; t < count; ++t) {
-        const double* p = part + 2 * (first + t * stride);
-        a.add(p[0]);
-        a.add(p[1]);
+    // eight partials are loaded before any is added; the adds keep index order
+    for (i64 t = 0; t < count; t += 8) {
+        double h[8], l[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const double* p = part + 2 * (first + (t + u < count ? t + u : t) * stride);
+            h[u] = p[0];
+            l[u] = p[1];
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u)
+            if (t + u < count) {
+                a.add(h[u]);
+                a.add(l[u]);
+            }
     }
     return a.s + a.c;
 }
@@ -504,12 +554,17 @@ CD AccI<double, MAX> combine_idx_seq(const double* part, i64 first, i64 count, i
 {
     AccI<double, MAX> a;
     a.init();
-    for (i64 t = 0; t < count; ++t) {
-        const double* p = part + 2 * (first + t * stride);
-        AccI<double, MAX> o;
-        o.v = p[0];
-        o.i = __builtin_bit_cast(i64, p[1]);
-        a.merge(o);
+    for (i64 t = 0; t < count; t += 8) {
+        AccI<double, MAX> o[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const double* p = part + 2 * (first + (t + u < count ? t + u : t) * stride);
+            o[u].v = p[0];
+            o[u].i = __builtin_bit_cast(i64, p[1]);
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u)
+            if (t + u < count) a.merge(o[u]);
     }
     return a;
 }
