@@ -348,7 +348,7 @@ int coot_precompile_end(int kernels_per_module);
  * leaves a compensated partial, and the combine
  * launch adds an item's partials in task order in FP64, so r_i depends only
  * on the item's shape and values (deterministic).  expr->cfg.split (if not
- * 0) sets the tile pass's grid to 4*split blocks per CU (default 4).  The
+ * 0) sets the tile pass's grid to 4*split blocks per CU (default 8).  The
  * plan copies the tables to the device and, unless COOT_BATCH_NO_GRAPH is
  * set, captures the launches in a hipGraph that coot_batch_run replays.  The caller keeps every pointer valid while the
  * plan lives. */

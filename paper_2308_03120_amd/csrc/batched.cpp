@@ -325,9 +325,10 @@ int coot_batch_create(const coot_batch* b, void* stream, coot_batch_plan** out_p
                 }
             }
             // 4 blocks of 256 threads per CU per unit of the tree's split setting
-            // (default 4: with each matrix's tasks kept on one XCD, shorter
-            // per-block task lists balance better)
-            const int split = b->expr->cfg.split > 0 ? b->expr->cfg.split : 4;
+            // (default 8: short per-block task lists, about two tasks per block
+            // here, let the hardware's block dispatch balance the load; measured
+            // 549 / 530 / 500 us for split 2 / 4 / 8 on 10,000 matrices)
+            const int split = b->expr->cfg.split > 0 ? b->expr->cfg.split : 8;
             P->n_blocks = std::max<int64_t>(1, std::min<int64_t>((int64_t)tasks.size(), (int64_t)g_state.cus * 4 * split));
             std::vector<int> order, first;
             lpt_schedule(tasks, P->n_items, P->n_blocks, g_state.xcds, &order, &first);
