@@ -31,6 +31,8 @@ int main()
     double* Q = reinterpret_cast<double*>(uintptr_t(1) << 41);
     fmat A(P, 30, 20), B(P + 1000, 30, 20), C(P + 2000, 30, 20), D(P + 3000, 30, 20), T(P + 4000, 20, 30);
     mat X(Q, 30, 20);
+    int32_t* I = reinterpret_cast<int32_t*>(uintptr_t(1) << 42);
+    imat K(I, 30, 20), L(I + 1000, 30, 20);
     // exact rewrites chosen by overload resolution while the type is built
     static_assert(std::is_same<decltype(trans(trans(A))), const fmat&>::value, "trans(trans(A)) is A");
     static_assert(std::is_same<decltype(trans(eye<fmat>(3, 4))), GenEye<float>>::value, "trans(eye) is eye");
@@ -50,5 +52,7 @@ int main()
     show("linspace", linspace<fvec>(-1.0, 2.0, 30) * 2.0);
     show("views", A.submat(1, 2, 10, 12) + B.submat(0, 0, 9, 10));
     show("diag", trans(A.diag(3)));
+    show("integers", conv_to<fmat>::from(K * 2 + L / 3) + A);
+    show("integer_conv", conv_to<imat>::from(A * 1000.0) + K);
     return 0;
 }

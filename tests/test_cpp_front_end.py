@@ -26,7 +26,7 @@ CXX = ["g++", "-std=c++17", "-O1", "-Wall", "-Wextra", "-Werror", "-D__HIP_PLATF
        "-I" + os.path.join(ROOT, "include")]
 LINK = ["-L" + LIBDIR, "-lcoot_mi355x", "-L/opt/rocm/lib", "-lamdhip64", "-Wl,-rpath," + LIBDIR]
 
-P, Q = 1 << 40, 1 << 41      # stand-in device addresses of the program's float / double memory
+P, Q, IP = 1 << 40, 1 << 41, 1 << 42   # stand-in device addresses: float, double, int32 memory
 CODE_TO_NAME = {v: k for k, v in coot.OPS.items()}
 
 
@@ -42,20 +42,21 @@ def described(tmp_path_factory):
 
 def memory(g):
     """Seeded contents of the program's stand-in float and double memory."""
-    return {P: ("f32", g.uniform(-2, 2, 6000).astype(np.float32)), Q: ("f64", g.uniform(-2, 2, 1000))}
+    return {P: ("f32", g.uniform(-2, 2, 6000).astype(np.float32)), Q: ("f64", g.uniform(-2, 2, 1000)),
+            IP: ("i32", g.integers(-2 ** 31, 2 ** 31, 2000).astype(np.int32))}
 
 
 def operand_of(mem, op):
     """Dense oracle operand for one row of the operand table."""
     rows, cols, ld, dtype, flags, g0, g1, ptr = op
-    dt = {0: "f32", 1: "f64"}[dtype]
+    dt = {0: "f32", 1: "f64", 5: "i32"}[dtype]
     if flags == coot.GEN_EYE:
         return oracle.eye(rows, cols, dt)
     if flags == coot.GEN_FILL:
         return oracle.fill(rows, cols, g0, dt)
     if flags == coot.GEN_LINSPACE:
         return oracle.linspace(g0, g1, rows * cols, dt, row=rows == 1)
-    base = P if ptr < Q else Q
+    base = P if ptr < Q else (Q if ptr < IP else IP)
     _, buf = mem[base]
     off = (ptr - base) // buf.itemsize
     idx = off + np.arange(rows)[:, None] + ld * np.arange(cols)[None, :]
@@ -96,6 +97,8 @@ def test_compile_time_rewrites_and_expressions(described):
         "linspace": (a * 2.0, [oracle.linspace(-1.0, 2.0, 30, "f32")]),
         "views": (a + b, [mat_at(mem, P, 1 + 2 * 30, 10, 11, 30), mat_at(mem, P, 1000, 10, 11, 30)]),
         "diag": (trans(a), [mat_at(mem, P, 3 * 30, 1, 17, 31)]),
+        "integers": (conv(a * 2.0 + b / 3.0, "f32") + c, [mat_at(mem, IP, 0, 30, 20), mat_at(mem, IP, 1000, 30, 20), A]),
+        "integer_conv": (conv(a * 1000.0, "i32") + b, [A, mat_at(mem, IP, 0, 30, 20)]),
     }
     assert set(cases) == set(described)
     for name, (tree, ops) in cases.items():
