@@ -963,11 +963,16 @@ static std::string emit_col(const Plan& p, const LaunchCfg& c, const std::string
         s << "        const " << stype(p.reads[j].dtype) << "* C" << j << " = L" << j << " + j * ld" << j << " + rs0;\n";
     // 2- and 4-byte data: two register buffers, the next step's loads in
     // flight while the current step is folded, whole steps without per-vector
-    // guards (FP32 1-3% faster, BF16 max 20%); 8-byte data keeps one buffer
-    // (the second costs FP64 columns 5%)
+    // guards (FP32 1-3% faster, 16-bit max 20%).  8-byte data keeps one buffer
+    // (the second costs FP64 columns 5%), and so do compensated sums of FP16
+    // (5% slower with the second buffer at 65 VGPRs; BF16 sums break even)
     int maxsz = 1;
-    for (const Read& r : p.reads) maxsz = std::max(maxsz, itemsize(r.dtype));
-    if (maxsz <= 4) {
+    bool f16 = false;
+    for (const Read& r : p.reads) {
+        maxsz = std::max(maxsz, itemsize(r.dtype));
+        f16 = f16 || r.dtype == COOT_F16;
+    }
+    if (maxsz <= 4 && !(f16 && acc_type(p) == "AccKF")) {
         auto load = [&](const std::string& buf, const std::string& b, bool guarded) {
             std::ostringstream o;
             o << "#pragma unroll\n            for (int e = 0; e < " << EPT << "; ++e) {\n";
