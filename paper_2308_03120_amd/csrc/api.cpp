@@ -275,8 +275,8 @@ static Kernel kernel_for(const Plan& p, const LaunchCfg& c)
 {
     std::string key = std::to_string(p.kind) + "|" + std::to_string(p.ve) + "|" + std::to_string(c.ept) + "|" +
                       std::to_string(p.out_dtype) + "|" + std::to_string(p.red_op) + "|" + std::to_string(p.pairwise) +
-                      "|" + std::to_string(p.alias_out) + "|" + std::to_string(p.tile_gen) + std::to_string(p.tile_lr) + "," +
-                      std::to_string(p.tile_lc) + "|" + p.body_sig;
+                      "|" + std::to_string(p.alias_out) + "|" + std::to_string(p.tile_gen) + std::to_string(p.tile_off32) +
+                      std::to_string(p.tile_lr) + "," + std::to_string(p.tile_lc) + "|" + p.body_sig;
     {
         std::lock_guard<std::mutex> lk(g_sig_mu);
         auto it = g_sig_kernels.find(key);

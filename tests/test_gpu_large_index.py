@@ -117,3 +117,26 @@ def test_transposed_read_and_column_sums_beyond_2e31():
     assert coot.reduce("index_max", X, [Am]).item() == (R - 5) + (C - 2) * R
     del A, Am
     torch.cuda.empty_cache()
+
+
+def test_thin_view_with_wide_stride_after_narrow_stride():
+    """A 2 x 40 FP64 view whose column stride (2^24 + 8 elements) puts the
+    per-lane offsets of a tile step beyond 32 bits, evaluated after the same
+    tree on a 2 x 40 view with a stride of 3: each call must run the kernel
+    built for its own offset width (the per-call kernel cache keys on it)."""
+    g = np.random.default_rng(33)
+    cols = 40
+    tree = X * 2.0 - 0.5
+    for ld in (3, (1 << 24) + 8):                    # the narrow stride first
+        M = torch.empty(cols, ld, dtype=torch.float64, device="cuda").t()    # ld x cols, column-major
+        vals = g.uniform(-4, 4, (2, cols))
+        M[0:2, :] = torch.from_numpy(vals).cuda()
+        view = M[0:2, :]
+        assert coot.operand(view).ld == ld
+        Y = torch.empty(cols, 2, dtype=torch.float64, device="cuda").t()
+        coot.eval(tree, [view], Y)
+        torch.cuda.synchronize()
+        want = oracle.evaluate(tree.postfix(), [synth.Mat(np.asfortranarray(vals), "f64")], "emu")
+        assert np.array_equal(Y.cpu().numpy(), want), ld
+        del M, Y, view
+        torch.cuda.empty_cache()
