@@ -246,9 +246,10 @@ static Geometry geometry(const Plan& p, const LaunchCfg& c)
         G.splits = q;
         G.grid = std::max<int64_t>(1, std::min(ceil_div(units * q, c.block), cap));
         if (q > 1) {
-            // the combine kernel takes a block per row from 256 splits on, else a thread per row
-            G.comb_grid = q >= 256 ? std::min<int64_t>(p.rows, (int64_t)g_state.cus * 16)
-                                   : std::max<int64_t>(1, std::min<int64_t>(ceil_div(p.rows, 256), (int64_t)g_state.cus * 16));
+            // the combine kernel takes a block per row from 256 splits on, a
+            // block per 64 rows from 16, else a thread per row
+            const int64_t per_block = q >= 256 ? 1 : (q >= 16 ? 64 : 256);
+            G.comb_grid = std::max<int64_t>(1, std::min<int64_t>(ceil_div(p.rows, per_block), (int64_t)g_state.cus * 16));
             G.part_bytes = (size_t)(p.rows * q) * red_partial_bytes(p.red_op);
         }
         break;

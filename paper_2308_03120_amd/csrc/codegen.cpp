@@ -1113,13 +1113,52 @@ static std::string emit_row(const Plan& p, const std::string& name)
     s << "        if (a.splits == 1) { " << write_direct(p, "r") << " } else { " << put_partial(p, "q * a.rows + r")
       << " }\n";
     s << "    }\n}\n";
-    // combine, splits in order: a block per row when the splits are many, a
-    // thread per row otherwise
+    // combine in a fixed order: a block per row from 256 splits on, four
+    // waves per 64 rows from 16, a thread per row below
     s << "extern \"C\" __global__ void __launch_bounds__(256) " << name << "_comb(const coot_kargs a)\n{\n";
     s << "    if (a.splits >= 256) {\n";
     s << "        for (i64 r = blockIdx.x; r < a.rows; r += gridDim.x) {\n            "
       << combine_and_write(p, "r", "a.splits", "a.rows", "r") << "\n        }\n";
     s << "        return;\n    }\n";
+    // 16 to 255 splits: four waves per 64 rows, wave k adding quarter k of
+    // the splits in order (adjacent lanes read adjacent slots of one split),
+    // the quarters merged in order through LDS
+    std::string acc, fold, put;
+    if (red_is_var(p.red_op)) {
+        acc = "AccV";
+        fold = "x = combine_var_seq(part, s0 * a.rows + r, s1 - s0, a.rows);";
+        put = put_var_result(p, "r", "y");
+    } else if (red_is_sum(p.red_op)) {
+        acc = "AccKD";
+        fold = "for (i64 t = s0; t < s1; t += 8) { double h[8], l[8];\n"
+               "#pragma unroll\n"
+               "                for (int u = 0; u < 8; ++u) { const double* pp = part + 2 * ((t + u < s1 ? t + u : t) * a.rows + r); "
+               "h[u] = pp[0]; l[u] = pp[1]; }\n"
+               "#pragma unroll\n"
+               "                for (int u = 0; u < 8; ++u) if (t + u < s1) { x.add(h[u]); x.add(l[u]); } }";
+        put = put_sum_result(p, "r", "(y.s + y.c)");
+    } else {
+        const std::string mx = red_is_max(p.red_op) ? "true" : "false";
+        acc = "AccI<double, " + mx + ">";
+        fold = "x = combine_idx_seq<" + mx + ">(part, s0 * a.rows + r, s1 - s0, a.rows);";
+        put = (p.red_op == COOT_RED_INDEX_MIN || p.red_op == COOT_RED_INDEX_MAX)
+                  ? "put_u64(a.res, r, y.i);"
+                  : put_value(p, "r", "(y.i < 0 ? __builtin_nan(\"\") : y.v)");
+    }
+    s << "    if (a.splits >= 16) {\n";
+    s << "        const int lane = threadIdx.x & 63, k = threadIdx.x >> 6;\n";
+    s << "        const i64 qs = (a.splits + 3) / 4, s0 = k * qs, s1 = s0 + qs < a.splits ? s0 + qs : a.splits;\n";
+    s << "        const double* part = (const double*)a.part;\n";
+    s << "        __shared__ " << acc << " lq[256];\n";
+    s << "        for (i64 r0 = (i64)blockIdx.x * 64; r0 < a.rows; r0 += (i64)gridDim.x * 64) {\n";
+    s << "            const i64 r = r0 + lane;\n";
+    s << "            " << acc << " x;\n            x.init();\n";
+    s << "            if (r < a.rows) { " << fold << " }\n";
+    s << "            __syncthreads();\n            lq[threadIdx.x] = x;\n            __syncthreads();\n";
+    s << "            if (k == 0 && r < a.rows) {\n";
+    s << "                " << acc << " y = lq[lane];\n";
+    s << "#pragma unroll\n                for (int m = 1; m < 4; ++m) y.merge(lq[m * 64 + lane]);\n";
+    s << "                " << put << "\n            }\n        }\n        return;\n    }\n";
     s << "    for (i64 r = (i64)blockIdx.x * blockDim.x + threadIdx.x; r < a.rows; r += (i64)gridDim.x * blockDim.x) {\n        "
       << combine_and_write_seq(p, "r", "a.splits", "a.rows", "r") << "\n    }\n}\n";
     return s.str();
