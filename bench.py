@@ -510,6 +510,10 @@ def tiled_workload(args, np, torch, synth, coot):
                              ("scale_submat_16383x16383_f32",
                               lambda: coot.eval(X0 * 2.0, [coot.submat(A, 1, 1, n - 1, n - 1)],
                                                 coot.submat(Y, 0, 0, n - 2, n - 2)), 8 * (n - 1) * (n - 1)),
+                             # both views one element off their lines (the tile grid follows the output)
+                             ("scale_submat_offset_out_16383x16383_f32",
+                              lambda: coot.eval(X0 * 2.0, [coot.submat(A, 1, 1, n - 1, n - 1)],
+                                                coot.submat(Y, 1, 1, n - 1, n - 1)), 8 * (n - 1) * (n - 1)),
                              ("trace_16384x16384_f32", lambda: coot.trace(A), 4 * n)):
         med, mn, p90 = event_stats(torch, fn)
         gbs = nbytes / (med * 1e-6) / 1e9

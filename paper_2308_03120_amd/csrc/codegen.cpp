@@ -578,15 +578,21 @@ struct TileView {
 };
 
 // --- square 64 x 64 tiles --------------------------------------------------
+// shifted: the tile grid starts sh rows above the value (the per-call kernels)
 static std::string tile_prefetch_sq(const Plan& p, const TilePlan& tp, const std::string& in, const std::string& ti,
-                                    const std::string& tj, const TileView& v, const std::string& ldf)
+                                    const std::string& tj, const TileView& v, const std::string& ldf, bool shifted = false)
 {
     std::ostringstream o;
     o << in << "{\n";
-    o << in << "    const i64 pi0 = (i64)(" << ti << ") << 6, pj0 = (i64)(" << tj << ") << 6;\n";
+    o << in << "    const i64 pi0 = " << (shifted ? "((i64)(" + ti + ") << 6) - sh" : "(i64)(" + ti + ") << 6") << ", pj0 = (i64)("
+      << tj << ") << 6;\n";
+    if (shifted) o << in << "    const int plo = pi0 < 0 ? (int)-pi0 : 0;\n";
     o << in << "    const int pri = (int)(" << v.R << " - pi0 < 64 ? " << v.R << " - pi0 : 64);\n";
     o << in << "    const int prj = (int)(" << v.Cn << " - pj0 < 64 ? " << v.Cn << " - pj0 : 64);\n";
-    o << in << "    const u32 lnr = lane < pri ? (u32)lane : 0u, lnc = lane < prj ? (u32)lane : 0u;\n";
+    if (shifted)
+        o << in << "    const u32 lnr = lane >= plo && lane < pri ? (u32)lane : (u32)plo, lnc = lane < prj ? (u32)lane : 0u;\n";
+    else
+        o << in << "    const u32 lnr = lane < pri ? (u32)lane : 0u, lnc = lane < prj ? (u32)lane : 0u;\n";
     for (size_t j = 0; j < p.reads.size(); ++j) {
         const std::string J = std::to_string(j), L = v.L(j), ld = v.ld(j), S = stype(p.reads[j].dtype);
         if (tp.in_lds[j]) {
@@ -606,7 +612,7 @@ static std::string tile_prefetch_sq(const Plan& p, const TilePlan& tp, const std
     for (size_t j = 0; j < p.reads.size(); ++j) {
         const std::string J = std::to_string(j), C = ctype(dtype_prec(p.reads[j].dtype));
         if (tp.in_lds[j])
-            o << in << "        pt" << J << "[kk] = q < pri ? " << widen(p.reads[j].dtype, ldf + "(a" + J + " + lnc)") << " : (" << C
+            o << in << "        pt" << J << "[kk] = " << (shifted ? "q >= plo && " : "") << "q < pri ? " << widen(p.reads[j].dtype, ldf + "(a" + J + " + lnc)") << " : (" << C
               << ")0;\n";
         else if (p.reads[j].trans)
             o << in << "        pr" << J << "[kk] = q < prj ? " << widen(p.reads[j].dtype, ldf + "(a" + J + " + lrs" + J + ")")
@@ -644,15 +650,18 @@ static std::string tile_stage_sq(const Plan& p, const TilePlan& tp, const std::s
 template <class F>
 static std::string tile_compute_sq(const Plan& p, const TilePlan& tp, const std::string& in, const std::string& ti,
                                    const std::string& tj, const std::string& R, const std::string& Cn,
-                                   const std::string& out, const std::string& OT, const std::string& ldo, F per_elem)
+                                   const std::string& out, const std::string& OT, const std::string& ldo, F per_elem,
+                                   bool shifted = false)
 {
     std::ostringstream s;
     s << in << "{\n";
-    s << in << "    const i64 i0 = (i64)(" << ti << ") << 6, j0 = (i64)(" << tj << ") << 6;\n";
+    s << in << "    const i64 i0 = " << (shifted ? "((i64)(" + ti + ") << 6) - sh" : "(i64)(" + ti + ") << 6") << ", j0 = (i64)("
+      << tj << ") << 6;\n";
+    if (shifted) s << in << "    const int lo = i0 < 0 ? (int)-i0 : 0;\n";
     s << in << "    const int ri = (int)(" << R << " - i0 < 64 ? " << R << " - i0 : 64);\n";
     s << in << "    const int rj = (int)(" << Cn << " - j0 < 64 ? " << Cn << " - j0 : 64);\n";
     if (!out.empty()) s << in << "    " << OT << "* po = " << out << " + (i0 + (j0 + w) * " << ldo << ");\n";
-    s << in << "    if (lane < ri) {\n";
+    s << in << "    if (" << (shifted ? "lane >= lo && " : "") << "lane < ri) {\n";
     s << in << "        const i64 ig = i0 + lane;\n";
     s << in << "#pragma unroll\n" << in << "        for (int kk = 0; kk < 16; ++kk) {\n";
     s << in << "            const int jj = w + 4 * kk;\n";
@@ -899,8 +908,11 @@ static std::string emit_tiled(const Plan& p, const std::string& name)
     s << "    const i64 R = a.rows, Cn = a.cols;\n";
     // tile shape, fixed per kernel: 2^lr x 2^lc
     s << "    const int lr = " << p.tile_lr << ", lc = " << p.tile_lc << ";\n";
+    // 64 x 64 tiles start sh rows above the value (0 <= sh < 64), so that
+    // the column segments of the reference operand begin on cache lines
+    if (!gen) s << "    const i64 sh = a.aux;\n";
     // tile counts fit in int for every matrix that fits in device memory
-    s << "    const int tr = (int)((R + (1 << lr) - 1) >> lr);\n";
+    s << "    const int tr = (int)((R + " << (gen ? "" : "sh + ") << "(1 << lr) - 1) >> lr);\n";
     s << "    const int tc = tr > 0 ? (int)((Cn + (1 << lc) - 1) >> lc) : 0, trs = tr > 0 ? tr : 1;\n";
     s << "    const int gq = (int)gridDim.x / trs, gr = (int)gridDim.x % trs;\n";
     s << "    int ti = (int)blockIdx.x % trs, tj = (int)blockIdx.x / trs;\n";
@@ -908,7 +920,7 @@ static std::string emit_tiled(const Plan& p, const std::string& name)
     TileView v{"R", "Cn", "lr", "lc", [](size_t j) { return "L" + std::to_string(j); },
                [](size_t j) { return "ld" + std::to_string(j); }};
     auto prefetch = [&](const std::string& in, const std::string& a, const std::string& b) {
-        return gen ? tile_prefetch_gen(p, tp, in, a, b, v, "ldnt", p.tile_off32) : tile_prefetch_sq(p, tp, in, a, b, v, "ldnt");
+        return gen ? tile_prefetch_gen(p, tp, in, a, b, v, "ldnt", p.tile_off32) : tile_prefetch_sq(p, tp, in, a, b, v, "ldnt", true);
     };
     auto elem = [&](const std::string& args, const std::string& in, const std::string& addr) {
         if (ew)
@@ -926,7 +938,7 @@ static std::string emit_tiled(const Plan& p, const std::string& name)
         s << tile_compute_gen(p, tp, "        ", "ti", "tj", "R", "Cn", "lr", "lc", ew ? "O" : "", stype(p.out_dtype), "ldo",
                               p.tile_off32, elem);
     else
-        s << tile_compute_sq(p, tp, "        ", "ti", "tj", "R", "Cn", ew ? "O" : "", stype(p.out_dtype), "ldo", elem);
+        s << tile_compute_sq(p, tp, "        ", "ti", "tj", "R", "Cn", ew ? "O" : "", stype(p.out_dtype), "ldo", elem, true);
     s << "        ti = ni;\n        tj = nj;\n";
     s << "    }\n";
     if (!ew) {
