@@ -1,0 +1,81 @@
+"""Square-tiled kernels on views that start inside a 128-byte line.  The
+64 x 64 tile grid of the per-call kernels starts as many rows above the value
+as the output's columns start into a line (a launch argument), so its first
+and last tile rows are partial.  Element-wise results must match the oracle
+bit for bit, nothing outside the output view may change, and reductions must
+keep the plain linear index (row + column * rows) of the value."""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from synth import leaves, trans
+
+from gpu_util import TORCH_DT, dev, host, need_gpu, same, torch
+
+pytestmark = pytest.mark.gpu
+
+from paper_2308_03120_amd import coot  # noqa: E402
+
+x, y = leaves(2)
+R, C, LD = 200, 150, 256          # several tiles with ragged tails; LD keeps one phase per column
+ODT = {"f32": "f32", "f64": "f64", "bf16": "f32"}
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    need_gpu()
+    coot.init(0)
+
+
+def mat(g, shape, dt):
+    return synth.Mat(synth.store(np.asfortranarray(g.uniform(-2, 2, shape)), dt), dt)
+
+
+def out_buffer(dt, off):
+    """NaN-filled buffer and an R x C view of it starting `off` elements in."""
+    buf = torch.full((C * LD + off + 1,), float("nan"), dtype=TORCH_DT[dt], device="cuda")
+    return buf, buf[off:off + C * LD].view(C, LD)[:, :R].t()
+
+
+@pytest.mark.parametrize("dt", ["f32", "f64", "bf16"])
+@pytest.mark.parametrize("offs", [(1, 1), (0, 3), (5, 0), (7, 7), (0, 0)])
+def test_elementwise_into_offset_views(dt, offs):
+    g = np.random.default_rng(500 + 100 * list(ODT).index(dt) + 10 * offs[0] + offs[1])
+    ia, ib, io = offs[0], (offs[0] + 2) % 9, offs[1]
+    A, B = mat(g, (R, C), dt), mat(g, (R, C), dt)
+    T = mat(g, (C, R), dt)
+    dA, dB = dev(A, ld=LD, offset=ia), dev(B, ld=LD, offset=ib)
+    dT = dev(T, ld=LD, offset=ia)
+    odt = ODT[dt]
+    for tree, gops, cops in ((x * 2.0 - y, [dA, dB], [A, B]), (trans(x) + y * 0.5, [dT, dB], [T, B])):
+        buf, Y = out_buffer(odt, io)
+        coot.eval(tree, gops, Y)
+        torch.cuda.synchronize()
+        want = oracle.evaluate(tree.postfix(), cops, "emu")
+        assert same(host(Y), want), (dt, offs, tree)
+        # nothing outside the view was written
+        full = buf[io:io + C * LD].view(C, LD)
+        assert torch.isnan(full[:, R:]).all() and torch.isnan(buf[:io]).all() and torch.isnan(buf[io + C * LD:]).all()
+
+
+@pytest.mark.parametrize("dt", ["f32", "f64", "bf16"])
+@pytest.mark.parametrize("off", [1, 3, 0])
+def test_reductions_over_offset_views(dt, off):
+    g = np.random.default_rng(1000 + 10 * list(ODT).index(dt) + off)
+    DA = g.uniform(-2, 2, (R, C))                  # draws; 16-bit Mats hold bit patterns
+    A, B = synth.Mat(synth.store(np.asfortranarray(DA), dt), dt), mat(g, (R, C), dt)
+    dA, dB = dev(A, ld=LD, offset=off), dev(B, ld=LD, offset=off)
+    o, _, s = oracle.reduce("accu", (x % y).postfix(), [A, B])
+    got = coot.reduce("accu", x % y, [dA, dB]).item()
+    tol = 1e-6 if dt != "f64" else 1e-13
+    assert abs(got - o[0]) <= tol * s[0]
+    # a unique maximum planted at each tile boundary row of the shifted grid and elsewhere
+    for (i, j) in ((0, 0), (R - 1, C - 1), (64 - off if off else 63, 70), (128 - off, 1), (17, 149)):
+        M = DA.copy()
+        M[i, j] = 50.0
+        Am = synth.Mat(synth.store(np.asfortranarray(M), dt), dt)
+        dM = dev(Am, ld=LD, offset=off)
+        assert coot.reduce("index_max", x, [dM]).item() == i + j * R, (dt, off, i, j)
+        assert coot.reduce("index_max", x % y, [dM, dB]).item() == \
+            oracle.reduce("index_max", (x % y).postfix(), [Am, B], mode="emu")[1][0]
