@@ -111,7 +111,7 @@ def main():
                          "precision: 16384^2 BF16/FP16 sums and dots; tiled: transposed reads (64x64 and "
                          "shape-adaptive tiles); small: the 1000x1000 FP32 calls, warm and cold; stats: mean, "
                          "var, stddev, count / all / any of relational trees")
-    ap.add_argument("--out-dir", default=os.path.join(ROOT, "gpurun_out"),
+    ap.add_argument("--out-dir", default=os.path.join(ROOT, "bench_out"),
                     help="where the cost-model workload writes its corpus table and weights")
     ap.add_argument("--trees", type=int, default=6000)
     ap.add_argument("--traffic-from", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
