@@ -82,7 +82,7 @@ def lib():
         L.oracle_eval.argtypes = [C.POINTER(_Node), C.c_int, C.POINTER(_Leaf), C.c_int, C.c_int,
                                   dp, dp, ip, ip]
         L.oracle_eval_at.argtypes = [C.POINTER(_Node), C.c_int, C.POINTER(_Leaf), C.c_int, C.c_int,
-                                     ip, C.c_int64, dp]
+                                     ip, C.c_int64, dp, dp]
         L.oracle_shape.argtypes = [C.POINTER(_Node), C.c_int, C.POINTER(_Leaf), C.c_int, ip, ip,
                                    C.POINTER(C.c_int32)]
         L.oracle_reduce.argtypes = [C.c_int, C.c_int, C.POINTER(_Node), C.c_int, C.POINTER(_Leaf), C.c_int,
@@ -171,15 +171,20 @@ def evaluate(tree, mats, mode: str = "exact", scale: bool = False):
     return v
 
 
-def evaluate_at(tree, mats, lin: np.ndarray, mode: str = "exact") -> np.ndarray:
-    """Pointwise evaluation at column-major linear indices of the root."""
+def evaluate_at(tree, mats, lin: np.ndarray, mode: str = "exact", scale: bool = False):
+    """Pointwise evaluation at column-major linear indices of the root (and the
+    running-error scale S there if ``scale``)."""
     nd, nn = _nodes(tree)
     lv, keep = _leaves(mats)
     lin = np.ascontiguousarray(lin, dtype=np.int64)
     out = np.empty(max(1, lin.size), np.float64)
-    rc = lib().oracle_eval_at(nd, nn, lv, len(mats), MODES[mode], _ip(lin), lin.size, _dp(out))
+    sc = np.empty(max(1, lin.size), np.float64) if scale else None
+    rc = lib().oracle_eval_at(nd, nn, lv, len(mats), MODES[mode], _ip(lin), lin.size, _dp(out),
+                              _dp(sc) if scale else None)
     if rc:
         raise OracleError(rc)
+    if scale:
+        return out[: lin.size], sc[: lin.size]
     return out[: lin.size]
 
 

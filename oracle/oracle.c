@@ -295,6 +295,47 @@ static double scalar_of(const or_node* n, int prec)
     return prec == 32 ? (double)(float)n->k : n->k;
 }
 
+/* Running-error scale S of an element-wise node from its operand values a, b
+ * (FP64) and their scales sa, sb: the first-order magnitude of the
+ * expression evaluated on absolute values, with each unary function's
+ * derivative (Higham, "Accuracy and Stability of Numerical Algorithms",
+ * 2nd ed., Section 3.1).  A leaf's scale is |x|; trans and conv keep their
+ * child's. */
+static double scale_op(int op, double a, double b, double k, double sa, double sb)
+{
+    switch (op) {
+    case OR_PLUS: case OR_MINUS: return sa + sb;
+    case OR_SCHUR: return sa * sb;
+    case OR_DIV: return (sa + fabs(a) * sb / fabs(b)) / fabs(b);
+    case OR_SCAL_PLUS: case OR_SCAL_MINUS_POST: case OR_SCAL_MINUS_PRE: return sa + fabs(k);
+    case OR_SCAL_TIMES: return fabs(k) * sa;
+    case OR_SCAL_DIV_POST: return sa / fabs(k);
+    case OR_SCAL_DIV_PRE: return fabs(k) * sa / (a * a);
+    case OR_ABS: return sa;
+    case OR_SQRT: return sqrt(fabs(a)) + sa / (2.0 * sqrt(fabs(a)));
+    case OR_EXP: return exp(a) * (1.0 + sa);
+    case OR_LOG: return fabs(log(a)) + sa / fabs(a);
+    /* first-order: |f(a)| + |f'(a)| S(a); functions that jump
+     * (floor ... sign) may move by a whole step */
+    case OR_SCAL_POW: return fabs(pow(a, k)) * (1.0 + fabs(k) * sa / fabs(a));
+    case OR_LOG10: return fabs(log10(a)) + sa / (fabs(a) * log(10.0));
+    case OR_LOG2: return fabs(log2(a)) + sa / (fabs(a) * log(2.0));
+    case OR_EXP2: return exp2(a) * (1.0 + sa * log(2.0));
+    case OR_SQUARE: return sa * sa;
+    case OR_FLOOR: case OR_CEIL: case OR_ROUND: case OR_TRUNC: return sa + 1.0;
+    case OR_SIGN: return 1.0;
+    case OR_COS: case OR_SIN: return 1.0 + sa;
+    case OR_TAN: return fabs(tan(a)) + sa * (1.0 + tan(a) * tan(a));
+    case OR_ACOS: case OR_ASIN: return fabs(apply_op(op, a, 0.0, 0.0)) + sa / sqrt(fabs(1.0 - a * a));
+    case OR_ATAN: return fabs(atan(a)) + sa / (1.0 + a * a);
+    case OR_COSH: case OR_SINH: return cosh(a) * (1.0 + sa);
+    case OR_TANH: return fabs(tanh(a)) + sa;
+    }
+    /* relational: the result is exact for the operands it is given; its
+     * magnitude is at most 1 */
+    return is_relational(op) ? 1.0 : 0.0;
+}
+
 /* ---- unfused evaluation: one temporary per node ------------------------ */
 /*
  * Evaluates the whole tree into `out` (root shape, column-major, ld = rows).
@@ -343,40 +384,7 @@ int oracle_eval(const or_node* nd, int nn, const or_leaf* lv, int nl, int mode,
                     v = to_prec(apply_op(N->op, a, b, k), prec, mode);
                     if (scale) {
                         double sa = sc[N->a][j], sb = is_binary(N->op) ? sc[N->b][j] : 0.0;
-                        switch (N->op) {
-                        case OR_PLUS: case OR_MINUS: s = sa + sb; break;
-                        case OR_SCHUR: s = sa * sb; break;
-                        case OR_DIV: s = (sa + fabs(a) * sb / fabs(b)) / fabs(b); break;
-                        case OR_SCAL_PLUS: case OR_SCAL_MINUS_POST: case OR_SCAL_MINUS_PRE:
-                            s = sa + fabs(k); break;
-                        case OR_SCAL_TIMES: s = fabs(k) * sa; break;
-                        case OR_SCAL_DIV_POST: s = sa / fabs(k); break;
-                        case OR_SCAL_DIV_PRE: s = fabs(k) * sa / (a * a); break;
-                        case OR_ABS: s = sa; break;
-                        case OR_SQRT: s = sqrt(fabs(a)) + sa / (2.0 * sqrt(fabs(a))); break;
-                        case OR_EXP: s = exp(a) * (1.0 + sa); break;
-                        case OR_LOG: s = fabs(log(a)) + sa / fabs(a); break;
-                        /* first-order: |f(a)| + |f'(a)| S(a); functions that jump
-                         * (floor ... sign) may move by a whole step */
-                        case OR_SCAL_POW: s = fabs(pow(a, k)) * (1.0 + fabs(k) * sa / fabs(a)); break;
-                        case OR_LOG10: s = fabs(log10(a)) + sa / (fabs(a) * log(10.0)); break;
-                        case OR_LOG2: s = fabs(log2(a)) + sa / (fabs(a) * log(2.0)); break;
-                        case OR_EXP2: s = exp2(a) * (1.0 + sa * log(2.0)); break;
-                        case OR_SQUARE: s = sa * sa; break;
-                        case OR_FLOOR: case OR_CEIL: case OR_ROUND: case OR_TRUNC: s = sa + 1.0; break;
-                        case OR_SIGN: s = 1.0; break;
-                        case OR_COS: case OR_SIN: s = 1.0 + sa; break;
-                        case OR_TAN: s = fabs(tan(a)) + sa * (1.0 + tan(a) * tan(a)); break;
-                        case OR_ACOS: case OR_ASIN: s = fabs(apply_op(N->op, a, 0.0, 0.0)) + sa / sqrt(fabs(1.0 - a * a)); break;
-                        case OR_ATAN: s = fabs(atan(a)) + sa / (1.0 + a * a); break;
-                        case OR_COSH: case OR_SINH: s = cosh(a) * (1.0 + sa); break;
-                        case OR_TANH: s = fabs(tanh(a)) + sa; break;
-                        default:
-                            /* relational: the result is exact for the operands
-                             * it is given; its magnitude is at most 1 */
-                            if (is_relational(N->op)) s = 1.0;
-                            break;
-                        }
+                        s = scale_op(N->op, a, b, k, sa, sb);
                     }
                 }
                 val[i][j] = v;
@@ -416,20 +424,31 @@ int oracle_shape(const or_node* nd, int nn, const or_leaf* lv, int nl,
 /* Independent second evaluator used to check sampled outputs of very large
  * workloads without materialising temporaries. */
 static double point(const or_node* nd, const node_info* info, const or_leaf* lv, int i,
-                    int64_t r, int64_t c, int mode)
+                    int64_t r, int64_t c, int mode, double* s)
 {
     const or_node* N = &nd[i];
-    if (N->op == OR_LEAF) return leaf_at(&lv[N->a], r, c);
-    if (N->op == OR_TRANS) return point(nd, info, lv, N->a, c, r, mode);
-    double a = point(nd, info, lv, N->a, r, c, mode);
-    if (N->op == OR_CONV) return oracle_round_to(N->b, a);
-    double b = is_binary(N->op) ? point(nd, info, lv, N->b, r, c, mode) : 0.0;
+    if (N->op == OR_LEAF) {
+        double v = leaf_at(&lv[N->a], r, c);
+        if (s) *s = fabs(v);
+        return v;
+    }
+    if (N->op == OR_TRANS) return point(nd, info, lv, N->a, c, r, mode, s);
+    double sa = 0.0, sb = 0.0;
+    double a = point(nd, info, lv, N->a, r, c, mode, s ? &sa : NULL);
+    if (N->op == OR_CONV) {
+        if (s) *s = sa;
+        return oracle_round_to(N->b, a);
+    }
+    double b = is_binary(N->op) ? point(nd, info, lv, N->b, r, c, mode, s ? &sb : NULL) : 0.0;
     double k = is_scalar(N->op) ? scalar_of(N, info[i].prec) : 0.0;
+    if (s) *s = scale_op(N->op, a, b, k, sa, sb);
     return to_prec(apply_op(N->op, a, b, k), info[i].prec, mode);
 }
 
+/* Values (and, if `scale` is not NULL, running-error scales) of the root at
+ * the column-major linear indices lin[0..m). */
 int oracle_eval_at(const or_node* nd, int nn, const or_leaf* lv, int nl, int mode,
-                   const int64_t* lin, int64_t m, double* out)
+                   const int64_t* lin, int64_t m, double* out, double* scale)
 {
     node_info* info = (node_info*)calloc((size_t)nn, sizeof(node_info));
     if (!info) return E_NOMEM;
@@ -437,7 +456,7 @@ int oracle_eval_at(const or_node* nd, int nn, const or_leaf* lv, int nl, int mod
     if (rc == OK) {
         int64_t R = info[nn - 1].rows;
         for (int64_t t = 0; t < m; ++t)
-            out[t] = point(nd, info, lv, nn - 1, lin[t] % R, lin[t] / R, mode);
+            out[t] = point(nd, info, lv, nn - 1, lin[t] % R, lin[t] / R, mode, scale ? &scale[t] : NULL);
     }
     free(info);
     return rc;

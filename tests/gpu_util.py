@@ -98,3 +98,41 @@ def classes_match(g, ex) -> bool:
 
 def rel(g: float, o: float) -> float:
     return abs(g - o) / abs(o) if o != 0 else abs(g)
+
+
+# ---- gate of a compensated sum ------------------------------------------------
+U_FP32 = 2.0 ** -24   # unit roundoff of the FP32 accumulation (F32, F16, BF16 data)
+U_FP64 = 2.0 ** -53   # unit roundoff of the FP64 accumulation (F64 and integer data)
+ILL_CONDITIONED = 1e-7
+
+
+def sum_gate(got, o, asum, n_terms, tol, u=U_FP32, what="sum", nonneg=False):
+    """Gate each result of a sum-like reduction against the exact sum o of its
+    terms, whose absolute values add up to asum.
+
+    The gate is the relative error |g - o| / |o| <= tol.  Only where the sum is
+    ill-conditioned, kappa * n * u^2 > 1e-7 with the condition number
+    kappa = asum / |o| and n the number of terms, may the normwise error
+    |g - o| / asum <= tol stand in: a compensated sum in working precision u
+    is accurate to about u |o| + n u^2 asum, so the relative gate is reachable
+    wherever that second term stays well below tol |o|.  nonneg marks sums
+    of nonnegative terms (norms, sums of squares): kappa = 1.  Raises
+    AssertionError naming the result, the gate that applied and both errors;
+    returns the number of results judged by each gate."""
+    g = np.atleast_1d(np.asarray(got, np.float64))
+    o = np.atleast_1d(np.asarray(o, np.float64))
+    a = np.atleast_1d(np.asarray(asum, np.float64))
+    err = np.abs(g - o)
+    with np.errstate(divide="ignore", invalid="ignore"):
+        kappa = np.where(nonneg, 1.0, np.where(o != 0, a / np.abs(o), np.inf))
+        relerr = np.where(o != 0, err / np.abs(o), np.where(err == 0, 0.0, np.inf))
+        normwise = np.where(a > 0, err / a, np.where(err == 0, 0.0, np.inf))
+    fallback = kappa * float(n_terms) * u * u > ILL_CONDITIONED
+    ok = np.where(fallback, normwise <= tol, relerr <= tol)
+    if not np.all(ok):
+        k = int(np.nonzero(~ok)[0][0])
+        gate = "normwise (ill-conditioned)" if fallback[k] else "relative"
+        raise AssertionError(
+            f"{what}[{k}] fails the {gate} gate {tol:g}: gpu={g[k]!r} exact={o[k]!r} rel={relerr[k]:.3e} "
+            f"normwise={normwise[k]:.3e} kappa={kappa[k]:.3e} n={n_terms} ({int(np.sum(~ok))} of {o.size} fail)")
+    return {"relative": int(np.sum(~fallback)), "normwise": int(np.sum(fallback))}

@@ -55,12 +55,7 @@ def test_z(data):
     got = Z[torch.from_numpy(idx).cuda()].double().cpu().numpy()
     want = oracle.evaluate_at(t.postfix(), [d["x"], d["y"]], idx, "emu")
     assert np.array_equal(got, want)
-    ex = oracle.evaluate_at(t.postfix(), [d["x"], d["y"]], idx, "exact")
-    # running-error scale S of z (first-order scale rules of the oracle, applied
-    # to this tree): S(sqrt|x|) = 1.5 sqrt|x|, S(x / (1+|y|)) = 2|x| / (1+|y|)
-    xs = d["x"][idx].astype(np.float64)
-    ys = d["y"][idx].astype(np.float64)
-    S = 1.5 * np.sqrt(np.abs(xs)) * np.abs(ys) + 2.0 * np.abs(xs) / (1 + np.abs(ys))
+    ex, S = oracle.evaluate_at(t.postfix(), [d["x"], d["y"]], idx, "exact", scale=True)
     tol = 2e-7 if dt == "f32" else 1e-15
     assert np.max(np.abs(got - ex) / S) <= tol
 

@@ -13,7 +13,7 @@ import pytest
 import oracle
 import synth
 
-from gpu_util import dev, empty, host, need_gpu, same, torch
+from gpu_util import dev, empty, host, need_gpu, same, sum_gate, torch
 
 pytestmark = pytest.mark.gpu
 
@@ -81,8 +81,7 @@ def test_small_workload(fe):
     o, _, _ = oracle.reduce("accu", trees["accu_AB"].postfix(), ops)
     assert abs(s.item() - o[0]) <= 1e-6 * abs(o[0])
     oc, _, asum = oracle.reduce("sum", synth.leaf(0).postfix(), [mats["A"]], dim=0)
-    err = np.abs(colsum.double().cpu().numpy() - oc)
-    assert np.all((err <= 1e-6 * np.abs(oc)) | (err <= 1e-6 * asum))
+    sum_gate(colsum.double().cpu().numpy(), oc, asum, 67, 1e-6, what="sum(A, 0)")
     _, oi, _ = oracle.reduce("index_max", trees["absB"].postfix(), ops, mode="emu")
     assert idx.item() == oi[0]
 
@@ -91,15 +90,21 @@ def test_in_place_updates(fe, g):
     n = 300
     A = g.uniform(-1, 1, (n, n)).astype(np.float32)
     B = g.uniform(-1, 1, (n, n)).astype(np.float32)
-    dA, dB = dev(synth.Mat(np.asfortranarray(A), "f32")), dev(synth.Mat(np.asfortranarray(B), "f32"))
+    Am, Bm = synth.Mat(np.asfortranarray(A), "f32"), synth.Mat(np.asfortranarray(B), "f32")
+    dA, dB = dev(Am), dev(Bm)
     run(fe, "fe_in_place", ptr(dA), ptr(dB), n)
-    a = (A.T + np.float32(1.0)).astype(np.float32)
-    b = B + a
-    b = b * a
-    b = b * np.float32(0.5)
-    b = b - np.float32(1.0)
-    assert np.array_equal(host(dA), a.astype(np.float64))
-    assert np.array_equal(host(dB), b.astype(np.float64))
+    # the statements one after the other, each evaluated by the oracle on the
+    # values the previous one stored: a = trans(a) + 1; b += a; b %= a;
+    # b *= 0.5; b -= 1
+    x, y = synth.leaves(2)
+    st = lambda v: synth.Mat(np.asfortranarray(v.astype(np.float32)), "f32")
+    a = oracle.evaluate((synth.trans(x) + 1.0).postfix(), [Am], "emu")
+    b = oracle.evaluate((y + x).postfix(), [st(a), Bm], "emu")
+    b = oracle.evaluate((y % x).postfix(), [st(a), st(b)], "emu")
+    b = oracle.evaluate((y * 0.5).postfix(), [st(a), st(b)], "emu")
+    b = oracle.evaluate((y - 1.0).postfix(), [st(a), st(b)], "emu")
+    assert np.array_equal(host(dA), a)
+    assert np.array_equal(host(dB), b)
 
 
 @pytest.mark.parametrize("k", [0, 4, -3])
@@ -129,10 +134,15 @@ def test_generators(fe):
     L = torch.empty(n, dtype=torch.float64, device="cuda")
     H = np.empty((c, r), np.float32)                  # host, column-major r x c
     run(fe, "fe_generators", ptr(Y), r, c, ptr(L), n, -1.25, 3.5, H.ctypes.data)
-    E = np.eye(r, c)
-    assert np.array_equal(host(Y), 3.0 * E + 1.0 + E)
-    assert np.array_equal(L.cpu().numpy(), oracle.linspace_values(-1.25, 3.5, n))
-    assert np.array_equal(H.T, E.astype(np.float32))
+    # y = 3 * eye(r, c) + ones(r, c) + trans(eye(c, r)), generators as the oracle's dense operands
+    a, b, e = synth.leaves(3)
+    want = oracle.evaluate((3.0 * a + b + synth.trans(e)).postfix(),
+                           [oracle.eye(r, c, "f32"), oracle.fill(r, c, 1.0, "f32"), oracle.eye(c, r, "f32")], "emu")
+    assert np.array_equal(host(Y), want)
+    lw = oracle.evaluate(synth.leaf(0).postfix(), [oracle.linspace(-1.25, 3.5, n, "f64")], "emu")
+    assert np.array_equal(L.cpu().numpy(), lw[:, 0])
+    ew = oracle.evaluate(synth.leaf(0).postfix(), [oracle.eye(r, c, "f32")], "emu")
+    assert np.array_equal(H.T.astype(np.float64), ew)
 
 
 def test_scalar_functions(fe, g):
@@ -174,8 +184,7 @@ def test_fused_conversion_and_dim_statistics(fe, g):
     assert np.array_equal(host(F), f.astype(np.float64))
     Fm = synth.Mat(np.asfortranarray(f), "f32")
     om, _, sm = oracle.reduce("mean", synth.leaf(0).postfix(), [Fm], dim=0)
-    err = np.abs(cm.double().cpu().numpy() - om)
-    assert np.all((err <= 1e-6 * np.abs(om)) | (err <= 1e-6 * sm))
+    sum_gate(cm.double().cpu().numpy(), om, sm, r, 1e-6, what="mean(F, 0)")
     ov, _, _ = oracle.reduce("var", synth.leaf(0).postfix(), [Fm], dim=1)
     assert np.all(np.abs(rv.double().cpu().numpy() - ov) <= 2e-7 * np.abs(ov))
 

@@ -15,7 +15,7 @@ import oracle
 import synth
 from synth import leaf, leaves, trans
 
-from gpu_util import dev, empty, host, need_gpu, same, torch
+from gpu_util import U_FP32, U_FP64, dev, empty, host, need_gpu, same, sum_gate, torch
 
 pytestmark = pytest.mark.gpu
 
@@ -125,8 +125,9 @@ def test_reductions_of_trees_with_generators(g, dt):
             elif op == "max":
                 assert same(got, o), (op, dim)
             else:
-                err = np.abs(got - o)
-                assert np.all((err <= tol * np.abs(o)) | (err <= tol * asum)), (op, dim)
+                r_, c_ = 513, 300
+                n = r_ * c_ if dim < 0 else (r_ if dim == 0 else c_)
+                sum_gate(got, o, asum, n, tol, u=U_FP64 if f64 else U_FP32, what=f"{op} dim {dim}")
     # accu(A % eye) is the trace
     t = coot.reduce("accu", x % y, [dev(A), E]).item()
     assert abs(t - np.trace(host(dev(A)))) <= tol * np.sum(np.abs(np.diagonal(host(dev(A)))))
@@ -135,7 +136,7 @@ def test_reductions_of_trees_with_generators(g, dt):
     V = mat(g, (n, 1), dt)
     got = coot.reduce("dot", x % y, [dev(V), coot.linspace(-1.0, 1.0, n, dt)]).item()
     o, _, asum = oracle.reduce("dot", (x % y).postfix(), [V, oracle.linspace(-1.0, 1.0, n, dt)])
-    assert abs(got - o[0]) <= tol * max(abs(o[0]), 1e-3 * asum[0])
+    sum_gate(got, o, asum, n, tol, u=U_FP64 if f64 else U_FP32, what="dot with linspace")
 
 
 @pytest.mark.parametrize("dt", ["f32", "f64", "bf16"])
@@ -183,7 +184,8 @@ def test_diag_trace_diagvec(g, dt):
             assert m == d.max()
         t = coot.trace(A).item()
         o, _, asum = oracle.reduce("accu", X.postfix(), [synth.Mat(np.asfortranarray(np.diagonal(Ah).reshape(1, -1)), "f64")])
-        assert abs(t - o[0]) <= (1e-13 if dt == "f64" else 1e-6) * max(abs(o[0]), 1e-3 * asum[0])
+        sum_gate(t, o, asum, np.diagonal(Ah).size, 1e-13 if dt == "f64" else 1e-6,
+                 u=U_FP64 if dt == "f64" else U_FP32, what=f"trace {shape}")
     # in place through the diagonal: A.diag() += 1
     Am = mat(g, (50, 50), dt)
     A = dev(Am)

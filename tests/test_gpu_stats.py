@@ -5,8 +5,8 @@ any; the count of nonzero elements) against the CPU oracle.
 Gates: relational trees are bit-exact against the oracle's per-node rounded
 evaluation (a comparison is exact for the operands it is given); count, all
 and any are exact; the mean follows the sum gate (1e-6 relative for FP32
-data, 1e-13 for FP64, on the ill-conditioned fallback of the summed terms'
-scale); var and stddev, accumulated in FP64 for every storage type, within
+data, 1e-13 for FP64; the summed terms' scale stands in only for
+ill-conditioned sums); var and stddev, accumulated in FP64 for every storage type, within
 1e-12 relative of the oracle's two-pass variance of the same per-node rounded
 values."""
 import numpy as np
@@ -16,7 +16,7 @@ import oracle
 import synth
 from synth import eq, leaf, leaves, ne, trans
 
-from gpu_util import dev, empty, host, need_gpu, same, torch
+from gpu_util import U_FP32, U_FP64, dev, empty, host, need_gpu, same, sum_gate, torch
 
 pytestmark = pytest.mark.gpu
 
@@ -56,12 +56,12 @@ def check_mean(tree, mats, dim=-1, f64=False):
     got = red("mean", tree, mats, dim).astype(np.float64)
     o, _, scale = oracle.reduce("mean", tree.postfix(), mats, dim=dim, mode="emu")
     tol = 1e-13 if f64 else 1e-6
-    for k in range(o.size):
-        if np.isnan(o[k]):
-            assert np.isnan(got[k])
-            continue
-        err = abs(got[k] - o[k])
-        assert err <= tol * abs(o[k]) or err <= tol * scale[k], (k, got[k], o[k], scale[k])
+    nan = np.isnan(o)
+    assert np.array_equal(np.isnan(got), nan)
+    r, c, prec = oracle.shape(tree, mats)
+    n = r * c if dim < 0 else (r if dim == 0 else c)
+    # the mean is a sum divided once: the sum's gate, with the oracle's mean of |terms|
+    sum_gate(got[~nan], o[~nan], scale[~nan], n, tol, u=U_FP64 if prec == 64 else U_FP32, what=f"mean dim {dim}")
 
 
 def check_var(op, tree, mats, dim=-1, tol=1e-12):
@@ -115,7 +115,7 @@ def test_relational_in_larger_and_transposed_trees(g):
 
 
 @pytest.mark.parametrize("dt", ["f32", "f64", "f16", "bf16"])
-@pytest.mark.parametrize("shape", [((1 << 20) + 3, 1), (1000, 300), (3, 100000), (100000, 3)])
+@pytest.mark.parametrize("shape", [((1 << 20) + 3, 1), (1000, 300), (3, 100000), (100000, 3), (1000, 5000)])
 def test_predicate_counts_exact(g, dt, shape):
     A = mat(g, shape, dt)
     for tree in (X > 0.3, 0.3 > X, ne(X, 0.0), X):
@@ -137,8 +137,11 @@ def test_all_any_on_all_true_and_all_false(g):
 
 
 @pytest.mark.parametrize("dt", ["f32", "f64", "f16", "bf16"])
-@pytest.mark.parametrize("shape", [((1 << 20) + 3, 1), (1000, 300), (3, 100000), (100000, 3), (64, 64)])
+@pytest.mark.parametrize("shape", [((1 << 20) + 3, 1), (1000, 300), (3, 100000), (100000, 3), (64, 64),
+                                   (1000, 5000)])
 def test_mean_var_stddev(g, dt, shape):
+    """(1000, 5000) gives the per-row reductions 78 column splits: the
+    combine of 16 to 255 splits by four waves per 64 rows."""
     A = mat(g, shape, dt, -2.0, 3.0)
     f64 = dt == "f64"
     for dim in (-1, 0, 1):

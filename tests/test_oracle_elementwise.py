@@ -149,6 +149,29 @@ def test_evaluate_at_agrees_with_unfused(g):
     lin = np.arange(17 * 9)
     pts = oracle.evaluate_at(t.postfix(), mats, lin, "emu")
     assert np.array_equal(pts, full.reshape(-1, order="F"))
+    # the pointwise running-error scale is the unfused one, element for element
+    for mode in ("emu", "exact"):
+        v, S = oracle.evaluate(t.postfix(), mats, mode, scale=True)
+        pv, pS = oracle.evaluate_at(t.postfix(), mats, lin[::-1], mode, scale=True)
+        assert np.array_equal(pv, v.reshape(-1, order="F")[::-1])
+        assert np.array_equal(pS, S.reshape(-1, order="F")[::-1])
+
+
+def test_pointwise_scale_of_z_by_hand(g):
+    """S of z = sqrt|x| % y - x / (1 + |y|), derived by hand from the
+    first-order rules: S(sqrt|x|) = sqrt|x| + |x| / (2 sqrt|x|) = 1.5 sqrt|x|,
+    times S(y) = |y|; S(1 + |y|) = 1 + |y|, so S(x / (1 + |y|)) =
+    (|x| + |x| (1 + |y|) / (1 + |y|)) / (1 + |y|) = 2|x| / (1 + |y|); the
+    difference adds the two."""
+    x = g.standard_normal(4000)
+    y = g.standard_normal(4000)
+    tree = synth.cfg2_trees()["z"]
+    lin = np.arange(4000)[::7]
+    v, S = oracle.evaluate_at(tree.postfix(), [x, y], lin, "exact", scale=True)
+    xs, ys = x[lin], y[lin]
+    want = 1.5 * np.sqrt(np.abs(xs)) * np.abs(ys) + 2.0 * np.abs(xs) / (1.0 + np.abs(ys))
+    assert np.max(np.abs(S - want) / want) <= 4e-16
+    assert np.max(np.abs(v - (np.sqrt(np.abs(xs)) * ys - xs / (1.0 + np.abs(ys))))) <= 1e-15 * np.max(want)
 
 
 def test_leading_dimension_view(g):
