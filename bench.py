@@ -92,9 +92,16 @@ def cpu_baseline(oracle, synth, np, min_s: float = 10.0, max_passes: int = 64):
             total_bytes += (3 + 3 + 2 + 1 + 1) * sz * n
         el += time.perf_counter() - t0
         reps += 1
+    model = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            model = next((ln.split(":", 1)[1].strip() for ln in f if ln.startswith("model name")), None)
+    except OSError:
+        pass
     return {"value": round(total_bytes / el / 1e9, 4), "unit": "GB/s", "cores": 1, "kind": "oracle",
             "sample": f"{reps} pass(es) of the 10 FP32+FP64 calls on 2^22-element vectors "
-                      f"(inputs generated beforehand, untimed), {el:.1f} s"}
+                      f"(inputs generated beforehand, untimed), {el:.1f} s",
+            "host_cpus": os.cpu_count(), "host_cpus_usable": len(os.sched_getaffinity(0)), "cpu_model": model}
 
 
 def main():
@@ -104,6 +111,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--unfused-steps", type=int, default=5)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--headline-only", action="store_true",
+                    help="scale workload: skip the precision, batched and small figures added to the line")
     ap.add_argument("--workload", default="scale",
                     choices=["scale", "costmodel", "batched", "precision", "tiled", "small", "stats"],
                     help="scale (default): the 2^28-element FP32/FP64 calls; costmodel: learned launch "
@@ -225,11 +234,17 @@ def main():
     torch.cuda.synchronize()
     ms_unfused = (time.perf_counter() - t1) / Ku * 1e3
 
-    # the plain-copy ceiling: the library's one-pass streaming 16-byte copy of
-    # the FP32 x (1 GiB read, 1 GiB written)
-    _, Xc, _, _, Zc = bufs[0]
-    copy_us = event_stats(torch, lambda: coot.copy(Zc, Xc))[0]
-    copy_gbs = 2 * Xc.numel() * Xc.element_size() / (copy_us * 1e-6) / 1e9
+    del bufs
+    torch.cuda.empty_cache()
+    # streaming ceilings of each read/write mix (the library's probes, 1 GiB
+    # per stream): element-wise calls (two reads per write) against the 2:1
+    # probe, reductions against the read-only probe
+    log("streaming ceilings")
+    ceil = ceilings(torch, coot)
+    for name, v in per.items():
+        mix = "mix_2to1" if name.split("_")[0] in ("axpy", "z") else "read_only"
+        v["ceiling"] = mix
+        v["frac_of_ceiling"] = round(v["GBps"] / ceil[mix]["GBps"], 4)
 
     # roofline of the dominant kernel (largest share of the step)
     dom_bytes = dict((n, b) for n, b, _ in steps)[dom]
@@ -243,6 +258,16 @@ def main():
         # the counters count only while the kernel they were taken on is unchanged
         if entry and entry.get("kernel") == kernel_names(coot, synth).get(dom):
             traffic = entry.get("bytes")
+
+    extra = {}
+    if not args.headline_only:
+        # the other workloads' headline figures, measured in the same run
+        log("precision: 16384^2 BF16/FP16 column sums, accu, dot")
+        extra["precision_16384sq_bf16_f16"] = precision_calls(np, torch, synth, coot)
+        log("batched: 10,000 matrices")
+        extra["batched_10000_matrices"] = batched_calls(np, torch, synth, coot)
+        log("small: 1000x1000 FP32, warm and cold")
+        extra["small_1000sq_f32"] = small_calls(np, torch, synth, coot)
 
     cpu = None
     if not args.no_cpu:
@@ -275,9 +300,8 @@ def main():
                      "peak": PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / PEAK_GBS, 4), "traffic": traffic},
         "cpu_baseline": cpu,
-        "copy_ceiling": {"kernel": "coot_copy16", "bytes": 2 * Xc.numel() * Xc.element_size(),
-                         "us": round(copy_us, 2), "GBps": round(copy_gbs, 1),
-                         "dominant_frac_of_copy": round(achieved / copy_gbs, 4)},
+        "ceilings": ceil,
+        **extra,
     }
     print(json.dumps(out), flush=True)
 
@@ -361,8 +385,10 @@ def costmodel_workload(args, np, torch, synth, coot):
     print(json.dumps(out), flush=True)
 
 
-def batched_workload(args, np, torch, synth, coot):
-    """10,000 matrices: one graph-replayed launch vs per-matrix fused launches vs unfused per-node launches."""
+def batched_calls(np, torch, synth, coot, reps=20, baselines=True):
+    """10,000 matrices: one graph-replayed launch (through a plan and through
+    the one-call entry) vs per-matrix fused launches vs unfused per-node
+    launches."""
     d = synth.cfg4_inputs()
     shapes, offs = d["shapes"], d["offsets"]
     dA, dB = torch.from_numpy(d["A"]).cuda(), torch.from_numpy(d["Bp"]).cuda()
@@ -380,56 +406,97 @@ def batched_workload(args, np, torch, synth, coot):
         return coot.BatchPlan(Ytree, [coot.F32, coot.F32], ptrs, yshape, out_ptrs=outs, red_tree=Rtree,
                               red_op="accu", red_out=red, flags=flags)
 
-    def timed(p, reps):
-        p.run()
+    def timed(run, reps):
+        run()
         torch.cuda.synchronize()
         a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         t0 = time.perf_counter()
         a.record()
         for _ in range(reps):
-            p.run()
+            run()
         b.record()
         torch.cuda.synchronize()
         return a.elapsed_time(b) / reps, (time.perf_counter() - t0) / reps * 1e3
 
     one = plan(0)
-    t_one, w_one = timed(one, max(10, args.steps))
+    t_one, w_one = timed(one.run, max(10, reps))
+    us_one = event_stats(torch, one.run)[0]
+    desc = coot.BatchDescriptor(Ytree, [coot.F32, coot.F32], ptrs, yshape, out_ptrs=outs, red_tree=Rtree,
+                                red_op="accu", red_out=red)
+    t_call, w_call = timed(lambda: coot.eval_batched(desc), max(10, reps))
     nog = plan(coot.BATCH_NO_GRAPH)
-    t_nog, _ = timed(nog, max(10, args.steps))
-    if args.no_baselines:
-        per = unf = None
-        t_per = t_unf = float("nan")
-    else:
+    t_nog, _ = timed(nog.run, max(10, reps))
+    per = unf = None
+    t_per = t_unf = float("nan")
+    if baselines:
         per = plan(coot.BATCH_PER_ITEM)
-        t_per, w_per = timed(per, 3)
+        t_per, w_per = timed(per.run, 3)
         unf = plan(coot.BATCH_UNFUSED)
-        t_unf, w_unf = timed(unf, 1)
-    out = {
-        "metric": "batched fused evaluation effective GB/s (one graph-replayed launch)",
-        "value": round(nbytes / (t_one * 1e-3) / 1e9, 1), "unit": "GB/s", "n_gpus": 1, "higher_is_better": True,
-        "dtype": "f32", "data": "synthetic: seeded U[-1,1], 10,000 matrices, rows/cols log-uniform in [8, 512]",
-        "config": {"workload": "Y_i = trans(A_i) + 0.5*B_i', r_i = accu(Y_i % Y_i) for 10,000 matrices",
-                   "elements": elems, "algorithmic_bytes": nbytes},
+        t_unf, w_unf = timed(unf.run, 1)
+    for p in (one, nog, per, unf):
+        if p is not None:
+            p.close()
+    return {
+        "elements": elems, "algorithmic_bytes": nbytes,
+        "us_one_replay": round(us_one, 2),
+        "GBps_one_replay": round(nbytes / (us_one * 1e-6) / 1e9, 1),
         "ms_one_launch_graph": round(t_one, 4), "ms_one_launch_direct": round(t_nog, 4),
+        "ms_eval_batched_call": round(t_call, 4), "ms_eval_batched_wall": round(w_call, 4),
         "ms_per_matrix_launches": None if per is None else round(t_per, 3),
         "ms_unfused_per_node": None if unf is None else round(t_unf, 3),
         "speedup_vs_per_matrix": None if per is None else round(t_per / t_one, 2),
         "speedup_vs_unfused": None if unf is None else round(t_unf / t_one, 2),
-        "frac_of_peak": round(nbytes / (t_one * 1e-3) / 1e9 / PEAK_GBS, 4),
+        "frac_of_peak": round(nbytes / (us_one * 1e-6) / 1e9 / PEAK_GBS, 4),
     }
-    for p in (one, nog, per, unf):
-        if p is not None:
-            p.close()
+
+
+def batched_workload(args, np, torch, synth, coot):
+    """10,000 matrices: one graph-replayed launch vs per-matrix fused launches vs unfused per-node launches."""
+    r = batched_calls(np, torch, synth, coot, reps=args.steps, baselines=not args.no_baselines)
+    out = {
+        "metric": "batched fused evaluation effective GB/s (one graph-replayed launch)",
+        "value": r["GBps_one_replay"], "unit": "GB/s", "n_gpus": 1, "higher_is_better": True,
+        "dtype": "f32", "data": "synthetic: seeded U[-1,1], 10,000 matrices, rows/cols log-uniform in [8, 512]",
+        "config": {"workload": "Y_i = trans(A_i) + 0.5*B_i', r_i = accu(Y_i % Y_i) for 10,000 matrices",
+                   "elements": r["elements"], "algorithmic_bytes": r["algorithmic_bytes"]},
+        **{k: v for k, v in r.items() if k not in ("elements", "algorithmic_bytes")},
+    }
     print(json.dumps(out), flush=True)
 
 
-def precision_workload(args, np, torch, synth, coot):
-    """16384 x 16384 BF16/FP16: column sums, accu, dot, plain vs compensated FP32 accumulation."""
+def cfg3_device_inputs(torch, dt, tdt, n_rows=16384, n_cols=16384, seed=2308_3120_3):
+    """The precision workload's two matrices drawn on the device with a seeded
+    torch generator: |x| = exp(3 z), z ~ N(0,1) clipped to +-ln(1e4)/3, random
+    signs, stored (round to nearest even) in the 16-bit type; column-major.
+    The same distribution as the host recipe the parity tests use, drawn in
+    milliseconds instead of a minute (timing only: HBM-bound calls whose cost
+    does not depend on the values)."""
+    import math
+
+    g = torch.Generator(device="cuda")
+    g.manual_seed(seed)
+    clip = math.log(1e4) / 3.0
+    mats = []
+    for _ in range(2):
+        z = torch.randn(n_cols, n_rows, generator=g, device="cuda").clamp_(-clip, clip)
+        sign = torch.randint(0, 2, (n_cols, n_rows), generator=g, device="cuda").float().mul_(2.0).sub_(1.0)
+        mats.append((sign * torch.exp(3.0 * z)).to(tdt).t())
+        del z, sign
+    return mats
+
+
+def precision_calls(np, torch, synth, coot, host_inputs=False):
+    """16384 x 16384 BF16/FP16: column sums, accu, dot, plain vs compensated
+    FP32 accumulation; median single-call device times."""
     res = {}
     for dt, tdt in (("bf16", torch.bfloat16), ("f16", torch.float16)):
-        d = synth.cfg3_inputs(dt)
-        A = torch.from_numpy(np.ascontiguousarray(d["A"].data.T).view(np.int16)).view(tdt).cuda().t()
-        B = torch.from_numpy(np.ascontiguousarray(d["B"].data.T).view(np.int16)).view(tdt).cuda().t()
+        if host_inputs:
+            d = synth.cfg3_inputs(dt)
+            A = torch.from_numpy(np.ascontiguousarray(d["A"].data.T).view(np.int16)).view(tdt).cuda().t()
+            B = torch.from_numpy(np.ascontiguousarray(d["B"].data.T).view(np.int16)).view(tdt).cuda().t()
+            del d
+        else:
+            A, B = cfg3_device_inputs(torch, dt, tdt)
         x, y = synth.leaves(2)
         calls = (("colsum", lambda pw: coot.reduce("sum", x, [A], dim=0, pairwise=pw), 2),
                  ("accu", lambda pw: coot.reduce("accu", x, [A], pairwise=pw), 2),
@@ -444,12 +511,41 @@ def precision_workload(args, np, torch, synth, coot):
                 res[f"{name}_{dt}_{'pairwise' if pw else 'kahan'}"] = {
                     "us": round(us, 2), "GBps": round(nb * A.numel() / (us * 1e-6) / 1e9, 1)}
         del A, B
+        torch.cuda.empty_cache()
+    return res
+
+
+def precision_workload(args, np, torch, synth, coot):
+    """16384 x 16384 BF16/FP16: column sums, accu, dot, plain vs compensated FP32 accumulation."""
+    res = precision_calls(np, torch, synth, coot, host_inputs=True)
     gb = [v["GBps"] for k, v in res.items() if "kahan" in k]
     out = {"metric": "compensated FP32 reductions of 16-bit storage, effective GB/s", "value": min(gb),
            "unit": "GB/s (slowest compensated call)", "n_gpus": 1, "higher_is_better": True, "dtype": "bf16,f16",
            "data": "synthetic: |x| = exp(3z), z~N(0,1) clipped to [1e-4, 1e4], random signs, 16384^2",
            "per_call": res}
     print(json.dumps(out), flush=True)
+
+
+def ceilings(torch, coot, nbytes=1 << 30):
+    """Median device time and GB/s of the library's streaming probes over
+    `nbytes` per stream: read only, write only, 1:1 copy, 2 reads : 1 write;
+    plus the 2:1 ceiling derived from the read-only and write-only rates
+    (time of 2 read streams at the read rate plus 1 write stream at the write
+    rate)."""
+    src = torch.zeros(2 * nbytes // 4, dtype=torch.float32, device="cuda")
+    dst = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda")
+    res = {}
+    for name, kind, moved in (("read_only", coot.PROBE_READ, nbytes), ("write_only", coot.PROBE_WRITE, nbytes),
+                              ("copy_1to1", coot.PROBE_COPY, 2 * nbytes),
+                              ("mix_2to1", coot.PROBE_READ2_WRITE1, 3 * nbytes)):
+        us = event_stats(torch, lambda: coot.bandwidth_probe(kind, dst, src, nbytes))[0]
+        res[name] = {"us": round(us, 2), "GBps": round(moved / (us * 1e-6) / 1e9, 1)}
+    r, w = res["read_only"]["GBps"], res["write_only"]["GBps"]
+    res["mix_2to1_derived"] = {"GBps": round(3.0 / (2.0 / r + 1.0 / w), 1)}
+    res["bytes_per_stream"] = nbytes
+    del src, dst
+    torch.cuda.empty_cache()
+    return res
 
 
 def event_stats(torch, fn, reps=21, between=None):
@@ -527,7 +623,7 @@ def tiled_workload(args, np, torch, synth, coot):
                       "data": "synthetic: torch.rand on the device", "per_call": res}), flush=True)
 
 
-def small_workload(args, np, torch, synth, coot):
+def small_calls(np, torch, synth, coot):
     """The 1000 x 1000 FP32 calls: device time (events; warm = inputs in the 256 MB
     last-level cache, cold = a 512 MiB write between calls) and the paper-style host
     wall clock around call + synchronise (the host's preparation included); fused
@@ -563,6 +659,13 @@ def small_workload(args, np, torch, synth, coot):
             res[f"{name}_{'unfused' if u else 'fused'}"] = {
                 "us_warm_median": round(warm[0], 1), "us_cold_median": round(cold[0], 1),
                 "us_wall_median": round(walls[10], 1), "GBps_warm": round(bpe * 1e6 / (warm[0] * 1e-6) / 1e9, 1)}
+    del scratch
+    torch.cuda.empty_cache()
+    return res
+
+
+def small_workload(args, np, torch, synth, coot):
+    res = small_calls(np, torch, synth, coot)
     tot_f = sum(v["us_wall_median"] for k, v in res.items() if k.endswith("_fused"))
     tot_u = sum(v["us_wall_median"] for k, v in res.items() if k.endswith("_unfused"))
     print(json.dumps({"metric": "1000x1000 FP32 calls, host wall clock per call set (call + synchronise)",

@@ -341,17 +341,27 @@ int coot_precompile_end(int kernels_per_module);
  * NULL, Y_i is stored there in out_dtype.  If red_expr is not NULL, r_i =
  * red_op of red_expr evaluated on Y_i (red_expr's slot 0 is Y_i itself; only
  * the sum-like red_ops ACCU, SUM(dim -1), DOT, NORM1, NORM2 are allowed) is
- * written to red_out[i] (red_dtype F32 or F64).  Each item's 64x64 tiles are
- * cut into tasks of at most 4 tiles; on the host, items are spread over the
- * XCDs (each with its own L2) and each XCD's tasks over its blocks, longest
- * first, so that tiles sharing cache lines run under one L2; each task
- * leaves a compensated partial, and the combine
- * launch adds an item's partials in task order in FP64, so r_i depends only
- * on the item's shape and values (deterministic).  expr->cfg.split (if not
- * 0) sets the tile pass's grid to 4*split blocks per CU (default 8).  The
- * plan copies the tables to the device and, unless COOT_BATCH_NO_GRAPH is
- * set, captures the launches in a hipGraph that coot_batch_run replays.  The caller keeps every pointer valid while the
- * plan lives. */
+ * written to red_out[i] (red_dtype F32 or F64).  Each item's value is cut,
+ * by its shape alone, into units of at most 16384 elements (fewer when the
+ * operands read through trans() are wide: they are staged in 64 KiB of LDS):
+ * whole columns where the columns are short, 64-column blocks where they are
+ * long, and an item of at most a quarter of that one unit of its own.  One
+ * pass runs every unit: a large unit per block, small ones four to a block
+ * (one per wave); on the host, items are spread over the XCDs (each with its
+ * own L2), largest first, so that the units of an item share one L2.  Each
+ * unit leaves a compensated partial, and the combine launch adds an item's
+ * partials in unit order in FP64, so r_i depends only on the item's shape and
+ * values (deterministic, and the same in any batch).  expr->cfg is ignored.
+ * The plan copies the tables to the device and, unless COOT_BATCH_NO_GRAPH is
+ * set, captures the launches in a hipGraph that coot_batch_run replays.  The
+ * caller keeps every pointer valid while the plan lives.
+ *
+ * Aliasing: all units of all items may run at once, so an item's output may
+ * overlap only its own operand slot s, and only as the in-place form of the
+ * single-matrix rule (same first byte, same size, same element type, slot s
+ * never read through trans()); any other overlap of an output with an
+ * operand, another output or red_out fails with COOT_ERR_ALIAS before
+ * anything is allocated or launched. */
 typedef struct coot_batch {
     const coot_expr* expr;
     int32_t n_slots;
@@ -383,6 +393,17 @@ int coot_batch_run(coot_batch_plan* plan, void* stream);
 int64_t coot_batch_kernel_source(const coot_batch* batch, char* buf, int64_t cap);
 int coot_batch_destroy(coot_batch_plan* plan);
 
+/* One call for a batch (Section 6, collections of matrices; Section 3, small
+ * matrices use a GPU poorly): the first call with a descriptor builds its plan
+ * (coot_batch_create), later calls with a descriptor of identical contents
+ * (trees, dtypes, shapes, every pointer, flags) replay the plan's graph on
+ * `stream` (coot_batch_run).  The library keeps the plans of the 16 most
+ * recently used descriptors and frees them in coot_finalize; the caller keeps
+ * the memory a descriptor names valid while its plan may be replayed.  Errors
+ * and aliasing rules are those of coot_batch_create and coot_batch_run;
+ * dropping the oldest plan synchronises the device. */
+int coot_eval_batched(const coot_batch* batch, void* stream);
+
 /* ---------------------------------------------- launch-configuration choice -- */
 /* The configuration space: 64 configurations, index
  * cfg = ept_i*16 + block_i*4 + split_i with ept = 1<<ept_i, block = 64<<block_i,
@@ -398,7 +419,22 @@ int coot_config_of(int index, coot_config* cfg);
  *                      by coot_model_set), with the tuned cache taking
  *                      precedence and the default as the fallback. */
 enum { COOT_TUNE_DEFAULT = 0, COOT_TUNE_CACHE = 1, COOT_TUNE_MODEL = 2 };
+/* A model file (model_path) holds the 8 bytes "COOTMLP2", the feature schema
+ * (uint32, COOT_FEATURE_SCHEMA), a zero uint32, the kernel stamp it was
+ * trained on (uint64, coot_kernel_stamp), then COOT_MLP_N_PARAMS + 64 FP32
+ * values (parameters, feature means, feature standard deviations).  A file
+ * with another layout, schema or stamp is rejected with COOT_ERR_ARG and a
+ * message; tuning then falls back to COOT_TUNE_CACHE (the tuned cache, then
+ * the default) and no model stays installed. */
 int coot_set_tuning(int mode, const char* model_path);
+
+/* Identity of what the 64 configurations run, for cost-model files: a hash
+ * over the device prelude and, for a fixed set of calls covering every kernel
+ * kind, the generated source and launch geometry of each configuration.
+ * Writes it to *stamp and returns COOT_FEATURE_SCHEMA, the layout version of
+ * coot_features.  Host only. */
+#define COOT_FEATURE_SCHEMA 1
+int coot_kernel_stamp(uint64_t* stamp);
 
 /* Index of the fixed heuristic's configuration for this call.  Host only. */
 int coot_default_config(int red_op, int dim, const coot_expr* expr, const coot_operand* ops,
@@ -443,7 +479,9 @@ int coot_mlp_adam(float* params, const float* grad, float* m, float* v, int n, i
  * the feature standardisation: mean[32], std[32]) for COOT_TUNE_MODEL. */
 int coot_model_set(const float* params, const float* feat_mean, const float* feat_std);
 
-/* Configuration index the installed model picks for this call (host only). */
+/* Configuration index the installed model picks for this call.  Runs the
+ * model's forward kernel on the device (a private stream, synchronised before
+ * returning); the call itself is not launched. */
 int coot_model_choose(int red_op, int dim, const coot_expr* expr, const coot_operand* ops,
                       int n_ops, const coot_operand* out);
 
@@ -460,6 +498,20 @@ int coot_get_stats(coot_stats* stats);
 /* Plain device-to-device copy of `bytes` bytes with the library's streaming
  * kernel (the bandwidth ceiling the fused kernels are compared with). */
 int coot_copy(void* dst, const void* src, int64_t bytes, void* stream);
+
+/* Bandwidth probes: the simplest streaming kernels with a given mix of reads
+ * and writes, launched like the fused element-wise kernels' default (one
+ * pass, 256 threads, four 16-byte vectors per thread, nontemporal loads and
+ * stores), so that a fused call can be compared with the ceiling of its own
+ * read/write mix.  `bytes` (a multiple of 16) is the length of each stream;
+ * pointers are 16-byte aligned device memory:
+ *   COOT_PROBE_COPY          dst = src (coot_copy): reads and writes bytes
+ *   COOT_PROBE_READ          reads src; dst (16 bytes) is written only if a
+ *                            thread's XOR of its data has all bits set
+ *   COOT_PROBE_WRITE         writes dst (src unused)
+ *   COOT_PROBE_READ2_WRITE1  dst = src[0, bytes) XOR src[bytes, 2 bytes) */
+enum { COOT_PROBE_COPY = 0, COOT_PROBE_READ = 1, COOT_PROBE_WRITE = 2, COOT_PROBE_READ2_WRITE1 = 3 };
+int coot_bandwidth_probe(int kind, void* dst, const void* src, int64_t bytes, void* stream);
 
 #ifdef __cplusplus
 }

@@ -111,7 +111,8 @@ EXPORTS = [
     "coot_batch_destroy", "coot_config_of", "coot_set_tuning", "coot_features", "coot_autotune",
     "coot_mlp_forward", "coot_mlp_backward", "coot_mlp_adam", "coot_model_set", "coot_model_choose",
     "coot_get_stats", "coot_copy", "coot_precompile_begin", "coot_precompile_end",
-    "coot_default_config", "coot_batch_kernel_source",
+    "coot_default_config", "coot_batch_kernel_source", "coot_eval_batched", "coot_bandwidth_probe",
+    "coot_kernel_stamp",
 ]
 
 
@@ -146,6 +147,7 @@ def lib():
         L.coot_batch_kernel_source.argtypes = [P(Batch), C.c_char_p, i64]
         L.coot_batch_kernel_source.restype = i64
         L.coot_batch_destroy.argtypes = [vp]
+        L.coot_eval_batched.argtypes = [P(Batch), vp]
         L.coot_config_of.argtypes = [i32, P(Config)]
         L.coot_set_tuning.argtypes = [i32, C.c_char_p]
         L.coot_features.argtypes = [i32, i32, P(Expr), P(Operand), i32, P(Operand), P(C.c_float)]
@@ -158,6 +160,8 @@ def lib():
         L.coot_model_choose.argtypes = [i32, i32, P(Expr), P(Operand), i32, P(Operand)]
         L.coot_get_stats.argtypes = [P(Stats)]
         L.coot_copy.argtypes = [vp, vp, i64, vp]
+        L.coot_bandwidth_probe.argtypes = [i32, vp, vp, i64, vp]
+        L.coot_kernel_stamp.argtypes = [P(C.c_uint64)]
         L.coot_precompile_end.argtypes = [i32]
         L.coot_default_config.argtypes = [i32, i32, P(Expr), P(Operand), i32, P(Operand)]
         _lib = L
@@ -513,6 +517,13 @@ def set_tuning(mode: int, model_path: Optional[str] = None) -> None:
     _check(lib().coot_set_tuning(mode, model_path.encode() if model_path else None))
 
 
+def kernel_stamp():
+    """(feature schema, kernel stamp) of the library (coot_kernel_stamp)."""
+    st = C.c_uint64()
+    schema = _check(lib().coot_kernel_stamp(C.byref(st)))
+    return schema, st.value
+
+
 def model_set(params, mean, std) -> None:
     import numpy as np
 
@@ -555,6 +566,16 @@ def copy(dst, src, nbytes: Optional[int] = None, stream=None) -> None:
     _check(lib().coot_copy(dst.data_ptr(), src.data_ptr(), n, stream if stream is not None else current_stream()))
 
 
+PROBE_COPY, PROBE_READ, PROBE_WRITE, PROBE_READ2_WRITE1 = 0, 1, 2, 3
+
+
+def bandwidth_probe(kind: int, dst, src, nbytes: int, stream=None) -> None:
+    """Streaming probe of a read/write mix (coot_bandwidth_probe)."""
+    _check(lib().coot_bandwidth_probe(kind, dst.data_ptr() if dst is not None else None,
+                                      src.data_ptr() if src is not None else None, nbytes,
+                                      stream if stream is not None else current_stream()))
+
+
 def stats() -> dict:
     s = Stats()
     _check(lib().coot_get_stats(C.byref(s)))
@@ -562,19 +583,11 @@ def stats() -> dict:
 
 
 # ---- batched evaluation ---------------------------------------------------
-class BatchPlan:
-    """One persistent launch for many matrices (see coot_batch in coot.h)."""
+class BatchDescriptor:
+    """A marshalled coot_batch (see coot.h): one tree over many matrices."""
 
     def __init__(self, tree, slot_dtypes, leaf_ptrs, shapes, out_ptrs=None, out_dtype=F32, red_tree=None,
-                 red_op="accu", red_out=None, red_dtype=F32, flags=0, stream=None, split=None):
-        self.handle = C.c_void_p()
-        self._describe(tree, slot_dtypes, leaf_ptrs, shapes, out_ptrs, out_dtype, red_tree, red_op,
-                       red_out.data_ptr() if red_out is not None else None, red_dtype, flags, split)
-        _check(lib().coot_batch_create(C.byref(self._b), stream if stream is not None else current_stream(),
-                                       C.byref(self.handle)))
-
-    def _describe(self, tree, slot_dtypes, leaf_ptrs, shapes, out_ptrs, out_dtype, red_tree, red_op, red_out_ptr,
-                  red_dtype, flags, split):
+                 red_op="accu", red_out=None, red_dtype=F32, flags=0, split=None):
         import numpy as np
 
         # split: 4*split blocks per CU for the tile pass (None: library default)
@@ -590,6 +603,7 @@ class BatchPlan:
             self._op = (C.c_void_p * n_items)(*[int(x) for x in out_ptrs])
         sh = np.ascontiguousarray(np.asarray(shapes, dtype=np.int64).reshape(-1))
         self._sh = (C.c_int64 * sh.size)(*[int(x) for x in sh])
+        red_out_ptr = red_out if (red_out is None or isinstance(red_out, int)) else red_out.data_ptr()
         b = Batch()
         b.expr = C.pointer(self._e)
         b.n_slots = n_slots
@@ -604,7 +618,24 @@ class BatchPlan:
         b.red_out = red_out_ptr
         b.red_dtype = red_dtype
         b.flags = flags
-        self._b = b
+        self.struct = b
+
+
+def eval_batched(desc: BatchDescriptor, stream=None) -> None:
+    """coot_eval_batched: build (first call) or replay the batch's launch."""
+    _check(lib().coot_eval_batched(C.byref(desc.struct), stream if stream is not None else current_stream()))
+
+
+class BatchPlan:
+    """One persistent launch for many matrices (see coot_batch in coot.h)."""
+
+    def __init__(self, tree, slot_dtypes, leaf_ptrs, shapes, out_ptrs=None, out_dtype=F32, red_tree=None,
+                 red_op="accu", red_out=None, red_dtype=F32, flags=0, stream=None, split=None):
+        self.handle = C.c_void_p()
+        self.desc = BatchDescriptor(tree, slot_dtypes, leaf_ptrs, shapes, out_ptrs, out_dtype, red_tree, red_op,
+                                    red_out, red_dtype, flags, split)
+        _check(lib().coot_batch_create(C.byref(self.desc.struct), stream if stream is not None else current_stream(),
+                                       C.byref(self.handle)))
 
     @staticmethod
     def kernel_source(tree, slot_dtypes, shapes, out=True, out_dtype=F32, red_tree=None, red_op="accu",
@@ -612,14 +643,12 @@ class BatchPlan:
         """Host only: the HIP source of the batched kernels (pointers are placeholders)."""
         G = 1 << 40
         n = len(shapes)
-        d = BatchPlan.__new__(BatchPlan)
-        d.handle = C.c_void_p()
-        d._describe(tree, slot_dtypes, [[G * (s + 1) for s in range(len(slot_dtypes))]] * n, shapes,
-                    [G * 9] * n if out else None, out_dtype, red_tree, red_op,
-                    G * 10 if red_tree is not None else None, red_dtype, 0, None)
-        size = _check(lib().coot_batch_kernel_source(C.byref(d._b), None, 0))
+        d = BatchDescriptor(tree, slot_dtypes, [[G * (s + 1) for s in range(len(slot_dtypes))]] * n, shapes,
+                            [G * 9] * n if out else None, out_dtype, red_tree, red_op,
+                            G * 10 if red_tree is not None else None, red_dtype, 0, None)
+        size = _check(lib().coot_batch_kernel_source(C.byref(d.struct), None, 0))
         buf = C.create_string_buffer(size + 1)
-        _check(lib().coot_batch_kernel_source(C.byref(d._b), buf, size + 1))
+        _check(lib().coot_batch_kernel_source(C.byref(d.struct), buf, size + 1))
         return buf.value.decode()
 
     def run(self, stream=None) -> None:

@@ -175,15 +175,35 @@ def regret(times: np.ndarray, picks: np.ndarray) -> np.ndarray:
     return times[rows, picks] / times.min(axis=1) - 1.0
 
 
-def save_model(path: str, params, mean, std) -> None:
-    np.concatenate([np.asarray(params, np.float32), np.asarray(mean, np.float32),
-                    np.asarray(std, np.float32)]).astype(np.float32).tofile(path)
+MODEL_MAGIC = b"COOTMLP2"
+
+
+def save_model(path: str, params, mean, std, stamp: Optional[int] = None, schema: Optional[int] = None) -> None:
+    """Write a cost-model file stamped with the library's feature schema and
+    kernel stamp (coot_set_tuning rejects files made for other kernels)."""
+    if stamp is None or schema is None:
+        schema, stamp = coot.kernel_stamp()
+    head = MODEL_MAGIC + np.array([schema, 0], np.uint32).tobytes() + np.array([stamp], np.uint64).tobytes()
+    body = np.concatenate([np.asarray(params, np.float32), np.asarray(mean, np.float32),
+                           np.asarray(std, np.float32)]).astype(np.float32).tobytes()
+    with open(path, "wb") as f:
+        f.write(head + body)
+
+
+def read_model(path: str):
+    """(params, mean, std, schema, stamp) of a cost-model file."""
+    with open(path, "rb") as f:
+        raw = f.read()
+    assert raw[:8] == MODEL_MAGIC, "not a stamped cost-model file"
+    schema, zero = np.frombuffer(raw[8:16], np.uint32)
+    stamp = int(np.frombuffer(raw[16:24], np.uint64)[0])
+    a = np.frombuffer(raw[24:], np.float32)
+    assert zero == 0 and a.size == N_PARAMS + 64, "cost-model file has the wrong size"
+    return a[:N_PARAMS].copy(), a[N_PARAMS:N_PARAMS + 32].copy(), a[N_PARAMS + 32:].copy(), int(schema), stamp
 
 
 def load_model(path: str):
-    a = np.fromfile(path, dtype=np.float32)
-    assert a.size == N_PARAMS + 64, "model file has the wrong size"
-    return a[:N_PARAMS], a[N_PARAMS:N_PARAMS + 32], a[N_PARAMS + 32:]
+    return read_model(path)[:3]
 
 
 def summarize(times, default, picks_model) -> Dict[str, float]:

@@ -10,6 +10,7 @@
 
 namespace {
 
+typedef unsigned int u32;
 typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 
 // dst[i] = src[i] in 16-byte units: one pass, 4 vectors per thread, streaming
@@ -37,6 +38,41 @@ __global__ void __launch_bounds__(256) coot_copy16(u32x4* __restrict__ dst, cons
     }
     if (blockIdx.x == gridDim.x - 1)
         for (int64_t i = threadIdx.x; i < ntail; i += blockDim.x) dtail[i] = stail[i];
+}
+
+// Streaming probes with other read/write mixes, launched like the copy (and
+// like the fused element-wise kernels' default): one pass, 256 threads, 4
+// vectors of 16 bytes per thread, nontemporal.  KIND 1 reads only: the loads
+// are folded into a per-thread XOR that is stored only if all its bits are
+// set (the loads cannot be dropped; random data never stores).  KIND 2 writes
+// only.  KIND 3 reads two streams and writes one (dst = a XOR b), the mix of
+// a two-operand element-wise tree.
+template <int KIND>
+__global__ void __launch_bounds__(256) coot_probe16(u32x4* __restrict__ dst, const u32x4* __restrict__ src, int64_t nv)
+{
+    const int64_t step = (int64_t)gridDim.x * blockDim.x * 4;
+    u32x4 acc = {0u, 0u, 0u, 0u};
+    for (int64_t b = (int64_t)blockIdx.x * blockDim.x * 4 + threadIdx.x; b < nv; b += step) {
+        u32x4 r[4], q[4];
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            const int64_t v = b + (int64_t)e * blockDim.x;
+            if (v < nv) {
+                if (KIND != 2) r[e] = __builtin_nontemporal_load(src + v);
+                if (KIND == 3) q[e] = __builtin_nontemporal_load(src + nv + v);
+            }
+        }
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            const int64_t v = b + (int64_t)e * blockDim.x;
+            if (v < nv) {
+                if (KIND == 1) acc ^= r[e];
+                if (KIND == 2) __builtin_nontemporal_store(u32x4{(u32)v, 0u, 0u, 0u}, dst + v);
+                if (KIND == 3) __builtin_nontemporal_store(r[e] ^ q[e], dst + v);
+            }
+        }
+    }
+    if (KIND == 1 && (acc.x & acc.y & acc.z & acc.w) == 0xffffffffu) dst[0] = acc;
 }
 
 // ---- MLP 32 -> 64 (ReLU) -> 64 -----------------------------------------------
@@ -166,6 +202,26 @@ int coot_copy_launch(void* dst, const void* src, int64_t bytes, int cus, void* s
     if (grid < 1) grid = 1;
     hipLaunchKernelGGL(coot_copy16, dim3((unsigned)grid), dim3(256), 0, (hipStream_t)stream, (u32x4*)dst,
                        (const u32x4*)src, nv, (unsigned char*)dst + nv * 16, (const unsigned char*)src + nv * 16, tail);
+    return hipGetLastError() == hipSuccess ? 0 : -8;
+}
+
+int coot_probe_launch(int kind, void* dst, const void* src, int64_t bytes, void* stream)
+{
+    const int64_t nv = bytes / 16;
+    int64_t need = (nv + 1023) / 1024;
+    int64_t grid = need < INT64_C(0x7fffffff) ? need : INT64_C(0x7fffffff);
+    if (grid < 1) grid = 1;
+    u32x4* d = (u32x4*)dst;
+    const u32x4* sv = (const u32x4*)src;
+    hipStream_t st = (hipStream_t)stream;
+    switch (kind) {
+    case COOT_PROBE_READ: hipLaunchKernelGGL(coot_probe16<1>, dim3((unsigned)grid), dim3(256), 0, st, d, sv, nv); break;
+    case COOT_PROBE_WRITE: hipLaunchKernelGGL(coot_probe16<2>, dim3((unsigned)grid), dim3(256), 0, st, d, sv, nv); break;
+    case COOT_PROBE_READ2_WRITE1:
+        hipLaunchKernelGGL(coot_probe16<3>, dim3((unsigned)grid), dim3(256), 0, st, d, sv, nv);
+        break;
+    default: return -10;
+    }
     return hipGetLastError() == hipSuccess ? 0 : -8;
 }
 

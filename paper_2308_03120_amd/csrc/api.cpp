@@ -259,6 +259,71 @@ static Geometry geometry(const Plan& p, const LaunchCfg& c)
     return G;
 }
 
+// Identity of what the 64 launch configurations run: FNV-1a over the device
+// prelude and, for a fixed set of calls covering every kernel kind, each
+// configuration's generated source and launch geometry.  A cost model timed
+// on other kernels (or another geometry) gets another stamp.
+uint64_t kernel_stamp()
+{
+    const uintptr_t G = uintptr_t(1) << 40;
+    auto op = [&](int k, int64_t r, int64_t c, int dt) {
+        return coot_operand{(void*)(G * (uintptr_t)k), r, c, std::max<int64_t>(1, r), dt, 0, {0.0, 0.0}};
+    };
+    // x, y leaves; z = sqrt(abs(x)) % y - x / (1 + abs(y)); trans(x) + 0.5 y; x % y
+    const coot_node z_tree[] = {{COOT_LEAF, 0, -1, 0, 0.0},       {COOT_ABS, 0, -1, 0, 0.0},
+                                {COOT_SQRT, 1, -1, 0, 0.0},       {COOT_LEAF, 1, -1, 0, 0.0},
+                                {COOT_SCHUR, 2, 3, 0, 0.0},       {COOT_ABS, 3, -1, 0, 0.0},
+                                {COOT_SCAL_PLUS, 5, -1, 0, 1.0},  {COOT_DIV, 0, 6, 0, 0.0},
+                                {COOT_MINUS, 4, 7, 0, 0.0}};
+    const coot_node t_tree[] = {{COOT_LEAF, 0, -1, 0, 0.0},
+                                {COOT_TRANS, 0, -1, 0, 0.0},
+                                {COOT_LEAF, 1, -1, 0, 0.0},
+                                {COOT_SCAL_TIMES, 2, -1, 0, 0.5},
+                                {COOT_PLUS, 1, 3, 0, 0.0}};
+    const coot_node p_tree[] = {{COOT_LEAF, 0, -1, 0, 0.0}, {COOT_LEAF, 1, -1, 0, 0.0}, {COOT_SCHUR, 0, 1, 0, 0.0}};
+    struct Call {
+        int red, dim;
+        const coot_node* nodes;
+        int nn;
+        int64_t r, c;
+        int dt;
+        bool trans;
+    };
+    const Call calls[] = {
+        {-1, -1, z_tree, 9, 1 << 24, 1, COOT_F32, false},  {-1, -1, z_tree, 9, 1 << 24, 1, COOT_F64, false},
+        {-1, -1, z_tree, 9, 1 << 24, 1, COOT_BF16, false}, {COOT_RED_DOT, -1, p_tree, 3, 1 << 24, 1, COOT_F32, false},
+        {COOT_RED_ACCU, -1, p_tree, 3, 1 << 24, 1, COOT_F16, false},
+        {-1, -1, t_tree, 5, 4096, 4096, COOT_F32, true},  {-1, -1, t_tree, 5, 2, 1 << 22, COOT_F32, true},
+        {COOT_RED_ACCU, -1, t_tree, 5, 4096, 4096, COOT_F32, true},
+        {COOT_RED_SUM, 0, p_tree, 3, 4096, 4096, COOT_F32, false}, {COOT_RED_SUM, 0, p_tree, 3, 8, 1 << 16, COOT_F32, false},
+        {COOT_RED_SUM, 1, p_tree, 3, 4096, 4096, COOT_F32, false}, {COOT_RED_SUM, 1, p_tree, 3, 1 << 20, 3, COOT_F64, false},
+    };
+    uint64_t h = fnv1a(prelude_source());
+    auto mix = [&](const std::string& t) { h = fnv1a(hex64(h) + t); };
+    for (const Call& k : calls) {
+        coot_operand ops[2] = {k.trans ? op(1, k.c, k.r, k.dt) : op(1, k.r, k.c, k.dt), op(2, k.r, k.c, k.dt)};
+        const int64_t orows = k.red < 0 ? k.r : (k.dim == 0 ? 1 : (k.dim == 1 ? k.r : 1));
+        const int64_t ocols = k.red < 0 ? k.c : (k.dim == 0 ? k.c : 1);
+        const int odt = k.red < 0 ? k.dt : (k.dt == COOT_F64 ? COOT_F64 : COOT_F32);
+        coot_operand out = op(3, orows, ocols, odt);
+        out.ld = std::max<int64_t>(1, orows);
+        coot_expr e{k.nodes, k.nn, 0, {0, 0, 0, 0}};
+        Plan p = make_plan(k.red, k.dim, &e, ops, 2, &out);
+        // the generated text depends on the configuration only through ept
+        std::unordered_map<int, uint64_t> src_hash;
+        for (int i = 0; i < COOT_N_CONFIGS; ++i) {
+            LaunchCfg c = normalise_config(p, config_of(i));
+            auto it = src_hash.find(c.ept);
+            if (it == src_hash.end()) it = src_hash.emplace(c.ept, fnv1a(kernel_source(p, c, nullptr, nullptr))).first;
+            Geometry g = geometry(p, c);
+            mix(hex64(it->second) + "|" + std::to_string(g.grid) + "," + std::to_string(g.block) +
+                "," + std::to_string(g.splits) + "," + std::to_string(g.comb_grid) + "," + std::to_string(g.aux) +
+                "," + std::to_string(i == config_index(default_config(p))));
+        }
+    }
+    return h;
+}
+
 static void fill_reads(const Plan& p, const coot_operand* ops, coot_kargs& a)
 {
     for (size_t j = 0; j < p.reads.size(); ++j) {
@@ -298,12 +363,17 @@ static int64_t tile_row_shift(const Plan& p, const coot_operand* ops, const coot
 static std::mutex g_sig_mu;
 static std::unordered_map<std::string, Kernel> g_sig_kernels;
 
+static std::string sig_key(const Plan& p, const LaunchCfg& c)
+{
+    return std::to_string(p.kind) + "|" + std::to_string(p.ve) + "|" + std::to_string(c.ept) + "|" +
+           std::to_string(p.out_dtype) + "|" + std::to_string(p.red_op) + "|" + std::to_string(p.pairwise) + "|" +
+           std::to_string(p.alias_out) + "|" + std::to_string(p.tile_gen) + std::to_string(p.tile_off32) +
+           std::to_string(p.tile_lr) + "," + std::to_string(p.tile_lc) + "|" + p.body_sig;
+}
+
 static Kernel kernel_for(const Plan& p, const LaunchCfg& c)
 {
-    std::string key = std::to_string(p.kind) + "|" + std::to_string(p.ve) + "|" + std::to_string(c.ept) + "|" +
-                      std::to_string(p.out_dtype) + "|" + std::to_string(p.red_op) + "|" + std::to_string(p.pairwise) +
-                      "|" + std::to_string(p.alias_out) + "|" + std::to_string(p.tile_gen) + std::to_string(p.tile_off32) +
-                      std::to_string(p.tile_lr) + "," + std::to_string(p.tile_lc) + "|" + p.body_sig;
+    std::string key = sig_key(p, c);
     {
         std::lock_guard<std::mutex> lk(g_sig_mu);
         auto it = g_sig_kernels.find(key);
@@ -360,7 +430,7 @@ void run_plan(const Plan& p, const LaunchCfg& cfg_in, const coot_operand* ops, c
         if ((p.kind == K_RED_ROW || p.kind == K_RED_COL) && G.splits > 1) launch(k.fn2, G.comb_grid, 256, a, st);
     }
     if (host) {
-        hipchk(hipMemcpyAsync(out->ptr, s.res, res_bytes / 8 * (size_t)itemsize(out->dtype), hipMemcpyDeviceToHost, st),
+        hipchk(hipMemcpyAsync(out->ptr, a.res, res_bytes / 8 * (size_t)itemsize(out->dtype), hipMemcpyDeviceToHost, st),
                "hipMemcpyAsync");
         hipchk(hipStreamSynchronize(st), "hipStreamSynchronize");
     }

@@ -10,6 +10,7 @@
 #include <mutex>
 #include <queue>
 #include <set>
+#include <string>
 #include <vector>
 
 #include "internal.h"
@@ -21,8 +22,7 @@ using namespace coot;
 struct coot_batch_plan {
     Kernel k{};
     coot_batch_item_d* d_items = nullptr;
-    coot_batch_task_d* d_tasks = nullptr;
-    int* d_order = nullptr;
+    coot_batch_unit_d* d_units = nullptr;
     int* d_blk_first = nullptr;
     double* d_part = nullptr;
     int64_t n_items = 0;
@@ -83,69 +83,110 @@ void free_plan(coot_batch_plan* p)
     if (p->exec) (void)hipGraphExecDestroy(p->exec);
     if (p->graph) (void)hipGraphDestroy(p->graph);
     (void)hipFree(p->d_items);
-    (void)hipFree(p->d_tasks);
+    (void)hipFree(p->d_units);
     (void)hipFree(p->d_part);
-    (void)hipFree(p->d_order);
     (void)hipFree(p->d_blk_first);
     delete p;
 }
 
-// Longest-processing-time-first assignment of tasks to blocks: the costliest
-// remaining task goes to the least loaded block (ties: lowest block).  Cost of
-// a task: its tiles plus a fixed share for its partial reduction.
-//
-// XCD-aware: the blocks of XCD x are x, x + X, x + 2X, ... (X = xcds), and
-// each XCD has its own L2.  Neighbouring tiles of a matrix share the cache
-// lines at their edges, so a matrix's tasks all go to one XCD: matrices are
-// first spread over the XCDs by LPT on their total cost, then each XCD's
-// tasks over its own blocks by LPT.
-void lpt_schedule(const std::vector<coot_batch_task_d>& tasks, int64_t n_items, int64_t n_blocks, int xcds,
-                  std::vector<int>* order, std::vector<int>* first)
+// Units of item `item` (Y_i of R x Cn) for units of at most E elements, in
+// order (their partial slots follow this order):
+//  - an item of at most E/4 elements whose staged rows fit a quarter of the
+//    LDS stage is one unit (a small unit: a wave can run it);
+//  - short columns (R <= E/32): units of whole columns, k >= 32 of them, the
+//    item split into equal parts (contiguous runs of Y_i);
+//  - long columns: 64-column blocks of E/64 rows.
+// Every unit fits the stage: rc * (k + 1) <= E + E/32.
+bool item_units(int item, int64_t R, int64_t Cn, int64_t E, std::vector<coot_batch_unit_d>* out)
 {
-    const int64_t n = (int64_t)tasks.size();
-    auto cost = [&](int i) { return (double)(tasks[(size_t)i].t1 - tasks[(size_t)i].t0) + 0.25; };
+    const int64_t n = R * Cn;
+    if (n == 0) return false;
+    const int64_t cap = coot_batch_stage_cap(E);
+    auto push = [&](int64_t p0, int64_t q0, int64_t rc, int64_t k) {
+        out->push_back(coot_batch_unit_d{item, (int)p0, (int)q0, (int)rc, (int)k, 0});
+    };
+    if (n <= E / 4 && R * (Cn | 1) <= cap / 4) {
+        push(0, 0, R, Cn);
+        return true;
+    }
+    if (R <= E / 32) {
+        const int64_t kmax = E / R;
+        const int64_t nq = (Cn + kmax - 1) / kmax;
+        const int64_t k = (Cn + nq - 1) / nq;
+        for (int64_t q0 = 0; q0 < Cn; q0 += k) push(0, q0, R, std::min(k, Cn - q0));
+        return false;
+    }
+    const int64_t rc = E / 64, kc = 64;
+    for (int64_t q0 = 0; q0 < Cn; q0 += kc)
+        for (int64_t p0 = 0; p0 < R; p0 += rc) push(p0, q0, std::min(rc, R - p0), std::min(kc, Cn - q0));
+    return false;
+}
+
+// Block schedule.  XCD-aware: blocks x, x + X, x + 2X, ... (X = xcds) run on
+// XCD x, whose L2 the XCD's blocks share, so all units of an item go to one
+// XCD (items spread over the XCDs longest first, each to the least loaded);
+// an XCD runs its large items' units first, largest item first, each unit a
+// block of its own, then its small units four to a block.  Shorter XCD lists
+// are padded with empty blocks.  Returns the units in block order and each
+// block's first unit.
+void schedule_units(const std::vector<std::vector<coot_batch_unit_d>>& per_item, const std::vector<bool>& small,
+                    int xcds, std::vector<coot_batch_unit_d>* units, std::vector<int>* first)
+{
+    const int64_t n_items = (int64_t)per_item.size();
+    const int64_t X = std::max(1, xcds);
+    auto cost = [&](int64_t i) {
+        double c = 0.0;
+        for (const auto& u : per_item[(size_t)i]) c += (double)u.rc * u.k + 256.0;
+        return c;
+    };
+    std::vector<int64_t> items;
+    std::vector<double> icost((size_t)n_items);
+    for (int64_t i = 0; i < n_items; ++i) {
+        icost[(size_t)i] = cost(i);
+        if (!per_item[(size_t)i].empty()) items.push_back(i);
+    }
+    std::stable_sort(items.begin(), items.end(), [&](int64_t a, int64_t b) { return icost[(size_t)a] > icost[(size_t)b]; });
     typedef std::pair<double, int64_t> Load;
-    const int64_t X = (xcds > 1 && n_blocks % xcds == 0) ? xcds : 1;
-    // matrices -> XCDs
-    std::vector<double> icost((size_t)std::max<int64_t>(n_items, 1), 0.0);
-    for (int64_t i = 0; i < n; ++i) icost[(size_t)tasks[(size_t)i].item] += cost((int)i);
-    std::vector<int> items((size_t)n_items);
-    for (int64_t i = 0; i < n_items; ++i) items[(size_t)i] = (int)i;
-    std::stable_sort(items.begin(), items.end(), [&](int a, int b) { return icost[(size_t)a] > icost[(size_t)b]; });
-    std::vector<int64_t> xcd_of((size_t)std::max<int64_t>(n_items, 1), 0);
-    {
-        std::priority_queue<Load, std::vector<Load>, std::greater<Load>> heap;
-        for (int64_t x = 0; x < X; ++x) heap.push(Load(0.0, x));
-        for (int i : items) {
-            Load l = heap.top();
-            heap.pop();
-            xcd_of[(size_t)i] = l.second;
-            heap.push(Load(l.first + icost[(size_t)i], l.second));
-        }
+    std::priority_queue<Load, std::vector<Load>, std::greater<Load>> heap;
+    for (int64_t x = 0; x < X; ++x) heap.push(Load(0.0, x));
+    std::vector<std::vector<int64_t>> xi((size_t)X);
+    for (int64_t i : items) {
+        Load l = heap.top();
+        heap.pop();
+        xi[(size_t)l.second].push_back(i);
+        heap.push(Load(l.first + icost[(size_t)i], l.second));
     }
-    // each XCD's tasks -> its blocks
-    std::vector<std::vector<int>> per((size_t)n_blocks);
+    // per XCD: blocks as lists of units
+    std::vector<std::vector<std::vector<coot_batch_unit_d>>> xb((size_t)X);
+    size_t longest = 0;
     for (int64_t x = 0; x < X; ++x) {
-        std::vector<int> idx;
-        for (int64_t i = 0; i < n; ++i)
-            if (xcd_of[(size_t)tasks[(size_t)i].item] == x) idx.push_back((int)i);
-        std::stable_sort(idx.begin(), idx.end(), [&](int a, int b) { return cost(a) > cost(b); });
-        std::priority_queue<Load, std::vector<Load>, std::greater<Load>> heap;
-        for (int64_t b = x; b < n_blocks; b += X) heap.push(Load(0.0, b));
-        for (int i : idx) {
-            Load l = heap.top();
-            heap.pop();
-            per[(size_t)l.second].push_back(i);
-            heap.push(Load(l.first + cost(i), l.second));
+        auto& bl = xb[(size_t)x];
+        std::vector<coot_batch_unit_d> pack;
+        for (int64_t i : xi[(size_t)x]) {
+            if (small[(size_t)i]) continue;
+            for (const auto& u : per_item[(size_t)i]) bl.push_back({u});
         }
+        for (int64_t i : xi[(size_t)x]) {
+            if (!small[(size_t)i]) continue;
+            pack.push_back(per_item[(size_t)i][0]);
+            if (pack.size() == 4) {
+                bl.push_back(pack);
+                pack.clear();
+            }
+        }
+        if (!pack.empty()) bl.push_back(pack);
+        longest = std::max(longest, bl.size());
     }
-    order->clear();
-    first->assign((size_t)n_blocks + 1, 0);
-    for (int64_t b = 0; b < n_blocks; ++b) {
-        (*first)[(size_t)b] = (int)order->size();
-        order->insert(order->end(), per[(size_t)b].begin(), per[(size_t)b].end());
-    }
-    (*first)[(size_t)n_blocks] = (int)order->size();
+    units->clear();
+    first->clear();
+    for (size_t j = 0; j < longest; ++j)
+        for (int64_t x = 0; x < X; ++x) {
+            first->push_back((int)units->size());
+            if (j < xb[(size_t)x].size())
+                units->insert(units->end(), xb[(size_t)x][j].begin(), xb[(size_t)x][j].end());
+        }
+    first->push_back((int)units->size());
+    if (first->size() < 2) first->push_back((int)units->size());  // no units: one empty block
 }
 
 // trans parity of every leaf slot (bit 0: read straight, bit 1: read transposed)
@@ -254,11 +295,123 @@ BatchTrees plan_batch(const coot_batch* b)
     return T;
 }
 
+
+// Every tile of every item may run at the same time as any other, so an
+// output that overlaps memory the launch reads or writes elsewhere races.
+// The one overlap allowed is the single-matrix in-place rule: item i's output
+// is exactly its own operand slot s (same first byte, same size, same element
+// type) and slot s is only read straight, so each element is read before it
+// is written, by the same lane.  Anything else (another item's operand, a
+// slot read through trans(), two outputs, the reduction results) fails.
+void check_batch_aliasing(const coot_batch* b, const BatchTrees& T)
+{
+    struct Ext {
+        uintptr_t lo, hi;
+        int item, slot;  // slot -1: an output or the reduction results
+    };
+    std::vector<Ext> reads, writes;
+    for (int i = 0; i < b->n_items; ++i) {
+        const int64_t r = b->shapes[2 * i], c = b->shapes[2 * i + 1];
+        if (r * c == 0) continue;
+        for (int s = 0; s < b->n_slots; ++s) {
+            const uintptr_t p = (uintptr_t)b->leaf_ptrs[(size_t)i * b->n_slots + s];
+            if (p && T.par[(size_t)s]) reads.push_back(Ext{p, p + (uintptr_t)(r * c * itemsize(b->slot_dtypes[s])), i, s});
+        }
+        if (T.has_out && b->out_ptrs[i]) {
+            const uintptr_t p = (uintptr_t)b->out_ptrs[i];
+            writes.push_back(Ext{p, p + (uintptr_t)(r * c * itemsize(b->out_dtype)), i, -1});
+        }
+    }
+    if (T.has_red && b->red_out && b->n_items > 0) {
+        const uintptr_t p = (uintptr_t)b->red_out;
+        writes.push_back(Ext{p, p + (uintptr_t)b->n_items * (uintptr_t)itemsize(b->red_dtype), -1, -1});
+    }
+    auto by_lo = [](const Ext& a, const Ext& c) { return a.lo < c.lo || (a.lo == c.lo && a.hi < c.hi); };
+    std::sort(writes.begin(), writes.end(), by_lo);
+    for (size_t k = 1; k < writes.size(); ++k)
+        if (writes[k].lo < writes[k - 1].hi) fail(COOT_ERR_ALIAS, "batch: two outputs overlap");
+    std::sort(reads.begin(), reads.end(), by_lo);
+    uintptr_t longest = 0;
+    for (const Ext& e : reads) longest = std::max(longest, e.hi - e.lo);
+    for (const Ext& w : writes) {
+        // reads that can overlap w start in (w.lo - longest, w.hi)
+        const uintptr_t from = w.lo > longest ? w.lo - longest : 0;
+        auto it = std::lower_bound(reads.begin(), reads.end(), Ext{from, 0, 0, 0}, by_lo);
+        for (; it != reads.end() && it->lo < w.hi; ++it) {
+            if (it->hi <= w.lo) continue;
+            const bool in_place = w.item >= 0 && it->item == w.item && it->lo == w.lo && it->hi == w.hi &&
+                                  T.par[(size_t)it->slot] == 1 && b->slot_dtypes[it->slot] == b->out_dtype;
+            if (!in_place)
+                fail(COOT_ERR_ALIAS, "batch: item " + std::to_string(w.item >= 0 ? w.item : it->item) +
+                                         ": an output overlaps an operand (only an item's own slot read straight, "
+                                         "with the same extent and element type, may be its output)");
+        }
+    }
+}
+
+// ---- one-call batched evaluation: plans cached by descriptor contents ----
+// The descriptor is walked field by field (trees, dtypes, every pointer and
+// shape, flags); a Sink either appends the bytes to a key or compares them
+// with a stored key, so a lookup copies nothing.
+template <class Sink>
+void walk_batch(const coot_batch* b, Sink& k)
+{
+    auto expr = [&](const coot_expr* e) {
+        const int32_t nn = e ? e->n_nodes : -1;
+        k.put(&nn, sizeof nn);
+        if (!e || nn <= 0 || !e->nodes) return;
+        k.put(&e->flags, sizeof e->flags);
+        k.put(&e->cfg, sizeof e->cfg);
+        k.put(e->nodes, sizeof(coot_node) * (size_t)nn);
+    };
+    expr(b->expr);
+    expr(b->red_expr);
+    const int32_t head[6] = {b->n_slots, b->n_items, b->out_dtype, b->red_op, b->red_dtype, (int32_t)b->flags};
+    k.put(head, sizeof head);
+    if (b->n_slots <= 0 || b->n_items < 0) return;
+    if (b->slot_dtypes) k.put(b->slot_dtypes, sizeof(int32_t) * (size_t)b->n_slots);
+    const size_t n = (size_t)b->n_items;
+    if (b->shapes) k.put(b->shapes, sizeof(int64_t) * 2 * n);
+    if (b->leaf_ptrs) k.put(b->leaf_ptrs, sizeof(void*) * n * (size_t)b->n_slots);
+    const int32_t has_out = b->out_ptrs != nullptr;
+    k.put(&has_out, sizeof has_out);
+    if (has_out) k.put(b->out_ptrs, sizeof(void*) * n);
+    k.put(&b->red_out, sizeof b->red_out);
+}
+
+struct KeyWriter {
+    std::string key;
+    void put(const void* p, size_t n) { key.append((const char*)p, n); }
+};
+
+struct KeyMatcher {
+    const std::string& key;
+    size_t at = 0;
+    bool same = true;
+    void put(const void* p, size_t n)
+    {
+        if (!same) return;
+        same = at + n <= key.size() && std::memcmp(key.data() + at, p, n) == 0;
+        at += n;
+    }
+};
+
+struct CachedPlan {
+    std::string key;
+    coot_batch_plan* plan;
+};
+constexpr size_t EVAL_CACHE_MAX = 16;
+std::mutex g_eval_mu;
+std::vector<CachedPlan> g_eval_cache;  // most recently used first
 }  // namespace
 
 namespace coot {
 void batch_destroy_all()
 {
+    {
+        std::lock_guard<std::mutex> lk(g_eval_mu);
+        g_eval_cache.clear();
+    }
     std::lock_guard<std::mutex> lk(g_plans_mu);
     for (auto* p : g_plans) free_plan(p);
     g_plans.clear();
@@ -273,6 +426,7 @@ int coot_batch_create(const coot_batch* b, void* stream, coot_batch_plan** out_p
         if (!b || !out_plan) fail(COOT_ERR_ARG, "NULL batch or plan pointer");
         *out_plan = nullptr;
         BatchTrees T = plan_batch(b);
+        check_batch_aliasing(b, T);
         ensure_init();
         const bool has_out = T.has_out, has_red = T.has_red;
         const std::vector<int>& par = T.par;
@@ -298,23 +452,22 @@ int coot_batch_create(const coot_batch* b, void* stream, coot_batch_plan** out_p
             P->n_items = b->n_items;
             P->slot_par = par;
             P->h_items.resize((size_t)b->n_items);
-            std::vector<coot_batch_task_d> tasks;
+            // units of every item (their partial slots in item order) and the block schedule
+            const int64_t E = batch_unit_elems(py);
+            std::vector<std::vector<coot_batch_unit_d>> per_item((size_t)b->n_items);
+            std::vector<bool> small((size_t)b->n_items, false);
+            int64_t n_units = 0;
             for (int i = 0; i < b->n_items; ++i) {
                 coot_batch_item_d& d = P->h_items[(size_t)i];
                 std::memset(&d, 0, sizeof d);
                 d.rows = b->shapes[2 * i];
                 d.cols = b->shapes[2 * i + 1];
-                coot_batch_tile_shape(d.rows, d.cols, &d.lr, &d.lc);
-                d.ntiles = d.rows > 0 && d.cols > 0
-                               ? ((d.rows + (1 << d.lr) - 1) >> d.lr) * ((d.cols + (1 << d.lc) - 1) >> d.lc)
-                               : 0;
-                if (d.ntiles > INT32_MAX) fail(COOT_ERR_SHAPE, "batch: item too large (more than 2^31 tiles)");
-                d.part0 = (int64_t)tasks.size();
-                for (int64_t t0 = 0; t0 < d.ntiles; t0 += COOT_BATCH_CHUNK) {
-                    if (tasks.size() >= (size_t)INT32_MAX) fail(COOT_ERR_SHAPE, "batch: more than 2^31 tasks");
-                    tasks.push_back(coot_batch_task_d{i, (int)t0, (int)std::min<int64_t>(d.ntiles, t0 + COOT_BATCH_CHUNK),
-                                                      (int)tasks.size()});
-                }
+                small[(size_t)i] = item_units(i, d.rows, d.cols, E, &per_item[(size_t)i]);
+                d.nunits = (int64_t)per_item[(size_t)i].size();
+                d.part0 = n_units;
+                for (int64_t j = 0; j < d.nunits; ++j) per_item[(size_t)i][(size_t)j].part = (int)(n_units + j);
+                n_units += d.nunits;
+                if (n_units >= (int64_t)INT32_MAX) fail(COOT_ERR_SHAPE, "batch: more than 2^31 units");
                 for (int s2 = 0; s2 < b->n_slots; ++s2) {
                     d.leaf[s2] = b->leaf_ptrs[(size_t)i * b->n_slots + s2];
                     if (!d.leaf[s2] && d.rows * d.cols > 0) fail(COOT_ERR_ARG, "batch: NULL operand pointer");
@@ -324,26 +477,22 @@ int coot_batch_create(const coot_batch* b, void* stream, coot_batch_plan** out_p
                     if (!d.out && d.rows * d.cols > 0) fail(COOT_ERR_ARG, "batch: NULL output pointer");
                 }
             }
-            // 4 blocks of 256 threads per CU per unit of the tree's split setting
-            // (default 8: short per-block task lists, about two tasks per block
-            // here, let the hardware's block dispatch balance the load; measured
-            // 549 / 530 / 500 us for split 2 / 4 / 8 on 10,000 matrices)
-            const int split = b->expr->cfg.split > 0 ? b->expr->cfg.split : 8;
-            P->n_blocks = std::max<int64_t>(1, std::min<int64_t>((int64_t)tasks.size(), (int64_t)g_state.cus * 4 * split));
-            std::vector<int> order, first;
-            lpt_schedule(tasks, P->n_items, P->n_blocks, g_state.xcds, &order, &first);
+            std::vector<coot_batch_unit_d> units;
+            std::vector<int> first;
+            schedule_units(per_item, small, g_state.xcds, &units, &first);
+            P->n_blocks = std::max<int64_t>(1, (int64_t)first.size() - 1);
+            if (P->n_blocks > 0x7fffffff) fail(COOT_ERR_SHAPE, "batch: too many blocks");
             auto up = [](void** dst, const void* src, size_t bytes) {
                 hipchk(hipMalloc(dst, std::max<size_t>(bytes, 16)), "hipMalloc(batch table)");
                 if (bytes) hipchk(hipMemcpy(*dst, src, bytes, hipMemcpyHostToDevice), "hipMemcpy(batch table)");
             };
             up((void**)&P->d_items, P->h_items.data(), P->h_items.size() * sizeof(coot_batch_item_d));
-            up((void**)&P->d_tasks, tasks.data(), tasks.size() * sizeof(coot_batch_task_d));
-            up((void**)&P->d_order, order.data(), order.size() * sizeof(int));
+            up((void**)&P->d_units, units.data(), units.size() * sizeof(coot_batch_unit_d));
             up((void**)&P->d_blk_first, first.data(), first.size() * sizeof(int));
             if (has_red) {
                 (void)hipFree(P->d_part);
                 P->d_part = nullptr;
-                hipchk(hipMalloc((void**)&P->d_part, std::max<size_t>(16, tasks.size() * 2 * sizeof(double))),
+                hipchk(hipMalloc((void**)&P->d_part, std::max<size_t>(16, (size_t)n_units * 2 * sizeof(double))),
                        "hipMalloc(batch partials)");
             }
             // kernels
@@ -351,7 +500,7 @@ int coot_batch_create(const coot_batch* b, void* stream, coot_batch_plan** out_p
             std::string src = batch_kernel_source(py, has_red ? &pr : nullptr, has_out, b->out_dtype, b->red_dtype,
                                                   read_slot, &name);
             P->k = get_kernel(name, src, has_red);
-            P->args = coot_bargs{P->d_items, P->d_tasks, P->d_order, P->d_blk_first, P->n_items, P->d_part, b->red_out};
+            P->args = coot_bargs{P->d_items, P->d_units, P->d_blk_first, P->n_items, P->d_part, b->red_out};
             // one launch captured in a graph
             if (!(b->flags & (COOT_BATCH_NO_GRAPH | COOT_BATCH_PER_ITEM | COOT_BATCH_UNFUSED)) && P->n_items > 0) {
                 hipStream_t cap;
@@ -447,6 +596,49 @@ int coot_batch_run(coot_batch_plan* P, void* stream)
             g_state.launches += P->has_red ? 2 : 1;
         }
         return COOT_OK;
+    });
+}
+
+int coot_eval_batched(const coot_batch* b, void* stream)
+{
+    return guard3([&] {
+        if (!b) fail(COOT_ERR_ARG, "NULL batch");
+        coot_batch_plan* P = nullptr;
+        {
+            std::lock_guard<std::mutex> lk(g_eval_mu);
+            for (size_t i = 0; i < g_eval_cache.size(); ++i) {
+                KeyMatcher m{g_eval_cache[i].key};
+                walk_batch(b, m);
+                if (m.same && m.at == g_eval_cache[i].key.size()) {
+                    P = g_eval_cache[i].plan;
+                    std::rotate(g_eval_cache.begin(), g_eval_cache.begin() + (ptrdiff_t)i,
+                                g_eval_cache.begin() + (ptrdiff_t)i + 1);
+                    break;
+                }
+            }
+        }
+        if (!P) {
+            int rc = coot_batch_create(b, stream, &P);
+            if (rc) return rc;
+            KeyWriter w;
+            walk_batch(b, w);
+            coot_batch_plan* evict = nullptr;
+            {
+                std::lock_guard<std::mutex> lk(g_eval_mu);
+                g_eval_cache.insert(g_eval_cache.begin(), CachedPlan{std::move(w.key), P});
+                if (g_eval_cache.size() > EVAL_CACHE_MAX) {
+                    evict = g_eval_cache.back().plan;
+                    g_eval_cache.pop_back();
+                }
+            }
+            if (evict) {
+                // its graph may still be running on some stream
+                hipchk(hipDeviceSynchronize(), "hipDeviceSynchronize");
+                int rc2 = coot_batch_destroy(evict);
+                if (rc2) return rc2;
+            }
+        }
+        return coot_batch_run(P, stream);
     });
 }
 

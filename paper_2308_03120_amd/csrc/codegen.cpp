@@ -1176,126 +1176,56 @@ static std::string emit_row(const Plan& p, const std::string& name)
     return s.str();
 }
 
-// --- batched kernels: one persistent tile pass over many items -----------------
-// Every block runs a list of tasks (at most four consecutive tiles of one item;
-// a longest-first schedule computed on the host, so the blocks finish
-// together).  Per tile the block evaluates the tree (reads transposed through
-// LDS), stores Y and folds the reduction tree of Y into compensated
-// accumulators; one block reduction per task gives a partial of r_i, and the
-// _comb kernel adds an item's partials in task order.  Tasks depend only on
-// item shapes, so r_i does not depend on the grid or on timing.
+// --- batched kernels: one pass over the units of many items ----------------
+// An item's value Y_i (R x Cn, column-major) is cut into units: blocks of
+// whole columns (rc = R rows, k columns) where the columns are short, or
+// 64-column blocks of E/64 rows where they are long; an item of at most E/4
+// elements is one unit of its own.  A unit's operands read through trans()
+// are staged in LDS: read along their own columns (k consecutive elements of
+// each of the unit's rc columns), stored with an odd row stride kp, and read
+// back transposed without bank conflicts.  Everything else moves in the
+// value's column-major order, so the output and the straight operands stream
+// contiguous runs (whole units when rc = R).  A block runs one large unit
+// with all its threads, or up to four small units, one per wave (each wave
+// with a quarter of the LDS stage).  Each unit leaves a compensated partial of
+// the item's reduction; the _comb kernel adds an item's partials in unit
+// order, so r_i depends only on the item's shape and values.
+int64_t batch_unit_elems(const Plan& py)
+{
+    int bytes = 0;
+    for (const Read& r : py.reads)
+        if (r.trans) bytes += itemsize(r.dtype);
+    int64_t e = 16384;
+    while (bytes > 0 && e * bytes > COOT_BATCH_LDS_BYTES) e >>= 1;
+    return e;
+}
+
 std::string batch_kernel_source(const Plan& py, const Plan* pr, bool has_out, int out_dtype, int red_dtype,
                                 const std::vector<int>& read_slot, std::string* name_out)
 {
-    // Loads and stores go through the caches: an item's column segments are
-    // rarely aligned to cache lines, and a line shared by two tiles is then
-    // served from L2 the second time (streaming hints cost ~15% here).
-    const std::string LDF = "ldpl", STF = "stpl";
-    std::ostringstream s;
+    const int64_t E = batch_unit_elems(py);
+    const int64_t CAP = coot_batch_stage_cap(E);  // LDS elements per staged read (block mode)
     const int rp = py.nodes[py.root].prec;
+    const std::string ACC = pr ? (pr->nodes[pr->root].prec == 64 ? "AccKD" : (pr->pairwise ? "AccPF" : "AccKF")) : "";
+    const std::string OS = stype(out_dtype);
+    const size_t nr = py.reads.size();
+    constexpr int U = 8;  // elements per thread in flight
+    std::ostringstream s;
     s << "// batch tree: " << py.body_sig << "\n";
     s << emit_eval(py, false, "x");
     if (pr) {
         s << "// reduction tree over Y: " << pr->body_sig << "\n";
         s << emit_eval(*pr, pr->product_form, "r");
     }
-    const TilePlan tp = tile_plan(py);
-    const std::string ACC = pr ? (pr->nodes[pr->root].prec == 64 ? "AccKD" : (pr->pairwise ? "AccPF" : "AccKF")) : "";
-    const std::string OS = stype(out_dtype);
-    const size_t nr = py.reads.size();
     auto S = [&](size_t j) { return std::string(stype(py.reads[j].dtype)); };
-    // Each block runs its tasks' tiles as one sequence; the tile after the
-    // current one (possibly the next task's first) is prefetched while the
-    // current one is computed.  Three views: c (the task being computed), q
-    // (the item of the prefetched tile) and d (the next task, its descriptor
-    // loaded one task ahead).
-    auto load_d = [&](const std::string& in, bool decl) {
-        std::ostringstream o;
-        const std::string T = decl ? "i64 " : "";
-        o << in << (decl ? "coot_batch_task_d " : "") << "dt = b.tasks[dk];\n";
-        o << in << (decl ? "i64 " : "") << "dR = b.items[dt.item].rows;\n";
-        o << in << (decl ? "i64 " : "") << "dCn = b.items[dt.item].cols;\n";
-        o << in << (decl ? "int " : "") << "dlr = b.items[dt.item].lr;\n";
-        o << in << (decl ? "int " : "") << "dlc = b.items[dt.item].lc;\n";
-        for (size_t j = 0; j < nr; ++j)
-            o << in << (decl ? "const " + S(j) + "* " : std::string()) << "dL" << j << " = (const " << S(j)
-              << "*)b.items[dt.item].leaf[" << read_slot[j] << "];\n";
-        if (has_out) o << in << (decl ? OS + "* " : std::string()) << "dO = (" << OS << "*)b.items[dt.item].out;\n";
-        (void)T;
-        return o.str();
-    };
-    s << "extern \"C\" __global__ void __launch_bounds__(256) COOT_KERNEL_NAME(const coot_bargs b)\n{\n";
-    s << tile_shared_decls(py, tp, "    ");
-    if (pr) s << "    __shared__ " << ACC << " lds_acc[4];\n";
-    s << "    const int lane = threadIdx.x & 63, w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);\n";
-    s << "    int si = b.blk_first[blockIdx.x];\n";
-    s << "    const int s_end = b.blk_first[blockIdx.x + 1];\n";
-    s << "    if (si >= s_end) return;\n";
-    s << "    int dk = b.order[si];\n";
-    s << load_d("    ", true);
-    s << "    i64 cR = dR, cCn = dCn;\n";
-    s << "    int clr = dlr, clc = dlc;\n";
-    if (has_out) s << "    " << OS << "* cO = dO;\n";
-    s << "    int ctr = (int)((cR + (1 << clr) - 1) >> clr), crem = dt.t1 - dt.t0, cpart = dt.part;\n";
-    s << "    int ti = dt.t0 % ctr, tj = dt.t0 / ctr;\n";
-    s << "    i64 qR = dR, qCn = dCn;\n";
-    s << "    int qlr = dlr, qlc = dlc;\n";
-    for (size_t j = 0; j < nr; ++j) s << "    const " << S(j) << "* qL" << j << " = dL" << j << ";\n";
-    s << "    dk = si + 1 < s_end ? b.order[si + 1] : dk;\n";
-    s << load_d("    ", false);
-    s << tile_regs(py, tp, "    ");
-    if (pr) s << "    " << ACC << " acc;\n    acc.init();\n";
-    // a straight read has the item's shape (ld = rows); a transposed one is cols x rows (ld = cols)
-    TileView v{"qR", "qCn", "qlr", "qlc", [](size_t j) { return "qL" + std::to_string(j); },
-               [&](size_t j) { return std::string(py.reads[j].trans ? "qCn" : "qR"); }};
-    // one specialised tile body per tile class (coot_batch_tile_shape)
-    static const int classes[7][2] = {{6, 6}, {3, 9}, {4, 8}, {5, 7}, {8, 3}, {7, 4}, {6, 5}};
-    auto by_class = [&](const std::string& in, const std::string& lrv, const std::string& lcv,
-                        const std::function<std::string(const std::string&, int, int)>& body) {
-        std::ostringstream o;
-        o << in << "switch (" << lrv << " * 16 + " << lcv << ") {\n";
-        for (const auto& c : classes) {
-            o << in << "case " << c[0] * 16 + c[1] << ": {\n" << body(in + "    ", c[0], c[1]);
-            o << in << "    break;\n" << in << "}\n";
-        }
-        o << in << "default:\n" << in << "    break;\n" << in << "}\n";
-        return o.str();
-    };
-    auto prefetch = [&](const std::string& in, const std::string& a1, const std::string& a2) {
-        return by_class(in, "qlr", "qlc", [&](const std::string& i2, int lr, int lc) {
-            if (lr == 6 && lc == 6) return tile_prefetch_sq(py, tp, i2, a1, a2, v, LDF);
-            TileView w = v;
-            w.lr = std::to_string(lr);
-            w.lc = std::to_string(lc);
-            return tile_prefetch_gen(py, tp, i2, a1, a2, w, LDF, true);
-        });
-    };
-    s << prefetch("    ", "ti", "tj");
-    s << "    for (;;) {\n";
-    s << "        int ni = ti + 1, nj = tj, nsi = si;\n";
-    s << "        if (ni >= ctr) { ni = 0; ++nj; }\n";
-    s << "        if (crem <= 1) {\n";
-    s << "            ++nsi;\n";
-    s << "            const int dtr = (int)((dR + (1 << dlr) - 1) >> dlr);\n";
-    s << "            ni = dt.t0 % dtr;\n            nj = dt.t0 / dtr;\n";
-    s << "        }\n";
-    s << "        const bool more = nsi < s_end;\n";
-    s << "        if (more && nsi != si) {\n";
-    s << "            qR = dR;\n            qCn = dCn;\n            qlr = dlr;\n            qlc = dlc;\n";
-    for (size_t j = 0; j < nr; ++j) s << "            qL" << j << " = dL" << j << ";\n";
-    s << "        }\n";
-    s << by_class("        ", "clr", "clc", [&](const std::string& i2, int lr, int lc) {
-        if (lr == 6 && lc == 6) return tile_stage_sq(py, tp, i2);
-        return tile_stage_gen(py, tp, i2, "cR", "cCn", "ti", "tj", std::to_string(lr), std::to_string(lc));
-    });
-    s << "        if (more) {\n" << prefetch("            ", "ni", "nj") << "        }\n";
-    auto elem = [&](const std::string& args, const std::string& in, const std::string& addr) {
+    // the value y of one element of Y_i: store it, fold it into the reduction
+    auto elem = [&](const std::string& in, const std::string& args, const std::string& yaddr) {
         std::ostringstream o;
         o << in << "const " << ctype(rp) << " y = x_eval(" << args << ");\n";
         std::string yv = "y";
         if (has_out) {
             o << in << "const " << OS << " yo = " << narrow(out_dtype, rp, "y") << ";\n";
-            o << in << STF << "(" << addr << ", yo);\n";
+            o << in << "O[" << yaddr << "] = yo;\n";
             if (out_dtype == COOT_F16) yv = "widen_f16(yo)";
             else if (out_dtype == COOT_BF16) yv = "widen_bf16(yo)";
             else yv = "yo";
@@ -1313,39 +1243,128 @@ std::string batch_kernel_source(const Plan& py, const Plan* pr, bool has_out, in
         }
         return o.str();
     };
-    s << by_class("        ", "clr", "clc", [&](const std::string& i2, int lr, int lc) {
-        if (lr == 6 && lc == 6)
-            return tile_compute_sq(py, tp, i2, "ti", "tj", "cR", "cCn", has_out ? "cO" : "", OS, "cR", elem);
-        return tile_compute_gen(py, tp, i2, "ti", "tj", "cR", "cCn", std::to_string(lr), std::to_string(lc),
-                                has_out ? "cO" : "", OS, "cR", true, elem);
-    });
-    s << "        if (nsi != si) {\n";
+    // One unit, run by nt threads (thread t), LDS stage at element offset sb.
+    // Stage: element (pp, qq) of the unit (qq fast) of each transposed read
+    // comes from T[(q0 + qq) + (p0 + pp) * Cn] and goes to lds[sb + qq + pp * kp].
+    // Compute: element (pp, qq) (pp fast) of Y_i at (p0 + pp) + (q0 + qq) * R.
+    // Both walks advance by nt elements per step with adds only.
+    auto unit_body = [&](const std::string& in, const std::string& nt, const std::string& t, const std::string& sb,
+                         bool block) {
+        std::ostringstream o;
+        o << in << "const coot_batch_unit_d u = b.units[ui];\n";
+        o << in << "const coot_batch_item_d& it = b.items[u.item];\n";
+        o << in << "const i64 R = it.rows, Cn = it.cols;\n";
+        o << in << "const int rc = u.rc, k = u.k, kp = k | 1, n = rc * k;\n";
+        for (size_t j = 0; j < nr; ++j)
+            o << in << "const " << S(j) << "* L" << j << " = (const " << S(j) << "*)it.leaf[" << read_slot[j] << "];\n";
+        // no __restrict__: an item's output may be its own straight operand (in place)
+        if (has_out) o << in << OS << "* O = (" << OS << "*)it.out;\n";
+        bool any_t = false;
+        for (size_t j = 0; j < nr; ++j) any_t = any_t || py.reads[j].trans;
+        if (any_t) {
+            // stage: walk (pp, qq), qq fast
+            o << in << "{\n";
+            o << in << "    const int dq = " << nt << " % k, dp = " << nt << " / k;\n";
+            o << in << "    int qq = " << t << " % k, pp = " << t << " / k;\n";
+            o << in << "    i64 g = (i64)(u.q0 + qq) + (i64)(u.p0 + pp) * Cn;\n";
+            o << in << "    int l = " << sb << " + qq + pp * kp;\n";
+            o << in << "    const i64 dg = (i64)dq + (i64)dp * Cn;\n";
+            o << in << "    const int dl = dq + dp * kp;\n";
+            o << in << "    for (int e0 = " << t << "; e0 < n; e0 += " << U << " * " << nt << ") {\n";
+            for (size_t j = 0; j < nr; ++j)
+                if (py.reads[j].trans) o << in << "        " << S(j) << " v" << j << "[" << U << "];\n";
+            o << in << "        int ls[" << U << "];\n";
+            o << in << "#pragma unroll\n" << in << "        for (int e = 0; e < " << U << "; ++e) {\n";
+            o << in << "            ls[e] = l;\n";
+            o << in << "            if (e0 + e * " << nt << " < n) {\n";
+            for (size_t j = 0; j < nr; ++j)
+                if (py.reads[j].trans) o << in << "                v" << j << "[e] = ldpl(L" << j << " + g);\n";
+            o << in << "            }\n";
+            o << in << "            qq += dq; pp += dp; g += dg; l += dl;\n";
+            o << in << "            if (qq >= k) { qq -= k; ++pp; g += Cn - k; l += kp - k; }\n";
+            o << in << "        }\n";
+            o << in << "#pragma unroll\n" << in << "        for (int e = 0; e < " << U << "; ++e)\n";
+            o << in << "            if (e0 + e * " << nt << " < n) {\n";
+            for (size_t j = 0; j < nr; ++j)
+                if (py.reads[j].trans) o << in << "                st" << j << "[ls[e]] = v" << j << "[e];\n";
+            o << in << "            }\n";
+            o << in << "    }\n" << in << "}\n";
+            if (block) {
+                o << in << "__syncthreads();\n";
+            } else {
+                o << in << "__builtin_amdgcn_fence(__ATOMIC_RELEASE, \"wavefront\");\n";
+                o << in << "__builtin_amdgcn_wave_barrier();\n";
+                o << in << "__builtin_amdgcn_fence(__ATOMIC_ACQUIRE, \"wavefront\");\n";
+            }
+        }
+        // compute: walk (pp, qq), pp fast
+        o << in << "{\n";
+        o << in << "    const int dp = " << nt << " % rc, dq = " << nt << " / rc;\n";
+        o << in << "    int pp = " << t << " % rc, qq = " << t << " / rc;\n";
+        o << in << "    i64 ya = (i64)(u.p0 + pp) + (i64)(u.q0 + qq) * R;\n";
+        o << in << "    int l = " << sb << " + qq + pp * kp;\n";
+        o << in << "    const i64 dya = (i64)dp + (i64)dq * R;\n";
+        o << in << "    const int dl = dq + dp * kp;\n";
+        o << in << "    for (int e0 = " << t << "; e0 < n; e0 += " << U << " * " << nt << ") {\n";
+        for (size_t j = 0; j < nr; ++j)
+            o << in << "        " << ctype(dtype_prec(py.reads[j].dtype)) << " v" << j << "[" << U << "];\n";
+        o << in << "        i64 ys[" << U << "];\n";
+        o << in << "#pragma unroll\n" << in << "        for (int e = 0; e < " << U << "; ++e) {\n";
+        o << in << "            ys[e] = ya;\n";
+        o << in << "            if (e0 + e * " << nt << " < n) {\n";
+        for (size_t j = 0; j < nr; ++j) {
+            if (py.reads[j].trans)
+                o << in << "                v" << j << "[e] = " << widen(py.reads[j].dtype, "st" + std::to_string(j) + "[l]") << ";\n";
+            else
+                o << in << "                v" << j << "[e] = " << widen(py.reads[j].dtype, "ldpl(L" + std::to_string(j) + " + ya)") << ";\n";
+        }
+        o << in << "            }\n";
+        o << in << "            pp += dp; qq += dq; ya += dya; l += dl;\n";
+        o << in << "            if (pp >= rc) { pp -= rc; ++qq; ya += R - rc; l += 1 - rc * kp; }\n";
+        o << in << "        }\n";
+        o << in << "#pragma unroll\n" << in << "        for (int e = 0; e < " << U << "; ++e)\n";
+        o << in << "            if (e0 + e * " << nt << " < n) {\n";
+        std::string args;
+        for (size_t j = 0; j < nr; ++j) args += (j ? ", v" : "v") + std::to_string(j) + "[e]";
+        o << elem(in + "                ", args, "ys[e]");
+        o << in << "            }\n";
+        o << in << "    }\n" << in << "}\n";
+        return o.str();
+    };
+    s << "extern \"C\" __global__ void __launch_bounds__(256) COOT_KERNEL_NAME(const coot_bargs b)\n{\n";
+    for (size_t j = 0; j < nr; ++j)
+        if (py.reads[j].trans) s << "    __shared__ " << S(j) << " st" << j << "[" << CAP << "];\n";
+    if (pr) s << "    __shared__ " << ACC << " lds_acc[4];\n";
+    s << "    const int first = b.blk_first[blockIdx.x], last = b.blk_first[blockIdx.x + 1];\n";
+    s << "    if (last - first == 1) {\n";
+    s << "        // one unit, all 256 threads\n";
+    s << "        const int ui = first;\n";
+    if (pr) s << "        " << ACC << " acc;\n        acc.init();\n";
+    s << unit_body("        ", "256", "(int)threadIdx.x", "0", true);
     if (pr) {
-        s << "            acc = block_reduce(acc, lds_acc);\n";
-        s << "            if (threadIdx.x == 0) {\n";
-        s << "                b.part[2 * (i64)cpart] = acc.hi();\n";
-        s << "                b.part[2 * (i64)cpart + 1] = acc.lo();\n";
-        s << "            }\n";
-        s << "            acc.init();\n";
+        s << "        acc = block_reduce(acc, lds_acc);\n";
+        s << "        if (threadIdx.x == 0) put_sum_partial(b.part, u.part, acc.hi(), acc.lo());\n";
     }
-    s << "            if (!more) break;\n";
-    s << "            cR = dR;\n            cCn = dCn;\n";
-    if (has_out) s << "            cO = dO;\n";
-    s << "            clr = dlr;\n            clc = dlc;\n";
-    s << "            ctr = (int)((cR + (1 << clr) - 1) >> clr);\n            crem = dt.t1 - dt.t0;\n            cpart = dt.part;\n";
-    s << "            dk = nsi + 1 < s_end ? b.order[nsi + 1] : dk;\n";
-    s << load_d("            ", false);
-    s << "        } else {\n            --crem;\n        }\n";
-    s << "        si = nsi;\n        ti = ni;\n        tj = nj;\n";
+    s << "    } else {\n";
+    s << "        // up to four small units, one per wave, each with a quarter of the stage\n";
+    s << "        const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;\n";
+    s << "        const int ui = first + w;\n";
+    s << "        if (ui < last) {\n";
+    if (pr) s << "            " << ACC << " acc;\n            acc.init();\n";
+    s << unit_body("            ", "64", "lane", "w * " + std::to_string(CAP / 4), false);
+    if (pr) {
+        s << "            wave_reduce(acc);\n";
+        s << "            if (lane == 0) put_sum_partial(b.part, u.part, acc.hi(), acc.lo());\n";
+    }
+    s << "        }\n";
     s << "    }\n}\n";
     if (pr) {
-        // per item: FP64 compensated sum of its tasks' partials in task order,
+        // per item: FP64 compensated sum of its units' partials in unit order,
         // then the final transform
         s << "extern \"C\" __global__ void __launch_bounds__(256) COOT_KERNEL_NAME_comb(const coot_bargs b)\n{\n";
         s << "    const i64 i = (i64)blockIdx.x * 256 + threadIdx.x;\n";
         s << "    if (i >= b.n_items) return;\n";
-        s << "    const i64 nt = b.items[i].ntiles, p0 = b.items[i].part0;\n";
-        s << "    const i64 np = (nt + COOT_BATCH_CHUNK - 1) / COOT_BATCH_CHUNK;\n";
+        s << "    const i64 np = b.items[i].nunits, p0 = b.items[i].part0;\n";
         s << "    AccKD a;\n    a.init();\n";
         s << "    for (i64 k = 0; k < np; ++k) {\n";
         s << "        a.add(b.part[2 * (p0 + k)]);\n        a.add(b.part[2 * (p0 + k) + 1]);\n    }\n";

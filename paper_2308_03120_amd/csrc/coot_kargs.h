@@ -50,26 +50,6 @@ COOT_HD int coot_tile_stride(int lr, int lc)
 }
 #define COOT_TILE_LDS 4160
 
-/* Tile shape of a batched item: one of seven classes, so that the batched
- * kernel can hold a specialised body for each.  64 x 64 when both sides reach
- * 64; otherwise the narrow side (rounded up to a power of two, at least 8)
- * spans the tile and the long side fills the rest: 8/16/32 x 512/256/128 or
- * 256/128/64 x 8/16/32. */
-COOT_HD void coot_batch_tile_shape(long long R, long long Cn, int* lr, int* lc)
-{
-    const int r0 = coot_lg2ceil(R), c0 = coot_lg2ceil(Cn);
-    if (r0 >= 6 && c0 >= 6) {
-        *lr = 6;
-        *lc = 6;
-    } else if (r0 <= c0) {
-        *lr = r0 < 3 ? 3 : r0;
-        *lc = 12 - *lr;
-    } else {
-        *lc = c0 < 3 ? 3 : c0;
-        *lr = 11 - *lc;
-    }
-}
-
 typedef struct coot_kargs {
     const void* leaf[COOT_MAX_READS];  /* distinct leaf reads (slot, transposed) */
     long long ld[COOT_MAX_READS];      /* leading dimension of each read's operand */
@@ -85,34 +65,37 @@ typedef struct coot_kargs {
     long long aux;
 } coot_kargs;
 
-/* batched evaluation: one descriptor per item; the items' tiles (shape from
- * coot_tile_shape) are cut into tasks of at most COOT_BATCH_CHUNK consecutive
- * tiles (column-major tile order within the item), and every block runs a list of tasks (a static
- * longest-first schedule computed on the host) */
-#define COOT_BATCH_CHUNK 4
+/* batched evaluation: each item's value is cut into units (blocks of rc x k
+ * values of Y_i starting at row p0, column q0), at most E elements each, E
+ * chosen so that the operands read through trans() fit COOT_BATCH_LDS_BYTES
+ * of LDS; a block runs one unit with all its threads or up to four small
+ * units, one per wave */
+#define COOT_BATCH_LDS_BYTES 65536
+/* LDS elements of one staged operand: a unit stores its rows with an odd
+ * stride kp <= k + 1, which needs at most rc more elements (rc <= E/32) */
+COOT_HD long long coot_batch_stage_cap(long long E) { return E + E / 32; }
 
 typedef struct coot_batch_item_d {
     long long rows, cols;              /* Y_i shape */
-    long long ntiles;                  /* tiles of Y_i */
-    long long part0;                   /* partial slot of the item's first task */
-    int lr, lc;                        /* tile shape: 2^lr x 2^lc (coot_tile_shape) */
+    long long nunits;                  /* units of Y_i */
+    long long part0;                   /* partial slot of the item's first unit */
     void* out;
     const void* leaf[6];
 } coot_batch_item_d;
 
-typedef struct coot_batch_task_d {
+typedef struct coot_batch_unit_d {
     int item;
-    int t0, t1;                        /* tiles [t0, t1) of the item */
-    int part;                          /* partial slot (item's tasks are consecutive) */
-} coot_batch_task_d;
+    int p0, q0;                        /* first row and column of the unit in Y_i */
+    int rc, k;                         /* rows and columns of the unit */
+    int part;                          /* partial slot (an item's units are consecutive) */
+} coot_batch_unit_d;
 
 typedef struct coot_bargs {
     const coot_batch_item_d* items;
-    const coot_batch_task_d* tasks;
-    const int* order;                  /* task indices, block by block */
-    const int* blk_first;              /* block b runs order[blk_first[b] .. blk_first[b+1]) */
+    const coot_batch_unit_d* units;    /* in block order */
+    const int* blk_first;              /* block b runs units [blk_first[b], blk_first[b+1]) */
     long long n_items;
-    double* part;                      /* (hi, lo) per task when there is a reduction */
+    double* part;                      /* (hi, lo) per unit when there is a reduction */
     void* red_out;
 } coot_bargs;
 

@@ -124,6 +124,8 @@ std::string kernel_source(const Plan& p, const LaunchCfg& cfg, std::string* name
 std::string prelude_source();
 std::string batch_kernel_source(const Plan& py, const Plan* pr, bool has_out, int out_dtype, int red_dtype,
                                 const std::vector<int>& read_slot, std::string* name_out);
+// largest unit (elements) of a batched plan: its transposed reads fit the LDS stage
+int64_t batch_unit_elems(const Plan& py);
 
 // 64-entry configuration space
 LaunchCfg config_of(int index);

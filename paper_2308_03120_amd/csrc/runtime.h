@@ -47,6 +47,7 @@ void launch(hipFunction_t f, int64_t grid, int block, coot_kargs& a, hipStream_t
 void run_plan(const Plan& p, const LaunchCfg& cfg, const coot_operand* ops, const coot_operand* out, hipStream_t st);
 LaunchCfg choose_config(const Plan& p, const coot_config& user);
 std::string tune_key(const Plan& p);
+uint64_t kernel_stamp();  // host only: identity of the kernels and geometries of the 64 configurations
 
 // cost model (tune.cpp)
 int model_pick(const Plan& p);

@@ -17,6 +17,7 @@
 #include "runtime.h"
 
 extern "C" int coot_copy_launch(void* dst, const void* src, int64_t bytes, int cus, void* stream);
+extern "C" int coot_probe_launch(int kind, void* dst, const void* src, int64_t bytes, void* stream);
 extern "C" int coot_mlp_forward_launch(const float* P, const float* X, int B, float* Y, float* Z1, float* H,
                                        void* stream);
 extern "C" int coot_mlp_backward_launch(const float* P, const float* X, const float* T, const float* M, int B,
@@ -187,17 +188,45 @@ int guard2(F&& f)
 
 extern "C" {
 
+// Cost-model file: the 8 bytes "COOTMLP2", the feature schema (u32), a zero
+// u32, the kernel stamp (u64), then the FP32 parameters, feature means and
+// feature standard deviations.
+static const char MODEL_MAGIC[8] = {'C', 'O', 'O', 'T', 'M', 'L', 'P', '2'};
+
 int coot_set_tuning(int mode, const char* model_path)
 {
     return guard2([&] {
         if (mode < COOT_TUNE_DEFAULT || mode > COOT_TUNE_MODEL) fail(COOT_ERR_ARG, "unknown tuning mode");
         if (mode == COOT_TUNE_MODEL && model_path && *model_path) {
+            // a file that does not fit the library leaves the tuned cache, then the default
+            auto reject = [&](const std::string& why) {
+                g_state.model_ok = false;
+                g_state.tune_mode = COOT_TUNE_CACHE;
+                fail(COOT_ERR_ARG, std::string("cost model ") + model_path + " rejected (" + why +
+                                       "); tuning falls back to the tuned cache, then the default");
+            };
             std::ifstream in(model_path, std::ios::binary);
             if (!in) fail(COOT_ERR_ARG, std::string("cannot open model file ") + model_path);
+            char magic[8] = {0};
+            uint32_t schema = 0, zero = 1;
+            uint64_t stamp = 0;
+            in.read(magic, 8);
+            in.read((char*)&schema, 4);
+            in.read((char*)&zero, 4);
+            in.read((char*)&stamp, 8);
+            if (!in || std::memcmp(magic, MODEL_MAGIC, 8) != 0 || zero != 0)
+                reject("not a stamped cost-model file");
+            if (schema != COOT_FEATURE_SCHEMA)
+                reject("feature schema " + std::to_string(schema) + ", the library's is " +
+                       std::to_string(COOT_FEATURE_SCHEMA));
+            const uint64_t mine = kernel_stamp();
+            if (stamp != mine)
+                reject("trained on kernels " + hex64(stamp) + ", the library's are " + hex64(mine) +
+                       ": retrain it on these kernels");
             std::vector<float> buf(COOT_MLP_N_PARAMS + 64);
             in.read((char*)buf.data(), (std::streamsize)(buf.size() * sizeof(float)));
-            if (in.gcount() != (std::streamsize)(buf.size() * sizeof(float)))
-                fail(COOT_ERR_ARG, "model file has the wrong size");
+            if (in.gcount() != (std::streamsize)(buf.size() * sizeof(float)) || in.peek() != EOF)
+                reject("wrong size");
             g_state.model_params.assign(buf.begin(), buf.begin() + COOT_MLP_N_PARAMS);
             g_state.feat_mean.assign(buf.begin() + COOT_MLP_N_PARAMS, buf.begin() + COOT_MLP_N_PARAMS + 32);
             g_state.feat_std.assign(buf.begin() + COOT_MLP_N_PARAMS + 32, buf.end());
@@ -206,6 +235,15 @@ int coot_set_tuning(int mode, const char* model_path)
         }
         g_state.tune_mode = mode;
         return COOT_OK;
+    });
+}
+
+int coot_kernel_stamp(uint64_t* stamp)
+{
+    return guard2([&] {
+        if (!stamp) fail(COOT_ERR_ARG, "stamp is NULL");
+        *stamp = kernel_stamp();
+        return COOT_FEATURE_SCHEMA;
     });
 }
 
@@ -332,6 +370,24 @@ int coot_copy(void* dst, const void* src, int64_t bytes, void* stream)
         ensure_init();
         if (bytes == 0) return COOT_OK;
         if (coot_copy_launch(dst, src, bytes, g_state.cus, stream)) fail(COOT_ERR_HIP, "copy launch");
+        return COOT_OK;
+    });
+}
+
+int coot_bandwidth_probe(int kind, void* dst, const void* src, int64_t bytes, void* stream)
+{
+    return guard2([&] {
+        if (kind < COOT_PROBE_COPY || kind > COOT_PROBE_READ2_WRITE1) fail(COOT_ERR_ARG, "unknown probe kind");
+        if (bytes < 0 || bytes % 16) fail(COOT_ERR_ARG, "probe length must be a nonnegative multiple of 16 bytes");
+        if (bytes > 0 && ((kind != COOT_PROBE_WRITE && !src) || !dst)) fail(COOT_ERR_ARG, "NULL probe buffer");
+        if (((uintptr_t)dst | (uintptr_t)src) & 15) fail(COOT_ERR_ARG, "probe needs 16-byte aligned pointers");
+        ensure_init();
+        if (bytes == 0) return COOT_OK;
+        if (kind == COOT_PROBE_COPY) {
+            if (coot_copy_launch(dst, src, bytes, g_state.cus, stream)) fail(COOT_ERR_HIP, "copy launch");
+        } else if (coot_probe_launch(kind, dst, src, bytes, stream)) {
+            fail(COOT_ERR_HIP, "probe launch");
+        }
         return COOT_OK;
     });
 }

@@ -208,3 +208,41 @@ def test_batched_kernels_compile_for_gfx950(tmp_path):
     # without a reduction there is no combine kernel
     src2 = coot.BatchPlan.kernel_source(synth.cfg4_tree(), [coot.F32, coot.F32], [[5, 7]])
     assert "_comb" not in src2
+
+
+def test_batch_aliasing_rejected_before_any_device_work():
+    """coot_batch_create checks every item's output against the memory the
+    launch reads and writes before it allocates or launches anything, so the
+    checks run without a device.  Y_i = trans(A_i) + 0.5 * B_i' (A_i r x c,
+    B_i' and Y_i c x r)."""
+    import ctypes as C
+
+    tree = synth.cfg4_tree()
+    r, c = 6, 4
+    n = r * c * 4  # bytes of one FP32 item
+
+    def create(ptrs, outs, shapes=((c, r), (c, r)), red_out=None):
+        d = coot.BatchDescriptor(tree, [coot.F32, coot.F32], ptrs, [list(s) for s in shapes], out_ptrs=outs,
+                                 red_tree=leaf(0) % leaf(0) if red_out else None, red_out=red_out)
+        h = C.c_void_p()
+        return coot.lib().coot_batch_create(C.byref(d.struct), None, C.byref(h))
+
+    A0, B0, A1, B1, Y0, Y1 = (G * k for k in range(1, 7))
+    ALIAS = -4
+    # the output is an operand read through trans()
+    assert create([[A0, B0], [A1, B1]], [A0, Y1]) == ALIAS
+    # the output overlaps another item's operand
+    assert create([[A0, B0], [A1, B1]], [Y0, B0 + 8]) == ALIAS
+    # two outputs overlap
+    assert create([[A0, B0], [A1, B1]], [Y0, Y0 + n - 4]) == ALIAS
+    # the reduction results overlap an output
+    assert create([[A0, B0], [A1, B1]], [Y0, Y1], red_out=Y1 + 4) == ALIAS
+    # the output is the item's own straight slot, but starts elsewhere inside it
+    assert create([[A0, B0], [A1, B1]], [B0 + 4, Y1]) == ALIAS
+    assert "overlaps" in coot.last_error()
+    # in place on the straight slot (same extent and type) and disjoint outputs pass the
+    # check; without a device the call then fails at the device step instead
+    assert create([[A0, B0], [A1, B1]], [B0, B1]) != ALIAS
+    assert create([[A0, B0], [A1, B1]], [Y0, Y1], red_out=G * 7) != ALIAS
+    # items of no elements touch no memory
+    assert create([[A0, B0], [A1, B1]], [A0, Y1], shapes=((0, 3), (c, r))) != ALIAS

@@ -31,11 +31,22 @@ def unpack(v):
             "b2": v[6208:6272]}
 
 
+def read_weights(path):
+    """The stamped cost-model file: "COOTMLP2", schema (u32), 0 (u32), kernel
+    stamp (u64), then 6272 parameters, 32 feature means, 32 feature scales."""
+    raw = open(path, "rb").read()
+    assert raw[:8] == b"COOTMLP2"
+    schema, zero = np.frombuffer(raw[8:16], np.uint32)
+    stamp = int(np.frombuffer(raw[16:24], np.uint64)[0])
+    w = np.frombuffer(raw[24:], np.float32).astype(np.float64)
+    assert zero == 0 and w.size == 6272 + 64
+    return w, int(schema), stamp
+
+
 @pytest.fixture(scope="module")
 def data():
     z = np.load(CORPUS)
-    w = np.fromfile(WEIGHTS, dtype=np.float32).astype(np.float64)
-    assert w.size == 6272 + 64
+    w, _, _ = read_weights(WEIGHTS)
     return z, unpack(w[:6272]), w[6272:6304], w[6304:6336]
 
 
@@ -63,3 +74,47 @@ def test_model_beats_default_on_held_out(data):
     # geometric-mean speedup of the model's choice over the default choice
     sp = np.exp(np.mean(np.log(t[np.arange(len(te)), z["default"][te]] / t[np.arange(len(te)), picks])))
     assert sp > 1.0
+
+
+def test_mismatched_model_files_are_rejected(tmp_path):
+    """coot_set_tuning refuses a model file made for other kernels, another
+    feature layout or an unstamped one, says why, and leaves no model
+    installed (tuning falls back to the tuned cache, then the default).  Host
+    only: the checks come before anything is copied to a device."""
+    from paper_2308_03120_amd import coot, costmodel as cm
+
+    schema, stamp = coot.kernel_stamp()
+    params = np.zeros(cm.N_PARAMS, np.float32)
+    mean, std = np.zeros(32, np.float32), np.ones(32, np.float32)
+    cases = {
+        "stale": (dict(stamp=stamp ^ 1, schema=schema), "retrain"),
+        "schema": (dict(stamp=stamp, schema=schema + 1), "feature schema"),
+    }
+    x = synth.leaf(0)
+    ops = [coot.fake_operand(1000, 1, "f32")]
+    out = coot.fake_operand(1000, 1, "f32", ptr=3 << 40)
+    for name, (kw, why) in cases.items():
+        path = str(tmp_path / f"{name}.bin")
+        cm.save_model(path, params, mean, std, **kw)
+        with pytest.raises(coot.CootError) as e:
+            coot.set_tuning(coot.TUNE_MODEL, path)
+        assert e.value.code == -10 and why in e.value.msg and "falls back" in e.value.msg
+        with pytest.raises(coot.CootError) as e:
+            coot.model_choose(None, -1, x + 1.0, ops, out)
+        assert "no cost model" in e.value.msg
+    # the unstamped layout of earlier files
+    raw = str(tmp_path / "raw.bin")
+    np.concatenate([params, mean, std]).tofile(raw)
+    with pytest.raises(coot.CootError) as e:
+        coot.set_tuning(coot.TUNE_MODEL, raw)
+    assert "not a stamped" in e.value.msg
+    coot.set_tuning(coot.TUNE_DEFAULT)
+
+
+def test_stamp_follows_the_kernels():
+    """The stamp is a pure function of the library's generated kernels and
+    launch geometry: stable across calls, and written into saved files."""
+    from paper_2308_03120_amd import coot
+
+    a = coot.kernel_stamp()
+    assert a == coot.kernel_stamp() and a[0] == 1 and a[1] != 0

@@ -85,32 +85,41 @@ def test_small_ragged_batch_against_oracle(dt):
     plan.close()
 
 
-def test_results_do_not_depend_on_the_grid():
-    """Items are cut into fixed 4-tile tasks whose partials are combined in task
-    order, so Y and r are bit-identical for every grid size."""
+def test_results_do_not_depend_on_the_batch():
+    """Items are cut into units by their shape alone and each item's unit
+    partials are added in unit order, so Y_i and r_i are bit-identical
+    whatever else is in the batch and wherever the item sits in it (here: the
+    batch, the batch reversed, and every third item alone)."""
     g = np.random.default_rng(8)
-    shapes = np.concatenate([np.array([[512, 512], [300, 500], [1, 4000], [4000, 1], [65, 65]]),
+    shapes = np.concatenate([np.array([[512, 512], [300, 500], [1, 4000], [4000, 1], [65, 65], [20000, 3]]),
                              g.integers(1, 300, (200, 2))])
     offs, total, A, B = make_batch(shapes, g)
     dA, dB = torch.from_numpy(A).cuda(), torch.from_numpy(B).cuda()
     es = 4
-    ptrs = [[dA.data_ptr() + int(o) * es, dB.data_ptr() + int(o) * es] for o in offs]
+    n = len(shapes)
     res = []
-    for split in (1, 2, 8):
+    for order in (np.arange(n), np.arange(n)[::-1], np.arange(n)[::3]):
         dY = torch.full((total,), float("nan"), device="cuda")
-        red = torch.zeros(len(shapes), device="cuda")
-        plan = coot.BatchPlan(Ytree, [coot.F32, coot.F32], ptrs, [[int(c), int(r)] for r, c in shapes],
-                              out_ptrs=[dY.data_ptr() + int(o) * es for o in offs], red_tree=Rtree, red_op="accu",
-                              red_out=red, split=split)
+        red = torch.full((n,), float("nan"), device="cuda")
+        plan = coot.BatchPlan(Ytree, [coot.F32, coot.F32],
+                              [[dA.data_ptr() + int(offs[i]) * es, dB.data_ptr() + int(offs[i]) * es] for i in order],
+                              [[int(shapes[i][1]), int(shapes[i][0])] for i in order],
+                              out_ptrs=[dY.data_ptr() + int(offs[i]) * es for i in order], red_tree=Rtree,
+                              red_op="accu", red_out=red)
         plan.run()
         torch.cuda.synchronize()
-        res.append((dY.clone(), red.clone()))
+        r = torch.full((n,), float("nan"), device="cuda")
+        r[torch.from_numpy(np.ascontiguousarray(order)).cuda()] = red[:len(order)]
+        res.append((order, dY.clone(), r))
         plan.close()
-    for y, r in res[1:]:
-        assert torch.equal(torch.nan_to_num(y, nan=7.0), torch.nan_to_num(res[0][0], nan=7.0))
-        assert torch.equal(r, res[0][1])
-    rh = res[0][1].cpu().numpy().astype(np.float64)
-    for i in (0, 1, 2, 3):
+    for order, y, r in res[1:]:
+        for i in order:
+            a, b_ = int(offs[i]), int(offs[i] + shapes[i].prod())
+            assert torch.equal(y[a:b_], res[0][1][a:b_]), i
+        idx = torch.from_numpy(np.ascontiguousarray(order)).cuda()
+        assert torch.equal(r[idx], res[0][2][idx])
+    rh = res[0][2].cpu().numpy().astype(np.float64)
+    for i in (0, 1, 2, 3, 5):
         Am, Bm = host_mats(shapes, offs, A, B, i)
         o, _, _ = oracle.reduce("accu", (Ytree % Ytree).postfix(), [Am, Bm], mode="emu")
         assert abs(rh[i] - o[0]) <= 1e-6 * abs(o[0]), (i, rh[i], o[0])
@@ -220,3 +229,84 @@ def test_unfused_baseline_matches(full):
     rel = ((red3 - red[:n]).abs() / red[:n]).max().item()
     assert rel <= 1e-6
     p3.close()
+
+
+def test_one_call_batched_entry(full):
+    """coot_eval_batched through the C ABI: the first call builds the plan,
+    later calls with the same descriptor replay its graph; Y_i bit-exact
+    against the oracle's per-node rounding, r_i within 1e-6 of the oracle, and
+    both bit-identical to coot_batch_run of an explicitly created plan."""
+    import ctypes as C
+
+    d, dA, dB, dY, red, plan = full
+    shapes, offs = d["shapes"], d["offsets"]
+    plan.run()
+    torch.cuda.synchronize()
+    y_ref, r_ref = dY.clone(), red.clone()
+    es = 4
+    dY2 = torch.full_like(dY, float("nan"))
+    red2 = torch.full_like(red, float("nan"))
+    desc = coot.BatchDescriptor(Ytree, [coot.F32, coot.F32],
+                                [[dA.data_ptr() + int(o) * es, dB.data_ptr() + int(o) * es] for o in offs],
+                                [[int(c), int(r)] for r, c in shapes],
+                                out_ptrs=[dY2.data_ptr() + int(o) * es for o in offs], out_dtype=coot.F32,
+                                red_tree=Rtree, red_op="accu", red_out=red2, red_dtype=coot.F32)
+    # the items' elements (the padding between items is never written)
+    inside = np.zeros(dY.numel(), bool)
+    for o, (r, c) in zip(offs, shapes):
+        inside[int(o):int(o) + int(r * c)] = True
+    inside = torch.from_numpy(inside).cuda()
+    launches0 = coot.stats()["launches"]
+    rc = coot.lib().coot_eval_batched(C.byref(desc.struct), C.c_void_p(coot.current_stream()))
+    assert rc == 0, coot.last_error()
+    torch.cuda.synchronize()
+    assert torch.equal(dY2[inside], y_ref[inside]) and torch.equal(red2, r_ref)
+    assert torch.isnan(dY2[~inside]).all()
+    # a replay of the cached plan: one graph launch, the same bits
+    dY2.fill_(float("nan"))
+    red2.fill_(float("nan"))
+    launches1 = coot.stats()["launches"]
+    assert coot.lib().coot_eval_batched(C.byref(desc.struct), C.c_void_p(coot.current_stream())) == 0
+    torch.cuda.synchronize()
+    assert coot.stats()["launches"] - launches1 == 1 and launches1 - launches0 == 1
+    assert torch.equal(dY2[inside], y_ref[inside]) and torch.equal(red2, r_ref)
+    Yh = dY2.cpu().numpy().astype(np.float64)
+    rh = red2.cpu().numpy().astype(np.float64)
+    g = np.random.default_rng(17)
+    for i in g.choice(len(shapes), 100, replace=False):
+        r, c = shapes[i]
+        Am, Bm = host_mats(shapes, offs, d["A"], d["Bp"], i)
+        em = oracle.evaluate(Ytree.postfix(), [Am, Bm], "emu")
+        assert np.array_equal(Yh[offs[i]:offs[i] + r * c].reshape((c, r), order="F"), em), i
+        o, _, _ = oracle.reduce("accu", (Ytree % Ytree).postfix(), [Am, Bm], mode="emu")
+        assert abs(rh[i] - o[0]) <= 1e-6 * o[0], (i, rh[i], o[0])
+
+
+def test_one_call_batched_entry_follows_the_descriptor():
+    """A descriptor whose contents change gets a plan of its own (new pointers
+    give new results); more descriptors than the library keeps evict the
+    oldest plan, which is rebuilt when used again."""
+    g = np.random.default_rng(21)
+    shapes = g.integers(1, 90, (40, 2))
+    offs, total, A, B = make_batch(shapes, g)
+    dA, dB = torch.from_numpy(A).cuda(), torch.from_numpy(B).cuda()
+    es = 4
+    ptrs = [[dA.data_ptr() + int(o) * es, dB.data_ptr() + int(o) * es] for o in offs]
+    outs = [torch.full((total,), float("nan"), device="cuda") for _ in range(18)]
+    reds = [torch.zeros(len(shapes), device="cuda") for _ in range(18)]
+    descs = [coot.BatchDescriptor(Ytree, [coot.F32, coot.F32], ptrs, [[int(c), int(r)] for r, c in shapes],
+                                  out_ptrs=[outs[k].data_ptr() + int(o) * es for o in offs], red_tree=Rtree,
+                                  red_out=reds[k]) for k in range(18)]
+    for k in range(18):
+        coot.eval_batched(descs[k])
+    coot.eval_batched(descs[0])   # evicted by the 17th descriptor: rebuilt
+    torch.cuda.synchronize()
+    for k in range(1, 18):
+        assert torch.equal(torch.nan_to_num(outs[k], nan=3.0), torch.nan_to_num(outs[0], nan=3.0))
+        assert torch.equal(reds[k], reds[0])
+    Yh = outs[0].cpu().numpy().astype(np.float64)
+    for i in (0, 7, 39):
+        r, c = shapes[i]
+        Am, Bm = host_mats(shapes, offs, A, B, i)
+        assert np.array_equal(Yh[offs[i]:offs[i] + r * c].reshape((c, r), order="F"),
+                              oracle.evaluate(Ytree.postfix(), [Am, Bm], "emu"))

@@ -1,6 +1,6 @@
-"""The committed cost model inside the library: coot_set_tuning(COOT_TUNE_MODEL)
-loads the trained weights and, at plan time, runs the MLP forward kernel on the
-call's features; its pick must be the argmin of the FP64 oracle forward of the
+"""The committed cost model inside the library: installed weights (coot_model_set,
+or a stamped file through coot_set_tuning(COOT_TUNE_MODEL)) are run, at plan
+time, by the MLP forward kernel on the call's features; its pick must be the argmin of the FP64 oracle forward of the
 same weights on the same features (up to near-ties the FP32 kernel may order
 differently), and the tuned call must still compute the right values."""
 import os
@@ -40,7 +40,8 @@ def unpack(v):
 def test_library_inference_matches_oracle_forward():
     params, mean, std = cm.load_model(WEIGHTS)
     p = unpack(params.astype(np.float64))
-    coot.set_tuning(coot.TUNE_MODEL, WEIGHTS)
+    coot.model_set(params, mean, std)
+    coot.set_tuning(coot.TUNE_MODEL)
     trees = synth.cfg5_trees(6000)
     _, te = synth.cfg5_split(6000, 5000)
     mismatches = 0
@@ -60,8 +61,24 @@ def test_library_inference_matches_oracle_forward():
     assert mismatches <= 2
 
 
+def test_stamped_file_loads(tmp_path):
+    """A model file stamped with the library's kernels is accepted by
+    coot_set_tuning and installed (its picks are the installed weights')."""
+    params, mean, std = cm.load_model(WEIGHTS)
+    path = str(tmp_path / "stamped.bin")
+    cm.save_model(path, params, mean, std)
+    coot.set_tuning(coot.TUNE_MODEL, path)
+    rt = synth.cfg5_trees(6000)[int(synth.cfg5_split(6000, 5000)[1][0])]
+    red, dim, ops, out = cm.fake_call(rt)
+    a = coot.model_choose(red, dim, rt.expr, ops, out)
+    coot.model_set(params, mean, std)
+    assert coot.model_choose(red, dim, rt.expr, ops, out) == a
+    coot.set_tuning(coot.TUNE_DEFAULT)
+
+
 def test_model_tuned_calls_compute_the_same_values():
-    coot.set_tuning(coot.TUNE_MODEL, WEIGHTS)
+    coot.model_set(*cm.load_model(WEIGHTS))
+    coot.set_tuning(coot.TUNE_MODEL)
     g = np.random.default_rng(17)
     x, y = synth.leaves(2)
     A = synth.Mat(np.asfortranarray(g.uniform(0.5, 2.0, (300, 700)).astype(np.float32)), "f32")
