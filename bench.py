@@ -335,7 +335,7 @@ def costmodel_workload(args, np, torch, synth, coot):
     coot.model_set(params, mean, std)
     gen = torch.Generator(device="cuda")
     gen.manual_seed(7)
-    sample = te_idx[:200]
+    sample = te_idx
     t_def = t_mod = t_unf = 0.0
     agree = 0
     for i in sample:
@@ -376,7 +376,7 @@ def costmodel_workload(args, np, torch, synth, coot):
                    "trees": len(trees), "train": int(len(tr_idx)), "held_out": int(len(te_idx)),
                    "configs": 64},
         "held_out": held, "train_fit": fit, "loss_history": hist,
-        "end_to_end_sample": {"trees": int(len(sample)), "model_picks_match_library_inference": agree,
+        "end_to_end_held_out": {"trees": int(len(sample)), "model_picks_match_library_inference": agree,
                               "ms_default": round(t_def, 3), "ms_model": round(t_mod, 3), "ms_unfused": round(t_unf, 3),
                               "model_speedup_over_default": round(t_def / t_mod, 4),
                               "model_speedup_over_unfused": round(t_unf / t_mod, 4)},
