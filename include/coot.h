@@ -52,7 +52,8 @@ enum {
     COOT_ERR_HIP = -8,          /* a HIP runtime call failed */
     COOT_ERR_NOMEM = -9,        /* host or device allocation failed */
     COOT_ERR_ARG = -10,         /* bad argument (null pointer, ld, sizes, flags) */
-    COOT_ERR_NOT_INIT = -11     /* coot_init has not been called */
+    COOT_ERR_NOT_INIT = -11,    /* coot_init has not been called */
+    COOT_ERR_NOT_READY = -12    /* coot_reduce_noalloc: the call's kernel is not loaded yet */
 };
 
 /* -------------------------------------------------------- element types -- */
@@ -299,6 +300,28 @@ int coot_eval(const coot_expr* expr, const coot_operand* ops, int n_ops,
  * synchronises the stream (the paper's `float r = accu(f)`). */
 int coot_reduce(int red_op, int dim, const coot_expr* expr, const coot_operand* ops,
                 int n_ops, const coot_operand* out, void* stream);
+
+/* coot_reduce without any device allocation, for callers that cannot
+ * allocate: code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc.  Same arguments and results as coot_reduce (bit-identical
+ * to it for the same call); the block partials live in one static device
+ * array of COOT_NOALLOC_SCRATCH_BYTES per GPU (held until the process ends)
+ * instead of per-stream memory.  It calls no hipMalloc/hipFree, compiles and
+ * loads no kernel, and never synchronises.  Errors beyond coot_reduce's:
+ *   COOT_ERR_NOT_INIT   coot_init has not been called on this device;
+ *   COOT_ERR_NOT_READY  the kernel of this call is not loaded yet (make the
+ *                       same kind of call once through coot_reduce first);
+ *   COOT_ERR_ARG        out has COOT_OPERAND_HOST, the call's partials exceed
+ *                       COOT_NOALLOC_SCRATCH_BYTES, or it needs a temporary
+ *                       (a per-dimension reduction of a tree that reads an
+ *                       operand transposed) or the unfused form.
+ * The launch configuration is the caller's (expr->cfg), a tuned or an
+ * already-predicted one, else the default: the learned model is not run.
+ * Every call on one GPU shares the array: calls that overlap on one GPU (two
+ * streams, or two host threads) race on it and must be ordered by the caller. */
+#define COOT_NOALLOC_SCRATCH_BYTES (16u << 20)
+int coot_reduce_noalloc(int red_op, int dim, const coot_expr* expr, const coot_operand* ops, int n_ops,
+                        const coot_operand* out, void* stream);
 
 /* Wait for all work enqueued on `stream` (Section 5: coot_synchronise). */
 int coot_synchronise(void* stream);

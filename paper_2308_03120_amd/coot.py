@@ -26,7 +26,7 @@ os.environ.setdefault("COOT_CACHE_DIR", os.path.join(_HERE, "_kcache"))
 OK = 0
 ERRORS = {
     -1: "BAD_TREE", -2: "SHAPE", -3: "DTYPE", -4: "ALIAS", -5: "EMPTY", -6: "UNSUPPORTED",
-    -7: "JIT", -8: "HIP", -9: "NOMEM", -10: "ARG", -11: "NOT_INIT",
+    -7: "JIT", -8: "HIP", -9: "NOMEM", -10: "ARG", -11: "NOT_INIT", -12: "NOT_READY",
 }
 F32, F64, F16, BF16, U64, I32, U32 = 0, 1, 2, 3, 4, 5, 6
 DTYPE_CODES = {"f32": F32, "f64": F64, "f16": F16, "bf16": BF16, "u64": U64, "i32": I32, "u32": U32}
@@ -136,6 +136,7 @@ def lib():
         L.coot_init.argtypes = [i32, C.c_uint]
         L.coot_eval.argtypes = [P(Expr), P(Operand), i32, P(Operand), vp]
         L.coot_reduce.argtypes = [i32, i32, P(Expr), P(Operand), i32, P(Operand), vp]
+        L.coot_reduce_noalloc.argtypes = [i32, i32, P(Expr), P(Operand), i32, P(Operand), vp]
         L.coot_synchronise.argtypes = [vp]
         L.coot_last_error.restype = C.c_char_p
         L.coot_validate.argtypes = [i32, i32, P(Expr), P(Operand), i32, P(Operand)]
@@ -409,6 +410,18 @@ def reduce(op, tree, operands: Sequence, out=None, dim: int = -1, pairwise: bool
     o = operand(out)
     _check(lib().coot_reduce(_red_code(op, pairwise), dim, C.byref(e), arr, n, C.byref(o),
                              stream if stream is not None else current_stream()))
+    return out
+
+
+def reduce_noalloc(op, tree, operands: Sequence, out, dim: int = -1, pairwise: bool = False, cfg=None,
+                   stream=None):
+    """coot_reduce_noalloc: ``reduce`` into a caller-given device ``out`` with no
+    device allocation (partials in the library's static scratch array)."""
+    e = expr(tree, cfg, False)
+    arr, n = _ops(operands)
+    o = operand(out)
+    _check(lib().coot_reduce_noalloc(_red_code(op, pairwise), dim, C.byref(e), arr, n, C.byref(o),
+                                     stream if stream is not None else current_stream()))
     return out
 
 

@@ -67,6 +67,7 @@ static void init_device(int device, unsigned flags)
     }
     if (device < 0 || device >= n) fail(COOT_ERR_ARG, "device index out of range");
     hipchk(hipSetDevice(device), "hipSetDevice");
+    noalloc_setup(device);
     hipDeviceProp_t prop;
     hipchk(hipGetDeviceProperties(&prop, device), "hipGetDeviceProperties");
     g_state.device = device;
@@ -177,6 +178,24 @@ LaunchCfg choose_config(const Plan& p, const coot_config& user)
     }
     if (g_state.tune_mode == COOT_TUNE_MODEL && g_state.model_ok) {
         int idx = model_pick(p);
+        if (idx >= 0) return config_of(idx);
+    }
+    return default_config(p);
+}
+
+// choose_config without running the learned model (no kernel launch, no
+// synchronisation): the caller's, a tuned or an already-predicted
+// configuration, else the default
+LaunchCfg choose_config_noalloc(const Plan& p, const coot_config& user)
+{
+    if (user.ept) return LaunchCfg{user.ept, user.block, user.split};
+    if (g_state.tune_mode != COOT_TUNE_DEFAULT) {
+        std::lock_guard<std::mutex> lk(g_state.mu);
+        auto it = g_state.tuned.find(tune_key(p));
+        if (it != g_state.tuned.end()) return config_of(it->second);
+    }
+    if (g_state.tune_mode == COOT_TUNE_MODEL && g_state.model_ok) {
+        int idx = model_cached_pick(p);
         if (idx >= 0) return config_of(idx);
     }
     return default_config(p);
@@ -371,7 +390,9 @@ static std::string sig_key(const Plan& p, const LaunchCfg& c)
            std::to_string(p.tile_lr) + "," + std::to_string(p.tile_lc) + "|" + p.body_sig;
 }
 
-static Kernel kernel_for(const Plan& p, const LaunchCfg& c)
+// loaded_only: never compile or load a module (the allocation-free entry
+// point); a kernel not yet resident fails with COOT_ERR_NOT_READY
+static Kernel kernel_for(const Plan& p, const LaunchCfg& c, bool loaded_only = false)
 {
     std::string key = sig_key(p, c);
     {
@@ -381,7 +402,15 @@ static Kernel kernel_for(const Plan& p, const LaunchCfg& c)
     }
     std::string name;
     std::string src = kernel_source(p, c, &name, nullptr);
-    Kernel k = get_kernel(name, src, p.kind == K_RED_ROW || p.kind == K_RED_COL || p.kind == K_RED_FLAT || p.kind == K_RED_TILED);
+    const bool comb = p.kind == K_RED_ROW || p.kind == K_RED_COL || p.kind == K_RED_FLAT || p.kind == K_RED_TILED;
+    Kernel k;
+    if (loaded_only) {
+        if (!find_loaded_kernel(name, comb, &k))
+            fail(COOT_ERR_NOT_READY, "the kernel of this call (" + name +
+                                         ") is not loaded yet: make the same call once through coot_reduce first");
+    } else {
+        k = get_kernel(name, src, comb);
+    }
     std::lock_guard<std::mutex> lk(g_sig_mu);
     g_sig_kernels[key] = k;
     return k;
@@ -394,10 +423,10 @@ void forget_kernels()
 }
 
 void run_plan(const Plan& p, const LaunchCfg& cfg_in, const coot_operand* ops, const coot_operand* out,
-              hipStream_t st)
+              hipStream_t st, const FixedScratch* fixed)
 {
     LaunchCfg c = normalise_config(p, cfg_in);
-    Kernel k = kernel_for(p, c);
+    Kernel k = kernel_for(p, c, fixed != nullptr);
     Geometry G = geometry(p, c);
     coot_kargs a;
     std::memset(&a, 0, sizeof a);
@@ -417,9 +446,18 @@ void run_plan(const Plan& p, const LaunchCfg& cfg_in, const coot_operand* ops, c
     const int64_t n_out = p.dim < 0 ? 1 : (p.dim == 0 ? p.cols : p.rows);
     const bool host = (out->flags & COOT_OPERAND_HOST) != 0;
     const size_t res_bytes = (size_t)n_out * 8;
-    Scratch& s = scratch_for(st, G.part_bytes, host ? res_bytes : 0);
-    a.part = s.part;
-    a.res = host ? s.res : out->ptr;
+    if (fixed) {
+        if (host) fail(COOT_ERR_ARG, "the allocation-free entry point needs a device output");
+        if (G.part_bytes > fixed->bytes)
+            fail(COOT_ERR_ARG, "the call needs " + std::to_string(G.part_bytes) + " bytes of partials, more than the " +
+                                   std::to_string(fixed->bytes) + " bytes of the static scratch array");
+        a.part = fixed->ptr;
+        a.res = out->ptr;
+    } else {
+        Scratch& s = scratch_for(st, G.part_bytes, host ? res_bytes : 0);
+        a.part = s.part;
+        a.res = host ? s.res : out->ptr;
+    }
     if (p.kind == K_RED_FLAT || p.kind == K_RED_TILED) {
         // pass 1 leaves one partial per block; pass 2 (one block) combines them
         a.splits = G.grid;

@@ -268,6 +268,15 @@ Kernel get_kernel(const std::string& name, const std::string& body, bool has_com
     return k;
 }
 
+bool find_loaded_kernel(const std::string& name, bool has_comb, Kernel* k)
+{
+    std::lock_guard<std::mutex> lk(g_mu);
+    auto it = g_mem.find(name);
+    if (it == g_mem.end() || (has_comb && !it->second.fn2)) return false;
+    *k = it->second;
+    return true;
+}
+
 void jit_unload_all()
 {
     std::lock_guard<std::mutex> lk(g_mu);

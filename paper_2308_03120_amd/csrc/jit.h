@@ -26,6 +26,9 @@ const std::string& cache_dir();
 // Load (compiling on a cache miss) the module of `body` and its entry point(s).
 Kernel get_kernel(const std::string& name, const std::string& body, bool has_comb);
 
+// The kernel only if its module is already loaded (no compilation, no load).
+bool find_loaded_kernel(const std::string& name, bool has_comb, Kernel* k);
+
 // Compile into the disk cache only (no device needed).  1 = compiled, 0 = cached.
 int precompile_kernel(const std::string& name, const std::string& body);
 

@@ -44,13 +44,25 @@ void ensure_init();
 Scratch& scratch_for(hipStream_t st, size_t part_bytes, size_t res_bytes);
 int64_t grid_cap(const LaunchCfg& c);
 void launch(hipFunction_t f, int64_t grid, int block, coot_kargs& a, hipStream_t st);
-void run_plan(const Plan& p, const LaunchCfg& cfg, const coot_operand* ops, const coot_operand* out, hipStream_t st);
+// device memory that stands in for the per-stream partials (allocation-free calls)
+struct FixedScratch {
+    void* ptr;
+    size_t bytes;
+};
+void run_plan(const Plan& p, const LaunchCfg& cfg, const coot_operand* ops, const coot_operand* out, hipStream_t st,
+              const FixedScratch* fixed = nullptr);
 LaunchCfg choose_config(const Plan& p, const coot_config& user);
+LaunchCfg choose_config_noalloc(const Plan& p, const coot_config& user);
+
+// allocation-free entry point (noalloc.hip): look up the static scratch
+// array's address on `device` (current)
+void noalloc_setup(int device);
 std::string tune_key(const Plan& p);
 uint64_t kernel_stamp();  // host only: identity of the kernels and geometries of the 64 configurations
 
 // cost model (tune.cpp)
 int model_pick(const Plan& p);
+int model_cached_pick(const Plan& p);  // an earlier prediction for p's size class, else -1
 
 // batched plans (batched.cpp)
 void batch_destroy_all();

@@ -141,6 +141,12 @@ static void model_upload()
 }
 
 // index of the configuration with the smallest predicted time (GPU inference)
+int model_cached_pick(const Plan& p)
+{
+    auto it = g_model_cache.find(tune_key(p));
+    return it == g_model_cache.end() ? -1 : it->second;
+}
+
 int model_pick(const Plan& p)
 {
     std::string key = tune_key(p);
