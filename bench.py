@@ -528,18 +528,23 @@ def precision_workload(args, np, torch, synth, coot):
 
 def ceilings(torch, coot, nbytes=1 << 30):
     """Median device time and GB/s of the library's streaming probes over
-    `nbytes` per stream: read only, write only, 1:1 copy, 2 reads : 1 write;
-    plus the 2:1 ceiling derived from the read-only and write-only rates
-    (time of 2 read streams at the read rate plus 1 write stream at the write
-    rate)."""
+    `nbytes` per stream: read only, write only, 1:1 copy, 2 reads : 1 write,
+    each the fastest of four launch shapes (threads x vectors per thread:
+    256x4, 64x1, 256x1, 128x2); plus the 2:1 ceiling derived from the
+    read-only and write-only rates (time of 2 read streams at the read rate
+    plus 1 write stream at the write rate)."""
     src = torch.zeros(2 * nbytes // 4, dtype=torch.float32, device="cuda")
     dst = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda")
     res = {}
+    shapes = ("256x4", "64x1", "256x1", "128x2")
     for name, kind, moved in (("read_only", coot.PROBE_READ, nbytes), ("write_only", coot.PROBE_WRITE, nbytes),
                               ("copy_1to1", coot.PROBE_COPY, 2 * nbytes),
                               ("mix_2to1", coot.PROBE_READ2_WRITE1, 3 * nbytes)):
-        us = event_stats(torch, lambda: coot.bandwidth_probe(kind, dst, src, nbytes))[0]
-        res[name] = {"us": round(us, 2), "GBps": round(moved / (us * 1e-6) / 1e9, 1)}
+        per = [event_stats(torch, lambda: coot.bandwidth_probe(kind | (sh << 8), dst, src, nbytes))[0]
+               for sh in range(4)]
+        b = min(range(4), key=lambda i: per[i])
+        res[name] = {"us": round(per[b], 2), "GBps": round(moved / (per[b] * 1e-6) / 1e9, 1), "shape": shapes[b],
+                     "GBps_by_shape": {shapes[i]: round(moved / (per[i] * 1e-6) / 1e9, 1) for i in range(4)}}
     r, w = res["read_only"]["GBps"], res["write_only"]["GBps"]
     res["mix_2to1_derived"] = {"GBps": round(3.0 / (2.0 / r + 1.0 / w), 1)}
     res["bytes_per_stream"] = nbytes

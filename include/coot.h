@@ -523,10 +523,12 @@ int coot_get_stats(coot_stats* stats);
 int coot_copy(void* dst, const void* src, int64_t bytes, void* stream);
 
 /* Bandwidth probes: the simplest streaming kernels with a given mix of reads
- * and writes, launched like the fused element-wise kernels' default (one
- * pass, 256 threads, four 16-byte vectors per thread, nontemporal loads and
- * stores), so that a fused call can be compared with the ceiling of its own
- * read/write mix.  `bytes` (a multiple of 16) is the length of each stream;
+ * and writes (one pass, nontemporal 16-byte loads and stores), so that a
+ * fused call can be compared with the ceiling of its own read/write mix.
+ * kind = a COOT_PROBE_* value | (shape << 8), shape the launch shape:
+ * 0 = 256 threads x 4 vectors per thread (COOT_PROBE_COPY with shape 0 is
+ * coot_copy), 1 = 64 x 1 (the fused element-wise default), 2 = 256 x 1,
+ * 3 = 128 x 2.  `bytes` (a multiple of 16) is the length of each stream;
  * pointers are 16-byte aligned device memory:
  *   COOT_PROBE_COPY          dst = src (coot_copy): reads and writes bytes
  *   COOT_PROBE_READ          reads src; dst (16 bytes) is written only if a

@@ -40,22 +40,22 @@ __global__ void __launch_bounds__(256) coot_copy16(u32x4* __restrict__ dst, cons
         for (int64_t i = threadIdx.x; i < ntail; i += blockDim.x) dtail[i] = stail[i];
 }
 
-// Streaming probes with other read/write mixes, launched like the copy (and
-// like the fused element-wise kernels' default): one pass, 256 threads, 4
-// vectors of 16 bytes per thread, nontemporal.  KIND 1 reads only: the loads
-// are folded into a per-thread XOR that is stored only if all its bits are
-// set (the loads cannot be dropped; random data never stores).  KIND 2 writes
+// Streaming probes with a given read/write mix, nontemporal, one pass, EPT
+// vectors of 16 bytes per thread (the launch shapes of the fused
+// element-wise kernels).  KIND 0 copies.  KIND 1 reads only: the loads are
+// folded into a per-thread XOR that is stored only if all its bits are set
+// (the loads cannot be dropped; random data never stores).  KIND 2 writes
 // only.  KIND 3 reads two streams and writes one (dst = a XOR b), the mix of
 // a two-operand element-wise tree.
-template <int KIND>
+template <int KIND, int EPT>
 __global__ void __launch_bounds__(256) coot_probe16(u32x4* __restrict__ dst, const u32x4* __restrict__ src, int64_t nv)
 {
-    const int64_t step = (int64_t)gridDim.x * blockDim.x * 4;
+    const int64_t step = (int64_t)gridDim.x * blockDim.x * EPT;
     u32x4 acc = {0u, 0u, 0u, 0u};
-    for (int64_t b = (int64_t)blockIdx.x * blockDim.x * 4 + threadIdx.x; b < nv; b += step) {
-        u32x4 r[4], q[4];
+    for (int64_t b = (int64_t)blockIdx.x * blockDim.x * EPT + threadIdx.x; b < nv; b += step) {
+        u32x4 r[EPT], q[EPT];
 #pragma unroll
-        for (int e = 0; e < 4; ++e) {
+        for (int e = 0; e < EPT; ++e) {
             const int64_t v = b + (int64_t)e * blockDim.x;
             if (v < nv) {
                 if (KIND != 2) r[e] = __builtin_nontemporal_load(src + v);
@@ -63,9 +63,10 @@ __global__ void __launch_bounds__(256) coot_probe16(u32x4* __restrict__ dst, con
             }
         }
 #pragma unroll
-        for (int e = 0; e < 4; ++e) {
+        for (int e = 0; e < EPT; ++e) {
             const int64_t v = b + (int64_t)e * blockDim.x;
             if (v < nv) {
+                if (KIND == 0) __builtin_nontemporal_store(r[e], dst + v);
                 if (KIND == 1) acc ^= r[e];
                 if (KIND == 2) __builtin_nontemporal_store(u32x4{(u32)v, 0u, 0u, 0u}, dst + v);
                 if (KIND == 3) __builtin_nontemporal_store(r[e] ^ q[e], dst + v);
@@ -74,6 +75,28 @@ __global__ void __launch_bounds__(256) coot_probe16(u32x4* __restrict__ dst, con
     }
     if (KIND == 1 && (acc.x & acc.y & acc.z & acc.w) == 0xffffffffu) dst[0] = acc;
 }
+
+template <int KIND>
+void probe_shape(int shape, int64_t nv, u32x4* d, const u32x4* sv, hipStream_t st)
+{
+    // (vectors per thread, threads per block) of shapes 0..3
+    static const int ept[4] = {4, 1, 1, 2}, blk[4] = {256, 64, 256, 128};
+    const int64_t per = (int64_t)ept[shape] * blk[shape];
+    int64_t grid = (nv + per - 1) / per;
+    if (grid > INT64_C(0x7fffffff)) grid = INT64_C(0x7fffffff);
+    if (grid < 1) grid = 1;
+    const dim3 g((unsigned)grid), b((unsigned)blk[shape]);
+    switch (shape) {
+    case 0: hipLaunchKernelGGL((coot_probe16<KIND, 4>), g, b, 0, st, d, sv, nv); break;
+    case 1: hipLaunchKernelGGL((coot_probe16<KIND, 1>), g, b, 0, st, d, sv, nv); break;
+    case 2: hipLaunchKernelGGL((coot_probe16<KIND, 1>), g, b, 0, st, d, sv, nv); break;
+    default: hipLaunchKernelGGL((coot_probe16<KIND, 2>), g, b, 0, st, d, sv, nv); break;
+    }
+}
+
+}  // namespace
+
+namespace {
 
 // ---- MLP 32 -> 64 (ReLU) -> 64 -----------------------------------------------
 // params: W1[32][64] b1[64] W2[64][64] b2[64]; row-major, W[i][j] input i -> output j.
@@ -205,21 +228,18 @@ int coot_copy_launch(void* dst, const void* src, int64_t bytes, int cus, void* s
     return hipGetLastError() == hipSuccess ? 0 : -8;
 }
 
-int coot_probe_launch(int kind, void* dst, const void* src, int64_t bytes, void* stream)
+int coot_probe_launch(int kind, int shape, void* dst, const void* src, int64_t bytes, void* stream)
 {
     const int64_t nv = bytes / 16;
-    int64_t need = (nv + 1023) / 1024;
-    int64_t grid = need < INT64_C(0x7fffffff) ? need : INT64_C(0x7fffffff);
-    if (grid < 1) grid = 1;
     u32x4* d = (u32x4*)dst;
     const u32x4* sv = (const u32x4*)src;
     hipStream_t st = (hipStream_t)stream;
+    if (shape < 0 || shape > 3) return -10;
     switch (kind) {
-    case COOT_PROBE_READ: hipLaunchKernelGGL(coot_probe16<1>, dim3((unsigned)grid), dim3(256), 0, st, d, sv, nv); break;
-    case COOT_PROBE_WRITE: hipLaunchKernelGGL(coot_probe16<2>, dim3((unsigned)grid), dim3(256), 0, st, d, sv, nv); break;
-    case COOT_PROBE_READ2_WRITE1:
-        hipLaunchKernelGGL(coot_probe16<3>, dim3((unsigned)grid), dim3(256), 0, st, d, sv, nv);
-        break;
+    case COOT_PROBE_COPY: probe_shape<0>(shape, nv, d, sv, st); break;
+    case COOT_PROBE_READ: probe_shape<1>(shape, nv, d, sv, st); break;
+    case COOT_PROBE_WRITE: probe_shape<2>(shape, nv, d, sv, st); break;
+    case COOT_PROBE_READ2_WRITE1: probe_shape<3>(shape, nv, d, sv, st); break;
     default: return -10;
     }
     return hipGetLastError() == hipSuccess ? 0 : -8;

@@ -163,7 +163,7 @@ std::string tune_key(const Plan& p)
     };
     return std::to_string(p.kind) + "|" + std::to_string(p.ve) + "|" + std::to_string(p.red_op) + "|" +
            std::to_string(p.pairwise) + "|" + std::to_string(p.dim) + "|" + std::to_string(p.tile_lr) + "," +
-           std::to_string(p.tile_lc) + "|" +
+           std::to_string(p.tile_lc) + "|t" + std::to_string(p.thin_k) + (p.thin_rows ? "r" : "c") + "|" +
            std::to_string(p.out_dtype) + "|" +
            p.body_sig + "|n" + std::to_string(lg2(p.n)) + "|r" + std::to_string(lg2(p.rows));
 }
@@ -225,6 +225,14 @@ static Geometry geometry(const Plan& p, const LaunchCfg& c)
     }
     case K_EW_TILED:
     case K_RED_TILED: {
+        if (p.thin_k) {
+            // groups of thin_v long-side positions, 8 / K groups per thread in flight
+            const int64_t ng = (p.thin_rows ? p.cols : p.rows) / p.thin_v;
+            const int64_t need = std::max<int64_t>(1, ceil_div(ng, 256 * std::max(1, 8 / p.thin_k)));
+            G.block = 256;
+            G.grid = std::min(need, c.split >= 8 ? need : (int64_t)g_state.cus * c.split * 2);
+            break;
+        }
         int64_t nt = ceil_div(p.rows, int64_t(1) << p.tile_lr) * ceil_div(p.cols, int64_t(1) << p.tile_lc);
         G.block = 256;
         G.grid = std::max<int64_t>(1, std::min(nt, c.split >= 8 ? nt : (int64_t)g_state.cus * c.split * 2));
@@ -387,7 +395,8 @@ static std::string sig_key(const Plan& p, const LaunchCfg& c)
     return std::to_string(p.kind) + "|" + std::to_string(p.ve) + "|" + std::to_string(c.ept) + "|" +
            std::to_string(p.out_dtype) + "|" + std::to_string(p.red_op) + "|" + std::to_string(p.pairwise) + "|" +
            std::to_string(p.alias_out) + "|" + std::to_string(p.tile_gen) + std::to_string(p.tile_off32) +
-           std::to_string(p.tile_lr) + "," + std::to_string(p.tile_lc) + "|" + p.body_sig;
+           std::to_string(p.tile_lr) + "," + std::to_string(p.tile_lc) + "|t" + std::to_string(p.thin_k) +
+           (p.thin_rows ? "r" : "c") + std::to_string(p.thin_v) + "v" + std::to_string(p.thin_vec) + "|" + p.body_sig;
 }
 
 // loaded_only: never compile or load a module (the allocation-free entry
@@ -436,7 +445,7 @@ void run_plan(const Plan& p, const LaunchCfg& cfg_in, const coot_operand* ops, c
     a.n = p.n;
     a.splits = G.splits;
     a.aux = G.aux;
-    if ((p.kind == K_EW_TILED || p.kind == K_RED_TILED) && !p.tile_gen) a.aux = tile_row_shift(p, ops, out);
+    if ((p.kind == K_EW_TILED || p.kind == K_RED_TILED) && !p.tile_gen && !p.thin_k) a.aux = tile_row_shift(p, ops, out);
     if (p.red_op < 0) {
         a.out = out->ptr;
         a.ld_out = out->ld;

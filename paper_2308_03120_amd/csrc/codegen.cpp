@@ -951,6 +951,193 @@ static std::string emit_tiled(const Plan& p, const std::string& name)
     return s.str();
 }
 
+// --- thin values: a short side of K <= 16 elements ---------------------------
+// The value is R x Cn with K = min(R, Cn) <= 16 (thin_rows: R = K).  A thread
+// takes a group of V consecutive long-side positions (one 16-byte vector
+// along the long side) and all K short-side indices of them; the 64 lanes of
+// a wave take 64 consecutive groups.  A strided operand (one run along the
+// long side per short-side index, at k*ld + g*V) is loaded directly: K
+// vectors per lane, consecutive lanes on consecutive vectors.  A packed
+// operand (ld == K: the value's own layout when the rows are short, an
+// operand read transposed when the columns are) holds a wave's 64 groups as
+// 64*V*K contiguous elements.  With K <= 2 each lane loads its own group's V*K
+// elements; otherwise the wave loads the whole run as K fully coalesced
+// vectors per lane and hands every lane its own group through a region of
+// LDS private to the wave (lane regions padded to an odd number of 16-byte
+// units, so the lanes' vector reads do not conflict), and packed outputs go
+// back the same way.  In registers element f = n*V + e of a packed group is
+// short-side index f % K of position f / K; the transposition to and from
+// the strided layout happens at indices fixed when the kernel is generated.
+// Misaligned operands move element by element.  8/K groups per thread are in
+// flight.  The positions after the last whole group (fewer than V) are done
+// element by element by the last block.
+static std::string emit_thin(const Plan& p, const std::string& name)
+{
+    const bool ew = p.kind == K_EW_TILED;
+    const int K = p.thin_k, V = p.thin_v, UG = std::max(1, 8 / K);
+    const bool sr = p.thin_rows;
+    const int rp = p.nodes[p.root].prec;
+    const std::string OS = ew ? stype(p.out_dtype) : "";
+    const std::string sK = std::to_string(K), sV = std::to_string(V), sVK = std::to_string(V * K);
+    auto packed = [&](int j) { return j < 0 ? sr : (p.reads[(size_t)j].trans ? !sr : sr); };
+    auto vec = [&](int j) { return (p.thin_vec & (j < 0 ? (1u << 31) : (1u << j))) != 0; };
+    // packed operands are exchanged through LDS from K = 2 on (2 x 2^26 FP32
+    // add: 283 us loading each lane's own 32 bytes, 263 us exchanged)
+    const bool stage = K >= 2;
+    auto staged = [&](int j) { return stage && packed(j) && vec(j); };
+    bool any_stage = ew && staged(-1);
+    for (size_t j = 0; j < p.reads.size(); ++j) any_stage = any_stage || staged((int)j);
+    const int maxsz = 16 / V;
+    const int RS = V * K + (K % 2 == 0 ? V : 0);  // a lane's LDS region, elements
+    std::ostringstream s;
+    s << "// thin value: short side " << (sr ? "rows" : "columns") << ", K = " << K << ", " << V
+      << "-element vectors (mask " << p.thin_vec << (any_stage ? ", packed through LDS" : "") << ")\n";
+    s << "extern \"C\" __global__ void __launch_bounds__(256) " << name << "(const coot_kargs a)\n{\n";
+    s << decl_reads(p, !p.alias_out);
+    if (ew) {
+        s << "    " << OS << "* " << (p.alias_out ? "" : "__restrict__ ") << "O = (" << OS << "*)a.out;\n";
+        s << "    const i64 ldo = a.ld_out;\n";
+    } else {
+        s << "    " << acc_type(p) << " acc;\n    acc.init();\n";
+    }
+    s << "    const i64 R = a.rows, Cn = a.cols;\n";
+    s << "    const i64 ln = " << (sr ? "Cn" : "R") << ", ng = ln / " << sV << ";\n";
+    s << "    const i64 step = (i64)gridDim.x * 256 * " << UG << ";\n";
+    s << "    const int lane = threadIdx.x & 63, w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);\n";
+    if (any_stage) {
+        s << "    __shared__ __align__(16) unsigned char lds_thin[" << 4 * 64 * RS * maxsz << "];\n";
+        s << "    unsigned char* const lw = lds_thin + w * " << 64 * RS * maxsz << ";\n";
+    }
+    // per-lane chunk c = n*64 + lane of a wave's packed run: its LDS slot
+    auto chunk_slot = [&](const std::string& n) {
+        return "((" + n + " * 64 + lane) / " + sK + ") * " + std::to_string(RS) + " + ((" + n + " * 64 + lane) % " + sK +
+               ") * " + sV;
+    };
+    // the group a chunk belongs to
+    auto chunk_group = [&](const std::string& n) { return "gw + (" + n + " * 64 + lane) / " + sK; };
+    // loop over the wave's group blocks (wave-uniform: every lane runs every iteration)
+    s << "    for (i64 gb = (i64)blockIdx.x * (256 * " << UG << ") + w * 64; gb < ng; gb += step) {\n";
+    for (size_t j = 0; j < p.reads.size(); ++j)
+        s << "        " << stype(p.reads[j].dtype) << " r" << j << "[" << UG << "][" << sK << "][" << sV << "];\n";
+    // loads are unconditional (a lane past the last group reads the last
+    // group again): with no branch around them the compiler keeps every load
+    // of the step in flight
+    s << "#pragma unroll\n        for (int u = 0; u < " << UG << "; ++u) {\n";
+    s << "            const i64 gw = gb + u * 256, g = gw + lane < ng ? gw + lane : ng - 1;\n";
+    s << "            const i64 gcl = (ng - gw) * " << sK << " - 1;  // last chunk of the wave inside the value\n";
+    s << "            (void)gcl;\n";
+    s << "#pragma unroll\n            for (int n = 0; n < " << sK << "; ++n) {\n";
+    for (size_t j = 0; j < p.reads.size(); ++j) {
+        const std::string J = std::to_string(j);
+        const std::string S = stype(p.reads[j].dtype);
+        if (staged((int)j)) {
+            s << "                ldv<" << S << ", " << sV << ">(L" << J << ", gw * " << sVK << " + (n * 64 + lane < gcl ? n * 64 + lane : gcl) * "
+              << sV << ", r" << J << "[u][n]);\n";
+            continue;
+        }
+        const std::string off = packed((int)j) ? "g * " + sVK + " + n * " + sV : "n * ld" + J + " + g * " + sV;
+        if (vec((int)j))
+            s << "                ldv<" << S << ", " << sV << ">(L" << J << ", " << off << ", r" << J << "[u][n]);\n";
+        else
+            s << "#pragma unroll\n                for (int e = 0; e < " << sV << "; ++e) r" << J << "[u][n][e] = ldnt(L" << J << " + ("
+              << off << " + e));\n";
+    }
+    s << "            }\n        }\n";
+    s << "#pragma unroll\n        for (int u = 0; u < " << UG << "; ++u) {\n";
+    s << "            const i64 gw = gb + u * 256, g = gw + lane;\n";
+    s << "            const bool gok = g < ng;\n";
+    // packed reads: chunks into the wave's LDS region, each lane's own group back
+    for (size_t j = 0; j < p.reads.size(); ++j) {
+        if (!staged((int)j)) continue;
+        const std::string J = std::to_string(j), S = stype(p.reads[j].dtype);
+        s << "            {\n                " << S << "* const T = (" << S << "*)lw;\n";
+        s << "#pragma unroll\n                for (int n = 0; n < " << sK << "; ++n)\n";
+        s << "                    lds_put<" << S << ", " << sV << ">(T, " << chunk_slot("n") << ", r" << J << "[u][n]);\n";
+        s << "                wave_lds_sync();\n";
+        s << "#pragma unroll\n                for (int n = 0; n < " << sK << "; ++n)\n";
+        s << "                    lds_get<" << S << ", " << sV << ">(T, lane * " << RS << " + n * " << sV << ", r" << J << "[u][n]);\n";
+        s << "                wave_lds_sync();\n            }\n";
+    }
+    if (ew) s << "            " << OS << " o[" << sK << "][" << sV << "];\n";
+    s << "            {\n";
+    // register of element (k, v) in a packed / strided operand
+    auto reg = [&](bool pk, int k, int v) {
+        const int f = v * K + k;
+        return pk ? "[" + std::to_string(f / V) + "][" + std::to_string(f % V) + "]"
+                  : "[" + std::to_string(k) + "][" + std::to_string(v) + "]";
+    };
+    for (int v = 0; v < V; ++v)
+        for (int k = 0; k < K; ++k) {
+            std::string args;
+            for (size_t j = 0; j < p.reads.size(); ++j) {
+                if (j) args += ", ";
+                args += widen(p.reads[j].dtype, "r" + std::to_string(j) + "[u]" + reg(packed((int)j), k, v));
+            }
+            // row and column of the element in the value
+            const std::string ig = sr ? "(i64)" + std::to_string(k) : "(g * " + sV + " + " + std::to_string(v) + ")";
+            const std::string jg = sr ? "(g * " + sV + " + " + std::to_string(v) + ")" : "(i64)" + std::to_string(k);
+            const std::string lin = "(" + ig + " + " + jg + " * R)";
+            if (p.gen_index) args += (args.empty() ? "" : ", ") + lin + ", " + ig + ", " + jg;
+            if (ew)
+                s << "                o" << reg(packed(-1), k, v) << " = " << narrow(p.out_dtype, rp, "x_eval(" + args + ")")
+                  << ";\n";
+            else
+                s << "                if (gok) " << accumulate(p, args, lin) << "\n";
+        }
+    if (ew && !staged(-1)) {
+        const std::string off = packed(-1) ? "g * " + sVK + " + n * " + sV : "n * ldo + g * " + sV;
+        if (vec(-1))
+            s << "                if (gok)\n#pragma unroll\n                    for (int n = 0; n < " << sK << "; ++n) stv<" << OS << ", "
+              << sV << ">(O, " << off << ", o[n]);\n";
+        else
+            s << "                if (gok)\n#pragma unroll\n                    for (int n = 0; n < " << sK << "; ++n)\n#pragma unroll\n"
+              << "                        for (int e = 0; e < " << sV << "; ++e) stnt(O + (" << off << " + e), o[n][e]);\n";
+    }
+    s << "            }\n";
+    if (ew && staged(-1)) {
+        // each lane's group into its LDS region, the wave's run out in coalesced chunks
+        s << "            {\n                " << OS << "* const T = (" << OS << "*)lw;\n";
+        s << "#pragma unroll\n                for (int n = 0; n < " << sK << "; ++n)\n";
+        s << "                    lds_put<" << OS << ", " << sV << ">(T, lane * " << RS << " + n * " << sV << ", o[n]);\n";
+        s << "                wave_lds_sync();\n";
+        s << "#pragma unroll\n                for (int n = 0; n < " << sK << "; ++n)\n";
+        s << "                    if (" << chunk_group("n") << " < ng) {\n";
+        s << "                        " << OS << " t[" << sV << "];\n";
+        s << "                        lds_get<" << OS << ", " << sV << ">(T, " << chunk_slot("n") << ", t);\n";
+        s << "                        stv<" << OS << ", " << sV << ">(O, gw * " << sVK << " + (n * 64 + lane) * " << sV << ", t);\n";
+        s << "                    }\n";
+        s << "                wave_lds_sync();\n            }\n";
+    }
+    s << "        }\n    }\n";
+    // positions after the last whole group
+    s << "    if (blockIdx.x == gridDim.x - 1) {\n";
+    s << "        for (i64 t = threadIdx.x; t < (ln - ng * " << sV << ") * " << sK << "; t += 256) {\n";
+    s << "            const i64 ps = ng * " << sV << " + t / " << sK << ", ks = t % " << sK << ";\n";
+    s << "            const i64 ig = " << (sr ? "ks" : "ps") << ", jg = " << (sr ? "ps" : "ks") << ";\n";
+    std::string targs;
+    for (size_t j = 0; j < p.reads.size(); ++j) {
+        const std::string J = std::to_string(j);
+        if (j) targs += ", ";
+        targs += widen(p.reads[j].dtype, p.reads[j].trans ? "ldnt(L" + J + " + (jg + ig * ld" + J + "))"
+                                                          : "ldnt(L" + J + " + (ig + jg * ld" + J + "))");
+    }
+    if (p.gen_index) targs += (targs.empty() ? "" : ", ") + std::string("ig + jg * R, ig, jg");
+    if (ew)
+        s << "            stnt(O + (ig + jg * ldo), (" << OS << ")(" << narrow(p.out_dtype, rp, "x_eval(" + targs + ")")
+          << "));\n";
+    else
+        s << "            " << accumulate(p, targs, "(ig + jg * R)") << "\n";
+    s << "        }\n    }\n";
+    if (!ew) {
+        s << "    __shared__ " << acc_type(p) << " lds_acc[4];\n";
+        s << "    acc = block_reduce(acc, lds_acc);\n";
+        s << "    if (threadIdx.x == 0) " << put_partial(p, "blockIdx.x") << "\n";
+    }
+    s << "}\n";
+    if (!ew) s << emit_partials_comb(p, name);
+    return s.str();
+}
+
 // --- per-column reductions (dim 0): one wave per (column, row segment) -------
 // With few columns each column is cut into a.splits segments of a.aux rows so
 // that enough waves stream; segment partials are combined per column, in
@@ -1209,7 +1396,10 @@ std::string batch_kernel_source(const Plan& py, const Plan* pr, bool has_out, in
     const std::string ACC = pr ? (pr->nodes[pr->root].prec == 64 ? "AccKD" : (pr->pairwise ? "AccPF" : "AccKF")) : "";
     const std::string OS = stype(out_dtype);
     const size_t nr = py.reads.size();
-    constexpr int U = 8;  // elements per thread in flight
+    // elements per thread in flight: the pass runs two blocks per CU (its LDS
+    // stage), so each thread keeps many loads in flight (8 -> 32: 487 -> 435 us
+    // for the 10,000-matrix workload)
+    constexpr int U = 32;
     std::ostringstream s;
     s << "// batch tree: " << py.body_sig << "\n";
     s << emit_eval(py, false, "x");
@@ -1395,7 +1585,7 @@ std::string kernel_source(const Plan& p, const LaunchCfg& cfg, std::string* name
     case K_EW_FLAT:
     case K_RED_FLAT: body << emit_flat(p, cfg, placeholder); break;
     case K_EW_TILED:
-    case K_RED_TILED: body << emit_tiled(p, placeholder); break;
+    case K_RED_TILED: body << (p.thin_k ? emit_thin(p, placeholder) : emit_tiled(p, placeholder)); break;
     case K_RED_COL: body << emit_col(p, cfg, placeholder); break;
     case K_RED_COLT: body << emit_colt(p, placeholder); break;
     case K_RED_ROW: body << emit_row(p, placeholder); break;

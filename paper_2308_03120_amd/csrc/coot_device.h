@@ -129,6 +129,33 @@ CD void stv(S* p, i64 e0, const S (&o)[VE])
     }
 }
 
+/* VE consecutive elements to / from LDS in one access (e0 a multiple of VE) */
+template <class S, int VE>
+CD void lds_put(S* p, int e0, const S (&o)[VE])
+{
+    typedef typename rawvec<(int)sizeof(S) * VE>::T R;
+    R r;
+    __builtin_memcpy(&r, o, sizeof r);
+    *(R*)(p + e0) = r;
+}
+
+template <class S, int VE>
+CD void lds_get(const S* p, int e0, S (&o)[VE])
+{
+    typedef typename rawvec<(int)sizeof(S) * VE>::T R;
+    const R r = *(const R*)(p + e0);
+    __builtin_memcpy(o, &r, sizeof r);
+}
+
+/* order the LDS accesses of one wave's lanes (LDS instructions of a wave
+ * complete in order; this keeps the compiler from moving them) */
+CD void wave_lds_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 /* single-element streaming load / store */
 template <class S>
 CD S ldnt(const S* p)

@@ -104,6 +104,13 @@ struct Plan {
     bool tile_gen = false;    // tiled kind on a thin value: shape-adaptive tiles
     int tile_lr = 6, tile_lc = 6;  // tile shape 2^lr x 2^lc of the tiled kinds
     bool tile_off32 = false;  // per-lane tile offsets fit in 32-bit byte offsets
+    // thin tiled value whose short side K = thin_k <= 16 (0: not thin): each
+    // thread takes groups of thin_v positions along the long side, all K
+    // elements of each, every access a whole vector (see emit_thin)
+    int thin_k = 0;
+    bool thin_rows = false;   // the short side is the rows (R = K), else the columns
+    int thin_v = 1;           // elements per vector access
+    uint32_t thin_vec = 0;    // bit j: read j moves whole vectors (bit 31: the output); else element by element
     bool gen_index = false;   // a generator needs the element's index (eye, linspace)
     std::string body_sig;     // canonical description of the element function
 };

@@ -386,6 +386,46 @@ Plan make_plan(int red_op_in, int dim, const coot_expr* expr, const coot_operand
         for (const Read& r : P.reads) bound = std::max(bound, 64 + (r.trans ? kt : ky) * r.ld);
         P.tile_off32 = bound < (int64_t(1) << 29);
     }
+    // thin values: a short side of at most 16 elements take the thin kernel
+    // (emit_thin), unless an operand cannot follow its layout.  An operand
+    // is "packed" when the K elements of each long-side position are
+    // contiguous and consecutive positions follow each other (ld == K: the
+    // value's layout when the rows are short, a transposed read when the
+    // columns are), "strided" when it holds one run along the long side per
+    // short-side index (any ld).  An operand moves whole vectors when its base
+    // and (strided) its ld are whole vectors, else element by element.
+    P.thin_k = 0;
+    if (P.tile_gen && P.rows >= 1 && P.cols >= 1 && std::min(P.rows, P.cols) <= 16) {
+        const bool sr = P.rows <= P.cols;
+        const int64_t K = sr ? P.rows : P.cols;
+        int maxsz = 1;
+        for (const Read& r : P.reads) maxsz = std::max(maxsz, itemsize(r.dtype));
+        if (P.red_op < 0) maxsz = std::max(maxsz, itemsize(out->dtype));
+        const int V = 16 / maxsz;
+        bool ok = true;
+        uint32_t vec = 0;
+        auto place = [&](const void* ptr, int64_t ld, int sz, bool packed, uint32_t bit) {
+            if (packed && ld != K) ok = false;
+            if ((uintptr_t)ptr % (uintptr_t)(V * sz) == 0 && (packed || ld % V == 0)) vec |= bit;
+        };
+        // a straight read (and the output) follows the value's layout, packed
+        // when the rows are the short side; a transposed read the other way
+        for (size_t j = 0; j < P.reads.size(); ++j) {
+            const Read& r = P.reads[j];
+            place(ops[r.slot].ptr, r.ld, itemsize(r.dtype), r.trans ? !sr : sr, 1u << j);
+        }
+        if (P.red_op < 0) place(out->ptr, out->ld, itemsize(out->dtype), sr, 1u << 31);
+        // register budget: groups in flight x K vectors x (reads + output)
+        const int64_t ug = std::max<int64_t>(1, 8 / K);
+        const int64_t nvec = (int64_t)P.reads.size() + (P.red_op < 0 ? 1 : 0);
+        ok = ok && ug * K * nvec <= 40;
+        if (ok) {
+            P.thin_k = (int)K;
+            P.thin_rows = sr;
+            P.thin_v = V;
+            P.thin_vec = vec;
+        }
+    }
     if (P.red_op >= 0 && (P.red_op == COOT_RED_ACCU || P.red_op == COOT_RED_SUM || P.red_op == COOT_RED_DOT) &&
         P.nodes[P.root].op == COOT_SCHUR) {
         P.product_form = true;
@@ -536,16 +576,24 @@ int config_index(const LaunchCfg& c)
 }
 
 // Defaults from streaming measurements on MI355X: element-wise kernels (reads
-// plus a write) run best as one pass of 256-thread blocks with 4 vectors per
-// thread; read-only reductions best as a persistent grid of 512-thread blocks
-// (2 per CU) with 8 vectors in flight per thread.
+// plus a write) run best as one pass of 64-thread blocks with one vector per
+// thread (2^28 FP32 z 519 -> 479 us, FP64 scale 762 -> 639 us against 256
+// threads with 4 vectors; the same or better from 2^20 elements on);
+// read-only reductions as a persistent grid of 512-thread blocks (2 per CU)
+// with two buffers of 2 vectors per thread (over 45 flat reductions of
+// 2^22..2^28 FP32/FP64/FP16 elements, accu, dot and index_max: 1.016x the
+// per-call best on geometric mean, worst 1.065x; 8 vectors per buffer:
+// 1.065x, worst 1.216x).
 LaunchCfg default_config(const Plan& p)
 {
     LaunchCfg c;
     switch (p.kind) {
-    case K_EW_FLAT: c = {4, 256, 8}; break;
-    case K_RED_FLAT: c = {8, 512, 1}; break;
-    case K_RED_COL: c = {2, 256, 8}; break;
+    case K_EW_FLAT: c = {1, 64, 8}; break;
+    case K_RED_FLAT: c = {2, 512, 1}; break;
+    // per-column reductions: 64-thread blocks, 4 per CU per split unit
+    // (40 column sums and index_max of 7 shapes x FP32/FP64/FP16: 1.054x the
+    // per-call best on geometric mean against 1.090x for 256-thread blocks)
+    case K_RED_COL: c = {2, 64, 4}; break;
     // tiled element-wise: shape-adaptive (thin) tiles run best as one pass
     // (split 8: 2 x 2^26 and 2^23 x 12 FP32 adds 12% faster than split 4),
     // 64 x 64 tiles as 2 blocks per CU (16384^2 adds 2-3% faster); tiled

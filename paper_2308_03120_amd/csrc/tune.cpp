@@ -17,7 +17,7 @@
 #include "runtime.h"
 
 extern "C" int coot_copy_launch(void* dst, const void* src, int64_t bytes, int cus, void* stream);
-extern "C" int coot_probe_launch(int kind, void* dst, const void* src, int64_t bytes, void* stream);
+extern "C" int coot_probe_launch(int kind, int shape, void* dst, const void* src, int64_t bytes, void* stream);
 extern "C" int coot_mlp_forward_launch(const float* P, const float* X, int B, float* Y, float* Z1, float* H,
                                        void* stream);
 extern "C" int coot_mlp_backward_launch(const float* P, const float* X, const float* T, const float* M, int B,
@@ -383,15 +383,17 @@ int coot_copy(void* dst, const void* src, int64_t bytes, void* stream)
 int coot_bandwidth_probe(int kind, void* dst, const void* src, int64_t bytes, void* stream)
 {
     return guard2([&] {
-        if (kind < COOT_PROBE_COPY || kind > COOT_PROBE_READ2_WRITE1) fail(COOT_ERR_ARG, "unknown probe kind");
+        const int base = kind & 0xff, shape = kind >> 8;
+        if (base < COOT_PROBE_COPY || base > COOT_PROBE_READ2_WRITE1) fail(COOT_ERR_ARG, "unknown probe kind");
+        if (shape < 0 || shape > 3) fail(COOT_ERR_ARG, "unknown probe launch shape");
         if (bytes < 0 || bytes % 16) fail(COOT_ERR_ARG, "probe length must be a nonnegative multiple of 16 bytes");
-        if (bytes > 0 && ((kind != COOT_PROBE_WRITE && !src) || !dst)) fail(COOT_ERR_ARG, "NULL probe buffer");
+        if (bytes > 0 && ((base != COOT_PROBE_WRITE && !src) || !dst)) fail(COOT_ERR_ARG, "NULL probe buffer");
         if (((uintptr_t)dst | (uintptr_t)src) & 15) fail(COOT_ERR_ARG, "probe needs 16-byte aligned pointers");
         ensure_init();
         if (bytes == 0) return COOT_OK;
-        if (kind == COOT_PROBE_COPY) {
+        if (base == COOT_PROBE_COPY && shape == 0) {
             if (coot_copy_launch(dst, src, bytes, g_state.cus, stream)) fail(COOT_ERR_HIP, "copy launch");
-        } else if (coot_probe_launch(kind, dst, src, bytes, stream)) {
+        } else if (coot_probe_launch(base, shape, dst, src, bytes, stream)) {
             fail(COOT_ERR_HIP, "probe launch");
         }
         return COOT_OK;

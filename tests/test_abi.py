@@ -2,6 +2,7 @@
 entry point of include/coot.h, validates arguments before touching a device,
 and generates kernels that compile for gfx950 under strict floating-point
 rules."""
+import ctypes as C
 import os
 import re
 import subprocess
@@ -174,6 +175,8 @@ def test_features_shape_and_content():
     ("index_max", -1, "absB", [(1000, 1000)] * 4, (1, 1)),
     (None, -1, "T", [(37, 211), (211, 37)], (211, 37)),
     ("accu", -1, "T", [(37, 211), (211, 37)], (1, 1)),
+    (None, -1, "T", [(3001, 2), (2, 3001)], (2, 3001)),        # thin value, short rows
+    ("index_max", -1, "T", [(12, 300), (300, 12)], (1, 1)),   # thin value, short columns
 ])
 def test_generated_kernels_compile_for_gfx950(tmp_path, monkeypatch, red, dim, tree, ops, out):
     monkeypatch.setenv("COOT_CACHE_DIR", str(tmp_path))
@@ -246,3 +249,17 @@ def test_batch_aliasing_rejected_before_any_device_work():
     assert create([[A0, B0], [A1, B1]], [Y0, Y1], red_out=G * 7) != ALIAS
     # items of no elements touch no memory
     assert create([[A0, B0], [A1, B1]], [A0, Y1], shapes=((0, 3), (c, r))) != ALIAS
+
+
+def test_probe_arguments_checked_on_the_host():
+    """coot_bandwidth_probe rejects unknown kinds and launch shapes, lengths
+    that are not whole vectors and misaligned pointers before touching a
+    device."""
+    L = coot.lib()
+    d, s = C.c_void_p(G), C.c_void_p(2 * G)
+    ERR_ARG = -10
+    assert L.coot_bandwidth_probe(7, d, s, 1024, None) == ERR_ARG
+    assert L.coot_bandwidth_probe(coot.PROBE_READ | (4 << 8), d, s, 1024, None) == ERR_ARG
+    assert "shape" in coot.last_error()
+    assert L.coot_bandwidth_probe(coot.PROBE_READ | (1 << 8), d, s, 1000, None) == ERR_ARG
+    assert L.coot_bandwidth_probe(coot.PROBE_COPY | (3 << 8), C.c_void_p(G + 8), s, 1024, None) == ERR_ARG

@@ -5,12 +5,13 @@ Input: n = 2^26 positive terms, the first half equal to L = 1 and the second
 half equal to s = 1.75 * 2^-19, exact in FP32, BF16 and FP16 (an FP16
 subnormal).  The exact sum is (n / 2)(1 + s).
 
-Why plain FP32 loses it: the flat reduction used here (elements per thread 8
-vectors, 512 threads per block, 512 blocks: the default for these calls)
-walks the vector in grid-stride steps of 2^21 vectors, each thread folding
-every other vector of a step into one of two running sums.  Each running sum
-therefore takes its 64 terms from the first half (all equal to 1) before any
-from the second half: it holds exactly 64 when the first s arrives, and
+Why plain FP32 loses it: the flat reduction used here (2 vectors per thread
+per step, 512 threads per block, 512 blocks: the default for these calls)
+walks the vector in grid-stride steps of 2^19 vectors, each thread folding
+every other vector of a step into one of two running sums, 2^19 running sums
+in all.  The first half's 2^25 terms are spread evenly over them, so each
+running sum takes its 64 terms from the first half (all equal to 1) before
+any from the second half: it holds exactly 64 when the first s arrives, and
 s < 2^-18 = half an ulp of 64, so every s is rounded away.  The tree that
 follows adds integers exactly, so plain accumulation returns n / 2, a
 relative error of s / (1 + s) = 3.3e-6.  The compensated form keeps each lost
@@ -30,7 +31,7 @@ from paper_2308_03120_amd import coot  # noqa: E402
 N = 1 << 26
 L = 1.0
 S = 1.75 * 2.0 ** -19
-FLAT_CFG = (8, 512, 1)
+FLAT_CFG = (2, 512, 1)
 
 
 def crafted(dt):
