@@ -373,9 +373,18 @@ Plan make_plan(int red_op_in, int dim, const coot_expr* expr, const coot_operand
         else
             P.kind = K_RED_ROW;
     }
-    P.tile_gen = (P.kind == K_EW_TILED || P.kind == K_RED_TILED) && (P.rows < 64 || P.cols < 64);
+    // Thin values, and values with no transposed read (strided views, eye),
+    // take the shape-adaptive tiles.  Without a transposed operand nothing
+    // needs a square tile: tall tiles (up to 4096 rows of one column) walk
+    // down each column, where 64 x 64 tiles touch 64 columns per wave
+    P.tile_gen = (P.kind == K_EW_TILED || P.kind == K_RED_TILED) && (P.rows < 64 || P.cols < 64 || !any_trans);
     if (P.tile_gen) {
-        coot_tile_shape(P.rows, P.cols, &P.tile_lr, &P.tile_lc);
+        if (any_trans) {
+            coot_tile_shape(P.rows, P.cols, &P.tile_lr, &P.tile_lc);
+        } else {
+            P.tile_lr = std::min(coot_lg2ceil(P.rows), 12);
+            P.tile_lc = std::min(coot_lg2ceil(P.cols), 12 - P.tile_lr);
+        }
         // per-lane offset bounds (elements of at most 8 bytes) of the tile
         // mappings: value order k = lines per step beyond the first, a
         // transposed read either order

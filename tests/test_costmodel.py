@@ -118,3 +118,13 @@ def test_stamp_follows_the_kernels():
 
     a = coot.kernel_stamp()
     assert a == coot.kernel_stamp() and a[0] == 1 and a[1] != 0
+
+
+def test_committed_weights_match_the_kernels():
+    """The committed model was trained on the kernels this library generates:
+    its feature schema and kernel stamp equal the library's, so
+    coot_set_tuning accepts it (a model timed on other kernels is refused)."""
+    from paper_2308_03120_amd import coot
+
+    _, schema, stamp = read_weights(WEIGHTS)
+    assert (schema, stamp) == coot.kernel_stamp()

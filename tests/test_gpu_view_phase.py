@@ -1,9 +1,11 @@
-"""Square-tiled kernels on views that start inside a 128-byte line.  The
-64 x 64 tile grid of the per-call kernels starts as many rows above the value
-as the output's columns start into a line (a launch argument), so its first
-and last tile rows are partial.  Element-wise results must match the oracle
-bit for bit, nothing outside the output view may change, and reductions must
-keep the plain linear index (row + column * rows) of the value."""
+"""Tiled kernels on views that start inside a 128-byte line.  Trees that read
+an operand transposed use 64 x 64 tiles whose grid starts as many rows above
+the value as the output's columns start into a line (a launch argument), so
+its first and last tile rows are partial; trees with straight reads only use
+tall tiles that walk down each column.  Element-wise results must match the
+oracle bit for bit, nothing outside the output view may change, and
+reductions must keep the plain linear index (row + column * rows) of the
+value."""
 import numpy as np
 import pytest
 
@@ -79,3 +81,35 @@ def test_reductions_over_offset_views(dt, off):
         assert coot.reduce("index_max", x, [dM]).item() == i + j * R, (dt, off, i, j)
         assert coot.reduce("index_max", x % y, [dM, dB]).item() == \
             oracle.reduce("index_max", (x % y).postfix(), [Am, B], mode="emu")[1][0]
+
+
+@pytest.mark.parametrize("dt", ["f32", "f64", "bf16"])
+def test_tall_tiles_over_long_strided_views(dt):
+    """Trees with no transposed read over strided views take tall tiles (up to
+    4096 rows of one column): a 4097 x 70 view (a full and a one-row tile per
+    column) starting inside a line, written into another offset view; the
+    result bit-exact, nothing outside the view written, and extrema planted
+    on either side of the 4096-row tile boundary keep their linear index."""
+    r, c, ld = 4097, 70, 4101
+    g = np.random.default_rng(4097 + list(ODT).index(dt))
+    DA = g.uniform(-2, 2, (r, c))
+    A = synth.Mat(synth.store(np.asfortranarray(DA), dt), dt)
+    B = mat(g, (r, c), dt)
+    dA, dB = dev(A, ld=ld, offset=3), dev(B, ld=ld + 2, offset=1)
+    odt = ODT[dt]
+    buf = torch.full((c * ld + 6,), float("nan"), dtype=TORCH_DT[odt], device="cuda")
+    Y = buf[5:5 + c * ld].view(c, ld)[:, :r].t()
+    tree = x * 2.0 - y
+    coot.eval(tree, [dA, dB], Y)
+    torch.cuda.synchronize()
+    assert same(host(Y), oracle.evaluate(tree.postfix(), [A, B], "emu")), dt
+    full = buf[5:5 + c * ld].view(c, ld)
+    assert torch.isnan(full[:, r:]).all() and torch.isnan(buf[:5]).all()
+    o, _, s = oracle.reduce("accu", (x % y).postfix(), [A, B])
+    got = coot.reduce("accu", x % y, [dA, dB]).item()
+    assert abs(got - o[0]) <= (1e-6 if dt != "f64" else 1e-13) * s[0]
+    for (i, j) in ((4095, 3), (4096, 3), (0, 69), (4096, 69)):
+        M = DA.copy()
+        M[i, j] = 50.0
+        dM = dev(synth.Mat(synth.store(np.asfortranarray(M), dt), dt), ld=ld, offset=3)
+        assert coot.reduce("index_max", x, [dM]).item() == i + j * r, (dt, i, j)
