@@ -1382,7 +1382,10 @@ int64_t batch_unit_elems(const Plan& py)
     int bytes = 0;
     for (const Read& r : py.reads)
         if (r.trans) bytes += itemsize(r.dtype);
-    int64_t e = 16384;
+    // 12288 FP32 elements: a 50 KB stage, three blocks per CU (16384: 68 KB,
+    // two blocks; 10,000-matrix workload 425 -> 399 us with 16 elements in
+    // flight per thread)
+    int64_t e = 12288;
     while (bytes > 0 && e * bytes > COOT_BATCH_LDS_BYTES) e >>= 1;
     return e;
 }
@@ -1396,10 +1399,11 @@ std::string batch_kernel_source(const Plan& py, const Plan* pr, bool has_out, in
     const std::string ACC = pr ? (pr->nodes[pr->root].prec == 64 ? "AccKD" : (pr->pairwise ? "AccPF" : "AccKF")) : "";
     const std::string OS = stype(out_dtype);
     const size_t nr = py.reads.size();
-    // elements per thread in flight: the pass runs two blocks per CU (its LDS
-    // stage), so each thread keeps many loads in flight (8 -> 32: 487 -> 435 us
-    // for the 10,000-matrix workload)
-    constexpr int U = 32;
+    // elements per thread in flight: the pass runs a few blocks per CU (its
+    // LDS stage), so each thread keeps many loads in flight (8 -> 16: 487 ->
+    // 435 us with the 68 KB stage; with the 50 KB stage 16 and 24 equal,
+    // 32 slower, 48 much slower)
+    constexpr int U = 16;
     std::ostringstream s;
     s << "// batch tree: " << py.body_sig << "\n";
     s << emit_eval(py, false, "x");
