@@ -369,21 +369,6 @@ static void fill_reads(const Plan& p, const coot_operand* ops, coot_kargs& a)
 // misaligned and 410 us with neither); a reduction follows the majority of
 // its reads in the value's order.  Operands whose column stride is not a
 // multiple of 128 bytes have no common phase and do not vote.
-static int64_t tile_row_shift(const Plan& p, const coot_operand* ops, const coot_operand* out)
-{
-    int votes[64] = {0};
-    auto vote = [&](const void* ptr, int64_t ld, int sz, int w) {
-        if (!ptr || sz <= 0 || (ld * sz) % 128 != 0 || (uintptr_t)ptr % (uintptr_t)sz) return;
-        votes[(int)(((uintptr_t)ptr % 128) / (uintptr_t)sz)] += w;  // < 64 elements of >= 2 bytes
-    };
-    for (const Read& r : p.reads)
-        if (!r.trans) vote(ops[r.slot].ptr, r.ld, itemsize(r.dtype), 2);
-    if (p.red_op < 0) vote(out->ptr, out->ld, itemsize(out->dtype), 1 << 20);
-    int best = 0;
-    for (int e = 1; e < 64; ++e)
-        if (votes[e] > votes[best]) best = e;
-    return best;
-}
 
 // One fused launch (two for split per-row reductions) of a plan.
 // kernels by plan signature: a repeated call skips source generation
@@ -394,7 +379,7 @@ static std::string sig_key(const Plan& p, const LaunchCfg& c)
 {
     return std::to_string(p.kind) + "|" + std::to_string(p.ve) + "|" + std::to_string(c.ept) + "|" +
            std::to_string(p.out_dtype) + "|" + std::to_string(p.red_op) + "|" + std::to_string(p.pairwise) + "|" +
-           std::to_string(p.alias_out) + "|" + std::to_string(p.tile_gen) + std::to_string(p.tile_off32) +
+           std::to_string(p.alias_out) + "|" + std::to_string(p.tile_gen) + std::to_string(p.tile_off32) + std::to_string(p.tile_tall) + std::to_string(p.tile_v4) +
            std::to_string(p.tile_lr) + "," + std::to_string(p.tile_lc) + "|t" + std::to_string(p.thin_k) +
            (p.thin_rows ? "r" : "c") + std::to_string(p.thin_v) + "v" + std::to_string(p.thin_vec) + "|" + p.body_sig;
 }
@@ -445,7 +430,10 @@ void run_plan(const Plan& p, const LaunchCfg& cfg_in, const coot_operand* ops, c
     a.n = p.n;
     a.splits = G.splits;
     a.aux = G.aux;
-    if ((p.kind == K_EW_TILED || p.kind == K_RED_TILED) && !p.tile_gen && !p.thin_k) a.aux = tile_row_shift(p, ops, out);
+    if ((p.kind == K_EW_TILED || p.kind == K_RED_TILED) && !p.thin_k) {
+        if (!p.tile_gen) a.aux = tile_row_shift(p, ops, out);
+        else if (p.tile_tall) a.aux = p.tile_sh;
+    }
     if (p.red_op < 0) {
         a.out = out->ptr;
         a.ld_out = out->ld;

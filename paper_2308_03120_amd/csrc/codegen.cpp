@@ -759,6 +759,179 @@ static std::string lane_addr(const std::string& ptr, const std::string& cond, co
     return ptr + " + (" + cond + " ? " + off + " : 0)";
 }
 
+// --- tall tiles ---------------------------------------------------------
+// Trees with straight reads only (views, index generators) and tile rows
+// 2^lr >= 64 (p.tile_tall).  The grid starts sh = a.aux rows above the value
+// (0 <= sh < 64, chosen on the host so the output's column segments begin on
+// 128-byte lines); tile (ti, tj) covers rows (ti << lr) - sh + [0, 2^lr) and
+// columns (tj << lc) + [0, 2^lc).  Step m = w + 4*kk of a wave covers tile
+// elements 64*m + [0, 64) in column order: with 64*w split off, the step's
+// row and column offsets are constants of kk (no walker).  A tile wholly
+// inside the value has no per-step tests; a partial one clamps each lane's
+// row and the step's column into the value for its loads (so every load is
+// unconditional) and tests them before it stores or accumulates.
+static std::string tall_origin(const std::string& in, const Plan& p, const std::string& ti, const std::string& tj,
+                               const std::string& rn, const std::string& cn)
+{
+    return in + "const i64 " + rn + " = ((i64)(" + ti + ") << " + std::to_string(p.tile_lr) + ") - sh, " + cn + " = (i64)(" +
+           tj + ") << " + std::to_string(p.tile_lc) + ";\n";
+}
+
+static std::string gen_wave_origin(const std::string& in, int lr)
+{
+    const int mask = (1 << lr) - 1;
+    return in + "const int wr = (64 * w) & " + std::to_string(mask) + ", wc = (64 * w) >> " + std::to_string(lr) + ";\n";
+}
+
+// step kk's row and column offsets from the wave origin (compile-time)
+static std::string gen_rc(int lr) { return "((256 * kk) & " + std::to_string((1 << lr) - 1) + ")"; }
+static std::string gen_cc(int lr) { return "((256 * kk) >> " + std::to_string(lr) + ")"; }
+
+// the steps guard when the tile holds fewer than 64 steps
+static std::string gen_step_guard(const Plan& p)
+{
+    const int nst = 1 << std::max(0, p.tile_lr + p.tile_lc - 6);
+    return nst >= 64 ? "" : "if (w + 4 * kk < " + std::to_string(nst) + ") ";
+}
+
+// guarded: a partial tile (rows clamped into [lo, hi) of the tile, the step's
+// column to the value's last)
+static std::string tall_prefetch(const Plan& p, const std::string& in, const std::string& ti, const std::string& tj,
+                                 const TileView& v, bool guarded)
+{
+    std::ostringstream o;
+    const int lr = p.tile_lr;
+    const std::string i2 = in + "    ", i3 = i2 + "    ";
+    o << in << (guarded ? "{ // partial tall tile\n" : "{ // whole tall tile: steps at fixed offsets\n");
+    o << tall_origin(i2, p, ti, tj, "pi0", "pj0");
+    o << gen_wave_origin(i2, lr);
+    if (guarded) {
+        o << i2 << "const int plo = pi0 < 0 ? (int)-pi0 : 0, phi = (int)(R - pi0 < (1 << " << lr << ") ? R - pi0 : (1 << " << lr
+          << "));\n";
+        o << i2 << "const i64 pcl = Cn - 1 - pj0;\n";
+    }
+    for (size_t j = 0; j < p.reads.size(); ++j) {
+        const std::string J = std::to_string(j), S = stype(p.reads[j].dtype);
+        o << i2 << "const " << S << "* a" << J << " = " << v.L(j) << " + (pi0 + pj0 * " << v.ld(j) << ");\n";
+    }
+    o << in << "#pragma unroll\n" << i2 << "for (int kk = 0; kk < 16; ++kk) " << gen_step_guard(p) << "{\n";
+    if (guarded) {
+        o << i3 << "const int t = wr + " << gen_rc(lr) << " + lane;\n";
+        o << i3 << "const u32 tcl = (u32)(t < plo ? plo : (t >= phi ? phi - 1 : t));\n";
+        o << i3 << "const i64 jl = wc + " << gen_cc(lr) << " < pcl ? wc + " << gen_cc(lr) << " : pcl;\n";
+    } else {
+        o << i3 << "const u32 tcl = (u32)(wr + " << gen_rc(lr) << " + lane);\n";
+        o << i3 << "const i64 jl = wc + " << gen_cc(lr) << ";\n";
+    }
+    for (size_t j = 0; j < p.reads.size(); ++j) {
+        const std::string J = std::to_string(j);
+        o << i3 << "pr" << J << "[kk] = " << widen(p.reads[j].dtype, "ldnt(at(a" + J + " + jl * " + v.ld(j) + ", tcl))") << ";\n";
+    }
+    o << i2 << "}\n" << in << "}\n";
+    return o.str();
+}
+
+template <class F>
+static std::string tall_compute(const Plan& p, const std::string& in, const std::string& ti, const std::string& tj,
+                                bool ew, const std::string& ldo, F per_elem, bool guarded)
+{
+    std::ostringstream s;
+    const int lr = p.tile_lr;
+    const std::string i2 = in + "    ", i3 = i2 + "    ";
+    s << in << "{\n";
+    s << tall_origin(i2, p, ti, tj, "i0", "j0");
+    s << gen_wave_origin(i2, lr);
+    if (guarded) {
+        s << i2 << "const int lo = i0 < 0 ? (int)-i0 : 0, hi = (int)(R - i0 < (1 << " << lr << ") ? R - i0 : (1 << " << lr << "));\n";
+        s << i2 << "const i64 ccn = Cn - j0;\n";
+    }
+    if (ew) s << i2 << stype(p.out_dtype) << "* po = O + (i0 + j0 * " << ldo << ");\n";
+    s << in << "#pragma unroll\n" << i2 << "for (int kk = 0; kk < 16; ++kk) " << gen_step_guard(p) << "{\n";
+    s << i3 << "const int t = wr + " << gen_rc(lr) << " + lane;\n";
+    s << i3 << "const i64 jl = wc + " << gen_cc(lr) << ";\n";
+    std::string in4 = i3;
+    if (guarded) {
+        s << i3 << "if (jl < ccn && t >= lo && t < hi) {\n";
+        in4 = i3 + "    ";
+    }
+    s << in4 << "const i64 ig = i0 + t, jg = j0 + jl;\n";
+    std::string args;
+    for (size_t j = 0; j < p.reads.size(); ++j) args += (j ? ", cr" : "cr") + std::to_string(j) + "[kk]";
+    if (p.gen_index) args += (args.empty() ? "" : ", ") + std::string("ig + jg * R, ig, jg");
+    s << per_elem(args, in4, ew ? "atw(po + jl * " + ldo + ", (u32)t)" : "");
+    if (guarded) s << i3 << "}\n";
+    s << i2 << "}\n" << in << "}\n";
+    return s.str();
+}
+
+// A whole tile with every operand's columns on 4-element boundaries
+// (p.tile_v4, 4096-element tiles): a lane moves 4 consecutive rows per
+// access, the wave 256 rows; its elements are 256*w + 4*lane + 1024*q
+// (q = 0..3) of the tile in column order, element 4*q + e of the lane's
+// registers being row e of access q.
+static std::string gen_v4_lane(const std::string& in, int lr)
+{
+    return in + "const int el = 256 * w + 4 * lane;\n" + in + "const i64 er = el & " + std::to_string((1 << lr) - 1) +
+           ", ec = el >> " + std::to_string(lr) + ";\n";
+}
+static std::string gen_rq(int lr) { return "((1024 * q) & " + std::to_string((1 << lr) - 1) + ")"; }
+static std::string gen_cq(int lr) { return "((1024 * q) >> " + std::to_string(lr) + ")"; }
+
+static std::string tall_prefetch_v4(const Plan& p, const std::string& in, const std::string& ti, const std::string& tj,
+                                    const TileView& v)
+{
+    std::ostringstream o;
+    const int lr = p.tile_lr;
+    const std::string i2 = in + "    ";
+    o << in << "{ // whole tall tile: 4 rows per access\n";
+    o << tall_origin(i2, p, ti, tj, "pi0", "pj0");
+    o << gen_v4_lane(i2, lr);
+    for (size_t j = 0; j < p.reads.size(); ++j) {
+        const std::string J = std::to_string(j), S = stype(p.reads[j].dtype);
+        o << i2 << "const " << S << "* a" << J << " = " << v.L(j) << " + (pi0 + pj0 * " << v.ld(j) << ");\n";
+        o << i2 << "const i64 v" << J << " = er + ec * " << v.ld(j) << ";\n";
+    }
+    o << in << "#pragma unroll\n" << i2 << "for (int q = 0; q < 4; ++q) {\n";
+    for (size_t j = 0; j < p.reads.size(); ++j) {
+        const std::string J = std::to_string(j), S = stype(p.reads[j].dtype);
+        o << i2 << "    { " << S << " t[4]; ldv<" << S << ", 4>(a" << J << " + (" << gen_rq(lr) << " + (i64)" << gen_cq(lr) << " * "
+          << v.ld(j) << "), v" << J << ", t);\n";
+        o << i2 << "#pragma unroll\n" << i2 << "      for (int e = 0; e < 4; ++e) pr" << J << "[4 * q + e] = "
+          << widen(p.reads[j].dtype, "t[e]") << "; }\n";
+    }
+    o << i2 << "}\n" << in << "}\n";
+    return o.str();
+}
+
+static std::string tall_compute_v4(const Plan& p, const std::string& in, const std::string& ti, const std::string& tj, bool ew,
+                                   const std::string& ldo)
+{
+    std::ostringstream s;
+    const int lr = p.tile_lr, rp = p.nodes[p.root].prec;
+    const std::string i2 = in + "    ", i3 = i2 + "    ";
+    const std::string OS = stype(p.out_dtype);
+    s << in << "{\n";
+    s << tall_origin(i2, p, ti, tj, "i0", "j0");
+    s << gen_v4_lane(i2, lr);
+    if (ew) s << i2 << OS << "* po = O + (i0 + j0 * " << ldo << ");\n" << i2 << "const i64 vo = er + ec * " << ldo << ";\n";
+    s << in << "#pragma unroll\n" << i2 << "for (int q = 0; q < 4; ++q) {\n";
+    s << i3 << "const i64 ib = i0 + er + " << gen_rq(lr) << ", jg = j0 + ec + " << gen_cq(lr) << ";\n";
+    if (ew) s << i3 << OS << " o[4];\n";
+    s << "#pragma unroll\n" << i3 << "for (int e = 0; e < 4; ++e) {\n";
+    s << i3 << "    const i64 ig = ib + e;\n";
+    std::string args;
+    for (size_t j = 0; j < p.reads.size(); ++j) args += (j ? ", cr" : "cr") + std::to_string(j) + "[4 * q + e]";
+    if (p.gen_index) args += (args.empty() ? "" : ", ") + std::string("ig + jg * R, ig, jg");
+    if (ew)
+        s << i3 << "    o[e] = (" << OS << ")(" << narrow(p.out_dtype, rp, "x_eval(" + args + ")") << ");\n";
+    else
+        s << i3 << "    " << accumulate(p, args, "(ig + jg * R)") << "\n";
+    s << i3 << "}\n";
+    if (ew) s << i3 << "stv<" << OS << ", 4>(po + (" << gen_rq(lr) << " + (i64)" << gen_cq(lr) << " * " << ldo << "), vo, o);\n";
+    s << i2 << "}\n" << in << "}\n";
+    return s.str();
+}
+
 static std::string tile_prefetch_gen(const Plan& p, const TilePlan& tp, const std::string& in, const std::string& ti,
                                      const std::string& tj, const TileView& v, const std::string& ldf, bool off32)
 {
@@ -908,18 +1081,33 @@ static std::string emit_tiled(const Plan& p, const std::string& name)
     s << "    const i64 R = a.rows, Cn = a.cols;\n";
     // tile shape, fixed per kernel: 2^lr x 2^lc
     s << "    const int lr = " << p.tile_lr << ", lc = " << p.tile_lc << ";\n";
-    // 64 x 64 tiles start sh rows above the value (0 <= sh < 64), so that
-    // the column segments of the reference operand begin on cache lines
-    if (!gen) s << "    const i64 sh = a.aux;\n";
+    // 64 x 64 and tall tiles start sh rows above the value (0 <= sh < 64),
+    // so that the column segments of the reference operand begin on cache
+    // lines
+    const bool tall = gen && p.tile_tall;
+    const bool shifted = !gen || tall;
+    if (shifted) s << "    const i64 sh = a.aux;\n";
     // tile counts fit in int for every matrix that fits in device memory
-    s << "    const int tr = (int)((R + " << (gen ? "" : "sh + ") << "(1 << lr) - 1) >> lr);\n";
+    if (tall)
+        s << "    const int tr = R > 0 ? (int)((R + sh + (1 << lr) - 1) >> lr) : 0;\n";
+    else
+        s << "    const int tr = (int)((R + " << (shifted ? "sh + " : "") << "(1 << lr) - 1) >> lr);\n";
     s << "    const int tc = tr > 0 ? (int)((Cn + (1 << lc) - 1) >> lc) : 0, trs = tr > 0 ? tr : 1;\n";
     s << "    const int gq = (int)gridDim.x / trs, gr = (int)gridDim.x % trs;\n";
     s << "    int ti = (int)blockIdx.x % trs, tj = (int)blockIdx.x / trs;\n";
     s << tile_regs(p, tp, "    ");
     TileView v{"R", "Cn", "lr", "lc", [](size_t j) { return "L" + std::to_string(j); },
                [](size_t j) { return "ld" + std::to_string(j); }};
+    // a tall tile wholly inside the value
+    auto tfull = [&](const std::string& a, const std::string& b) {
+        return "(((i64)(" + a + ") << lr) - sh >= 0 && ((i64)(" + a + ") << lr) - sh + (1 << lr) <= R && (((i64)(" + b +
+               ") + 1) << lc) <= Cn)";
+    };
     auto prefetch = [&](const std::string& in, const std::string& a, const std::string& b) {
+        if (tall)
+            return in + "{\n" + in + "if (" + tfull(a, b) + ")\n" +
+                   (p.tile_v4 ? tall_prefetch_v4(p, in + "    ", a, b, v) : tall_prefetch(p, in + "    ", a, b, v, false)) + in +
+                   "else\n" + tall_prefetch(p, in + "    ", a, b, v, true) + in + "}\n";
         return gen ? tile_prefetch_gen(p, tp, in, a, b, v, "ldnt", p.tile_off32) : tile_prefetch_sq(p, tp, in, a, b, v, "ldnt", true);
     };
     auto elem = [&](const std::string& args, const std::string& in, const std::string& addr) {
@@ -934,7 +1122,12 @@ static std::string emit_tiled(const Plan& p, const std::string& name)
     s << "        if (ni >= tr) { ni -= tr; ++nj; }\n";
     s << (gen ? tile_stage_gen(p, tp, "        ", "R", "Cn", "ti", "tj", "lr", "lc") : tile_stage_sq(p, tp, "        "));
     s << "        if (nj < tc)\n" << prefetch("            ", "ni", "nj");
-    if (gen)
+    if (tall)
+        s << "        if (" << tfull("ti", "tj") << ")\n"
+          << (p.tile_v4 ? tall_compute_v4(p, "        ", "ti", "tj", ew, "ldo") : tall_compute(p, "        ", "ti", "tj", ew, "ldo", elem, false))
+          << "        else\n"
+          << tall_compute(p, "        ", "ti", "tj", ew, "ldo", elem, true);
+    else if (gen)
         s << tile_compute_gen(p, tp, "        ", "ti", "tj", "R", "Cn", "lr", "lc", ew ? "O" : "", stype(p.out_dtype), "ldo",
                               p.tile_off32, elem);
     else

@@ -104,6 +104,13 @@ struct Plan {
     bool tile_gen = false;    // tiled kind on a thin value: shape-adaptive tiles
     int tile_lr = 6, tile_lc = 6;  // tile shape 2^lr x 2^lc of the tiled kinds
     bool tile_off32 = false;  // per-lane tile offsets fit in 32-bit byte offsets
+    // tall tiles: shape-adaptive tiles over straight reads only with tile rows
+    // 2^lr >= 64; the grid starts tile_sh rows above the value (a launch
+    // argument, so that the output's column segments begin on 128-byte lines)
+    bool tile_tall = false;
+    int tile_sh = 0;
+    bool tile_v4 = false;     // tall 4096-element tiles whose operands all start their columns (less
+                              // tile_sh rows) on 4-element boundaries: 4 consecutive rows per access
     // thin tiled value whose short side K = thin_k <= 16 (0: not thin): each
     // thread takes groups of thin_v positions along the long side, all K
     // elements of each, every access a whole vector (see emit_thin)
@@ -114,6 +121,11 @@ struct Plan {
     bool gen_index = false;   // a generator needs the element's index (eye, linspace)
     std::string body_sig;     // canonical description of the element function
 };
+
+// Rows (0..63) by which a tiled grid starts above the value: the phase, in
+// elements within a 128-byte line, shared by the output's columns (else by
+// most straight reads), so that their column segments begin on lines.
+int64_t tile_row_shift(const Plan& p, const coot_operand* ops, const coot_operand* out);
 
 // Validate and plan.  Throws Error.
 Plan make_plan(int red_op, int dim, const coot_expr* expr, const coot_operand* ops, int n_ops,

@@ -144,6 +144,22 @@ struct Info {
     int prec;
 };
 
+int64_t tile_row_shift(const Plan& p, const coot_operand* ops, const coot_operand* out)
+{
+    int votes[64] = {0};
+    auto vote = [&](const void* ptr, int64_t ld, int sz, int w) {
+        if (!ptr || sz <= 0 || (ld * sz) % 128 != 0 || (uintptr_t)ptr % (uintptr_t)sz) return;
+        votes[(int)(((uintptr_t)ptr % 128) / (uintptr_t)sz)] += w;  // < 64 elements of >= 2 bytes
+    };
+    for (const Read& r : p.reads)
+        if (!r.trans) vote(ops[r.slot].ptr, r.ld, itemsize(r.dtype), 2);
+    if (p.red_op < 0) vote(out->ptr, out->ld, itemsize(out->dtype), 1 << 20);
+    int best = 0;
+    for (int e = 1; e < 64; ++e)
+        if (votes[e] > votes[best]) best = e;
+    return best;
+}
+
 Plan make_plan(int red_op_in, int dim, const coot_expr* expr, const coot_operand* ops, int n_ops,
                const coot_operand* out)
 {
@@ -381,8 +397,15 @@ Plan make_plan(int red_op_in, int dim, const coot_expr* expr, const coot_operand
     if (P.tile_gen) {
         if (any_trans) {
             coot_tile_shape(P.rows, P.cols, &P.tile_lr, &P.tile_lc);
+        } else if (P.rows >= 64) {
+            // tall tiles: 8 to 16 tile rows down each column (tiles of 64 to
+            // 1024 rows), so that whole tiles dominate once the grid is
+            // shifted and only the first and last tile rows are partial
+            const int fl = 63 - __builtin_clzll((unsigned long long)P.rows);
+            P.tile_lr = std::max(6, std::min(fl - 3, 10));
+            P.tile_lc = std::min(coot_lg2ceil(P.cols), 12 - P.tile_lr);
         } else {
-            P.tile_lr = std::min(coot_lg2ceil(P.rows), 12);
+            P.tile_lr = coot_lg2ceil(P.rows);
             P.tile_lc = std::min(coot_lg2ceil(P.cols), 12 - P.tile_lr);
         }
         // per-lane offset bounds (elements of at most 8 bytes) of the tile
@@ -394,6 +417,24 @@ Plan make_plan(int red_op_in, int dim, const coot_expr* expr, const coot_operand
         int64_t bound = P.red_op < 0 ? 64 + ky * out->ld : 64;
         for (const Read& r : P.reads) bound = std::max(bound, 64 + (r.trans ? kt : ky) * r.ld);
         P.tile_off32 = bound < (int64_t(1) << 29);
+        // tall tiles: straight reads only, tile rows of at least 64; their
+        // grid shifts like the 64 x 64 one.  Whole 4096-element tall tiles
+        // move 4 consecutive rows per access when every operand's columns
+        // start, less the shift, on 4-element boundaries
+        P.tile_tall = !any_trans && lr >= 6;
+        P.tile_sh = P.tile_tall ? (int)tile_row_shift(P, ops, out) : 0;
+        P.tile_v4 = false;
+        if (P.tile_tall && lr + lc == 12) {
+            const int64_t sh = P.tile_sh;
+            auto al = [&](const void* ptr, int64_t ld, int sz) {
+                const uintptr_t u = (uintptr_t)ptr;
+                return u % (uintptr_t)sz == 0 && ((int64_t)((u / sz) % 4) - sh) % 4 == 0 && (P.cols == 1 || ld % 4 == 0);
+            };
+            bool ok = true;
+            for (const Read& r : P.reads) ok = ok && al(ops[r.slot].ptr, r.ld, itemsize(r.dtype));
+            if (P.red_op < 0) ok = ok && al(out->ptr, out->ld, itemsize(out->dtype));
+            P.tile_v4 = ok;
+        }
     }
     // thin values: a short side of at most 16 elements take the thin kernel
     // (emit_thin), unless an operand cannot follow its layout.  An operand
@@ -593,11 +634,28 @@ int config_index(const LaunchCfg& c)
 // 2^22..2^28 FP32/FP64/FP16 elements, accu, dot and index_max: 1.016x the
 // per-call best on geometric mean, worst 1.065x; 8 vectors per buffer:
 // 1.065x, worst 1.216x).
+// Element-wise trees bound by arithmetic rather than HBM run best with more
+// elements per thread: pow (either precision), and logarithms or
+// trigonometric functions computed in FP64 (2^28 elements: FP32 pow(|x|, 2.5)
+// 1000 -> 757 us, FP64 1530 -> 1492 us; FP64 log(|x| + 1) 980 -> 862 us,
+// FP64 sin(x) % cos(y) 1215 -> 1150 us with 256 threads x 4 vectors; FP32
+// log, sin and cos and every exp stay faster with one vector per thread).
+static bool alu_heavy(const Plan& p)
+{
+    for (const PNode& n : p.nodes) {
+        if (n.op == COOT_SCAL_POW) return true;
+        const bool lg = n.op == COOT_LOG || n.op == COOT_LOG2 || n.op == COOT_LOG10;
+        const bool trig = n.op >= COOT_COS && n.op <= COOT_TANH;
+        if (n.prec == 64 && (lg || trig)) return true;
+    }
+    return false;
+}
+
 LaunchCfg default_config(const Plan& p)
 {
     LaunchCfg c;
     switch (p.kind) {
-    case K_EW_FLAT: c = {1, 64, 8}; break;
+    case K_EW_FLAT: c = alu_heavy(p) ? LaunchCfg{4, 256, 8} : LaunchCfg{1, 64, 8}; break;
     case K_RED_FLAT: c = {2, 512, 1}; break;
     // per-column reductions: 64-thread blocks, 4 per CU per split unit
     // (40 column sums and index_max of 7 shapes x FP32/FP64/FP16: 1.054x the

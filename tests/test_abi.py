@@ -263,3 +263,25 @@ def test_probe_arguments_checked_on_the_host():
     assert "shape" in coot.last_error()
     assert L.coot_bandwidth_probe(coot.PROBE_READ | (1 << 8), d, s, 1000, None) == ERR_ARG
     assert L.coot_bandwidth_probe(coot.PROBE_COPY | (3 << 8), C.c_void_p(G + 8), s, 1024, None) == ERR_ARG
+
+
+@pytest.mark.parametrize("dt", ["f32", "f64", "bf16"])
+def test_tall_tile_kernels_compile_for_gfx950(tmp_path, monkeypatch, dt):
+    """Trees with straight reads only over strided views take tall tiles:
+    whole tiles with 4-row accesses (operands on a common 4-element phase),
+    whole tiles element by element (phases differ), partial tiles (clamped
+    loads, tested stores), and an index generator; element-wise and index
+    reductions."""
+    monkeypatch.setenv("COOT_CACHE_DIR", str(tmp_path))
+    x, y = leaves(2)
+    es = {"f32": 4, "f64": 8, "bf16": 2}[dt]
+    odt = "f64" if dt == "f64" else "f32"
+    r, c, ld = 9000, 40, 9024
+    for offs in ((4, 8, 4), (1, 6, 1)):
+        A = F(r, c, dt, ld=ld, ptr=G + offs[0] * es)
+        B = F(r, c, dt, ld=ld, ptr=2 * G + offs[1] * es)
+        Y = F(r, c, odt, ld=ld, ptr=3 * G + offs[2] * (8 if odt == "f64" else 4))
+        assert coot.precompile(None, -1, x * 2.0 - y, [A, B], Y) in (0, 1)
+        assert coot.precompile("index_max", -1, x % y, [A, B], F(1, 1, "u64", ptr=9 * G)) in (0, 1)
+    E = coot.eye(r, c, odt)
+    assert coot.precompile(None, -1, x * 0.5 + leaves(2)[1], [F(r, c, dt, ld=ld, ptr=G), E], F(r, c, odt, ptr=3 * G)) in (0, 1)

@@ -113,3 +113,73 @@ def test_tall_tiles_over_long_strided_views(dt):
         M[i, j] = 50.0
         dM = dev(synth.Mat(synth.store(np.asfortranarray(M), dt), dt), ld=ld, offset=3)
         assert coot.reduce("index_max", x, [dM]).item() == i + j * r, (dt, i, j)
+
+
+# tall tiles of 4096 elements, 2^lr x 2^lc: several tile rows, so that some
+# are whole with the grid shifted by the output's phase, and partial tiles at
+# both ends of the columns
+V4_SHAPES = [(9000, 19), (1024 * 6 + 5, 21), (256 * 9 + 3, 37), (64 * 20 + 7, 70), (128 * 11, 99)]
+
+
+@pytest.mark.parametrize("dt", ["f32", "f64", "bf16"])
+@pytest.mark.parametrize("r,c", V4_SHAPES)
+def test_whole_tall_tiles_four_rows_per_access(dt, r, c):
+    """Tall tiles start as many rows above the value as the output's columns
+    start into a 128-byte line (else the straight reads' most common phase).
+    Whole tiles move 4 consecutive rows per lane and access when every
+    operand's columns then start on 4-element boundaries (views 4 rows in, or
+    all one row in, leading dimensions multiples of 64), else single elements;
+    partial tiles clamp their loads into the value.  A tree with eye (needs
+    each element's row and column).  Results bit-exact, nothing outside the
+    view written, sums within the gate, extrema planted on both sides of the
+    4-row groups and the tile edges keep their index."""
+    g = np.random.default_rng(7000 + r + c + list(ODT).index(dt))
+    DA = g.uniform(-2, 2, (r, c))
+    A = synth.Mat(synth.store(np.asfortranarray(DA), dt), dt)
+    B = mat(g, (r, c), dt)
+    odt = ODT[dt]
+    ld = (r + 12 + 63) // 64 * 64
+    # offsets of A, B, Y (elements); 4-row accesses expected for the
+    # element-wise call (phase of Y) and the sum (phase of A on a tie)
+    for off_a, off_b, off_y, v4_ew, v4_red in ((4, 8, 4, True, True), (4, 9, 4, False, False),
+                                               (1, 1, 1, True, True), (1, 5, 2, False, True)):
+        dA, dB = dev(A, ld=ld, offset=off_a), dev(B, ld=ld, offset=off_b)
+        buf = torch.full((c * ld + off_y + 4,), float("nan"), dtype=TORCH_DT[odt], device="cuda")
+        Y = buf[off_y:off_y + c * ld].view(c, ld)[:, :r].t()
+        tree = x * 2.0 - y
+        src = coot.kernel_source(None, -1, tree, [dA, dB], Y)
+        assert ("4 rows per access" in src) == v4_ew and "whole tall tile" in src, (r, c, off_a, off_b)
+        coot.eval(tree, [dA, dB], Y)
+        torch.cuda.synchronize()
+        assert same(host(Y), oracle.evaluate(tree.postfix(), [A, B], "emu")), (dt, r, c, off_a, off_b)
+        full = buf[off_y:off_y + c * ld].view(c, ld)
+        assert torch.isnan(full[:, r:]).all() and torch.isnan(buf[:off_y]).all()
+        assert ("4 rows per access" in coot.kernel_source("accu", -1, x % y, [dA, dB],
+                                                           coot.fake_operand(1, 1, "f64" if dt == "f64" else "f32"))) == v4_red
+        o, _, s = oracle.reduce("accu", (x % y).postfix(), [A, B])
+        got = coot.reduce("accu", x % y, [dA, dB]).item()
+        assert abs(got - o[0]) <= (1e-6 if dt != "f64" else 1e-13) * s[0]
+    # index reductions over views on one phase: maxima at group and tile
+    # edges, a tie resolved to the lower linear index
+    dB = dev(B, ld=ld, offset=8)
+    for pts in (((3, 0),), ((4, 1),), ((r - 1, c - 1),), ((r - 4, c - 1), (r - 1, c - 2)),
+                ((min(r - 1, 4091), 0), (5, c - 1)), ((min(r - 1, 4092), c // 2),)):
+        M = DA.copy()
+        for (i, j) in pts:
+            M[i, j] = 50.0
+        Am = synth.Mat(synth.store(np.asfortranarray(M), dt), dt)
+        dM = dev(Am, ld=ld, offset=4)
+        want = min(i + j * r for (i, j) in pts)
+        assert coot.reduce("index_max", x, [dM]).item() == want, (dt, r, c, pts)
+        assert coot.reduce("index_max", x % y, [dM, dB]).item() == \
+            oracle.reduce("index_max", (x % y).postfix(), [Am, B], mode="emu")[1][0]
+    # a generator needing each element's position, with an operand on the
+    # output's phase
+    E = oracle.eye(r, c, odt)
+    t = x * 0.5 + synth.leaf(1)
+    dA = dev(A, ld=ld, offset=0)
+    Y = torch.empty(c, ld, dtype=TORCH_DT[odt], device="cuda")[:, :r].t()
+    assert "4 rows per access" in coot.kernel_source(None, -1, t, [dA, coot.eye(r, c, odt)], Y)
+    coot.eval(t, [dA, coot.eye(r, c, odt)], Y)
+    torch.cuda.synchronize()
+    assert same(host(Y), oracle.evaluate(t.postfix(), [A, E], "emu")), (dt, r, c)
