@@ -622,10 +622,25 @@ def tiled_workload(args, np, torch, synth, coot):
                      "GBps": round(gbs, 1), "frac_of_peak": round(gbs / PEAK_GBS, 4)}
     del A, Y
     torch.cuda.empty_cache()
+    # the tiled kernels' access pattern without their arithmetic: 16384-row
+    # FP32 streams of 1 GiB moved in tiles of 64..4096 rows (a wave access is
+    # 64 rows of one column; the run down a column is the tile's height)
+    nbytes = 1 << 30
+    src = torch.zeros(2 * nbytes // 4, dtype=torch.float32, device="cuda")
+    dst = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda")
+    ceil = {}
+    for name, kind, moved in (("copy", coot.PROBE_TILED_COPY, 2 * nbytes),
+                              ("mix_2to1", coot.PROBE_TILED_READ2_WRITE1, 3 * nbytes)):
+        for sh, rows in enumerate((64, 256, 1024, 4096)):
+            med = event_stats(torch, lambda: coot.bandwidth_probe(kind | (sh << 8), dst, src, nbytes))[0]
+            ceil[f"{name}_{rows}_row_runs"] = {"us": round(med, 1), "GBps": round(moved / (med * 1e-6) / 1e9, 1)}
+    del src, dst
+    torch.cuda.empty_cache()
     gb = [v["GBps"] for k, v in res.items() if not k.startswith("trace")]
     print(json.dumps({"metric": "transposed-read kernels, effective GB/s", "value": min(gb),
                       "unit": "GB/s (slowest case)", "n_gpus": 1, "higher_is_better": True, "dtype": "f32,f64",
-                      "data": "synthetic: torch.rand on the device", "per_call": res}), flush=True)
+                      "data": "synthetic: torch.rand on the device", "per_call": res,
+                      "tiled_ceilings_16384_rows_f32": ceil}), flush=True)
 
 
 def small_calls(np, torch, synth, coot):

@@ -534,8 +534,23 @@ int coot_copy(void* dst, const void* src, int64_t bytes, void* stream);
  *   COOT_PROBE_READ          reads src; dst (16 bytes) is written only if a
  *                            thread's XOR of its data has all bits set
  *   COOT_PROBE_WRITE         writes dst (src unused)
- *   COOT_PROBE_READ2_WRITE1  dst = src[0, bytes) XOR src[bytes, 2 bytes) */
-enum { COOT_PROBE_COPY = 0, COOT_PROBE_READ = 1, COOT_PROBE_WRITE = 2, COOT_PROBE_READ2_WRITE1 = 3 };
+ *   COOT_PROBE_READ2_WRITE1  dst = src[0, bytes) XOR src[bytes, 2 bytes)
+ * The tiled probes move each stream as a column-major matrix of 16384 rows
+ * of 4-byte elements (columns 64 KB apart) in tiles of 2^lr rows x 2^(12-lr)
+ * columns, one wave access being 64 consecutive rows of one column (4 bytes
+ * per lane): the access pattern of the tiled kernels, whose run down a
+ * column is the tile's height.  shape selects lr = 6, 8, 10, 12 (runs of
+ * 256 bytes to 16 KB); `bytes` must be a multiple of 4 MiB (64 columns):
+ *   COOT_PROBE_TILED_COPY          as COOT_PROBE_COPY
+ *   COOT_PROBE_TILED_READ2_WRITE1  as COOT_PROBE_READ2_WRITE1 */
+enum {
+    COOT_PROBE_COPY = 0,
+    COOT_PROBE_READ = 1,
+    COOT_PROBE_WRITE = 2,
+    COOT_PROBE_READ2_WRITE1 = 3,
+    COOT_PROBE_TILED_COPY = 4,
+    COOT_PROBE_TILED_READ2_WRITE1 = 5
+};
 int coot_bandwidth_probe(int kind, void* dst, const void* src, int64_t bytes, void* stream);
 
 #ifdef __cplusplus

@@ -580,6 +580,7 @@ def copy(dst, src, nbytes: Optional[int] = None, stream=None) -> None:
 
 
 PROBE_COPY, PROBE_READ, PROBE_WRITE, PROBE_READ2_WRITE1 = 0, 1, 2, 3
+PROBE_TILED_COPY, PROBE_TILED_READ2_WRITE1 = 4, 5
 
 
 def bandwidth_probe(kind: int, dst, src, nbytes: int, stream=None) -> None:

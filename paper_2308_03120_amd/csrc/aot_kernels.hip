@@ -94,6 +94,51 @@ void probe_shape(int shape, int64_t nv, u32x4* d, const u32x4* sv, hipStream_t s
     }
 }
 
+// Tiled probes: each stream a column-major matrix of 16384 rows of 4-byte
+// elements and `cols` columns (a multiple of 64), moved in tiles of 2^LR rows
+// x 2^(12-LR) columns, a block per tile (grid-stride); wave w's step kk
+// covers tile elements 64*(w + 4*kk) + [0, 64) in column order, so a wave
+// access is 64 consecutive rows.  KIND 0 copies, KIND 3 writes a XOR b.
+template <int KIND, int LR>
+__global__ void __launch_bounds__(256) coot_probe_tiled(u32* __restrict__ dst, const u32* __restrict__ src, int64_t cols)
+{
+    constexpr int LC = 12 - LR, MASK = (1 << LR) - 1;
+    constexpr int64_t N = 16384;
+    const int lane = threadIdx.x & 63, w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int64_t tr = N >> LR, nt = tr * (cols >> LC), second = N * cols;
+    for (int64_t t = blockIdx.x; t < nt; t += gridDim.x) {
+        const int64_t i0 = (t % tr) << LR, j0 = (t / tr) << LC;
+        u32 v[16];
+#pragma unroll
+        for (int kk = 0; kk < 16; ++kk) {
+            const int e = 64 * (w + 4 * kk);
+            const int64_t off = i0 + (e & MASK) + lane + (j0 + (e >> LR)) * N;
+            v[kk] = __builtin_nontemporal_load(src + off);
+            if (KIND == 3) v[kk] ^= __builtin_nontemporal_load(src + second + off);
+        }
+#pragma unroll
+        for (int kk = 0; kk < 16; ++kk) {
+            const int e = 64 * (w + 4 * kk);
+            __builtin_nontemporal_store(v[kk], dst + (i0 + (e & MASK) + lane + (j0 + (e >> LR)) * N));
+        }
+    }
+}
+
+template <int KIND>
+void probe_tiled(int shape, int64_t bytes, void* d, const void* s, int grid_cap, hipStream_t st)
+{
+    const int64_t cols = bytes / (16384 * 4), tiles = cols * 4;   // 4096-element tiles
+    const dim3 g((unsigned)(tiles < grid_cap ? tiles : grid_cap)), b(256);
+    u32* dd = (u32*)d;
+    const u32* ss = (const u32*)s;
+    switch (shape) {
+    case 0: hipLaunchKernelGGL((coot_probe_tiled<KIND, 6>), g, b, 0, st, dd, ss, cols); break;
+    case 1: hipLaunchKernelGGL((coot_probe_tiled<KIND, 8>), g, b, 0, st, dd, ss, cols); break;
+    case 2: hipLaunchKernelGGL((coot_probe_tiled<KIND, 10>), g, b, 0, st, dd, ss, cols); break;
+    default: hipLaunchKernelGGL((coot_probe_tiled<KIND, 12>), g, b, 0, st, dd, ss, cols); break;
+    }
+}
+
 }  // namespace
 
 namespace {
@@ -240,6 +285,8 @@ int coot_probe_launch(int kind, int shape, void* dst, const void* src, int64_t b
     case COOT_PROBE_READ: probe_shape<1>(shape, nv, d, sv, st); break;
     case COOT_PROBE_WRITE: probe_shape<2>(shape, nv, d, sv, st); break;
     case COOT_PROBE_READ2_WRITE1: probe_shape<3>(shape, nv, d, sv, st); break;
+    case COOT_PROBE_TILED_COPY: probe_tiled<0>(shape, bytes, dst, src, 16384, st); break;
+    case COOT_PROBE_TILED_READ2_WRITE1: probe_tiled<3>(shape, bytes, dst, src, 16384, st); break;
     default: return -10;
     }
     return hipGetLastError() == hipSuccess ? 0 : -8;

@@ -379,7 +379,7 @@ static std::string sig_key(const Plan& p, const LaunchCfg& c)
 {
     return std::to_string(p.kind) + "|" + std::to_string(p.ve) + "|" + std::to_string(c.ept) + "|" +
            std::to_string(p.out_dtype) + "|" + std::to_string(p.red_op) + "|" + std::to_string(p.pairwise) + "|" +
-           std::to_string(p.alias_out) + "|" + std::to_string(p.tile_gen) + std::to_string(p.tile_off32) + std::to_string(p.tile_tall) + std::to_string(p.tile_v4) +
+           std::to_string(p.alias_out) + "|" + std::to_string(p.tile_gen) + std::to_string(p.tile_off32) + std::to_string(p.tile_tall) + std::to_string(p.tile_v4) + "c" + std::to_string(p.tile_cached) +
            std::to_string(p.tile_lr) + "," + std::to_string(p.tile_lc) + "|t" + std::to_string(p.thin_k) +
            (p.thin_rows ? "r" : "c") + std::to_string(p.thin_v) + "v" + std::to_string(p.thin_vec) + "|" + p.body_sig;
 }

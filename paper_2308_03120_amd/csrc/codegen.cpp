@@ -824,8 +824,8 @@ static std::string tall_prefetch(const Plan& p, const std::string& in, const std
         o << i3 << "const i64 jl = wc + " << gen_cc(lr) << ";\n";
     }
     for (size_t j = 0; j < p.reads.size(); ++j) {
-        const std::string J = std::to_string(j);
-        o << i3 << "pr" << J << "[kk] = " << widen(p.reads[j].dtype, "ldnt(at(a" + J + " + jl * " + v.ld(j) + ", tcl))") << ";\n";
+        const std::string J = std::to_string(j), ldf = (p.tile_cached >> j) & 1u ? "ldpl" : "ldnt";
+        o << i3 << "pr" << J << "[kk] = " << widen(p.reads[j].dtype, ldf + "(at(a" + J + " + jl * " + v.ld(j) + ", tcl))") << ";\n";
     }
     o << i2 << "}\n" << in << "}\n";
     return o.str();

@@ -109,6 +109,8 @@ struct Plan {
     // argument, so that the output's column segments begin on 128-byte lines)
     bool tile_tall = false;
     int tile_sh = 0;
+    uint32_t tile_cached = 0; // tall tiles: bit j, read j's column segments do not start on lines
+                              // once shifted, so neighbouring steps share lines: load through the caches
     bool tile_v4 = false;     // tall 4096-element tiles whose operands all start their columns (less
                               // tile_sh rows) on 4-element boundaries: 4 consecutive rows per access
     // thin tiled value whose short side K = thin_k <= 16 (0: not thin): each

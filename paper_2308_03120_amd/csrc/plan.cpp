@@ -423,6 +423,19 @@ Plan make_plan(int red_op_in, int dim, const coot_expr* expr, const coot_operand
         // start, less the shift, on 4-element boundaries
         P.tile_tall = !any_trans && lr >= 6;
         P.tile_sh = P.tile_tall ? (int)tile_row_shift(P, ops, out) : 0;
+        // a read whose shifted column segments start inside a 128-byte line
+        // shares its first and last line with the neighbouring steps: those
+        // loads go through the caches (a nontemporal load refetches the line)
+        P.tile_cached = 0;
+        if (P.tile_tall)
+            for (size_t j = 0; j < P.reads.size(); ++j) {
+                const Read& r = P.reads[j];
+                const uintptr_t u = (uintptr_t)ops[r.slot].ptr;
+                const int64_t sz = itemsize(r.dtype);
+                const bool on_lines = u % (uintptr_t)sz == 0 && (P.cols == 1 || (r.ld * sz) % 128 == 0) &&
+                                      ((int64_t)(u % 128) / sz - P.tile_sh) * sz % 128 == 0;
+                if (!on_lines) P.tile_cached |= 1u << j;
+            }
         P.tile_v4 = false;
         if (P.tile_tall && lr + lc == 12) {
             const int64_t sh = P.tile_sh;

@@ -384,9 +384,11 @@ int coot_bandwidth_probe(int kind, void* dst, const void* src, int64_t bytes, vo
 {
     return guard2([&] {
         const int base = kind & 0xff, shape = kind >> 8;
-        if (base < COOT_PROBE_COPY || base > COOT_PROBE_READ2_WRITE1) fail(COOT_ERR_ARG, "unknown probe kind");
+        if (base < COOT_PROBE_COPY || base > COOT_PROBE_TILED_READ2_WRITE1) fail(COOT_ERR_ARG, "unknown probe kind");
         if (shape < 0 || shape > 3) fail(COOT_ERR_ARG, "unknown probe launch shape");
         if (bytes < 0 || bytes % 16) fail(COOT_ERR_ARG, "probe length must be a nonnegative multiple of 16 bytes");
+        if (base >= COOT_PROBE_TILED_COPY && bytes % (INT64_C(4) << 20))
+            fail(COOT_ERR_ARG, "a tiled probe's length must be a multiple of 4 MiB (64 columns of 16384 rows)");
         if (bytes > 0 && ((base != COOT_PROBE_WRITE && !src) || !dst)) fail(COOT_ERR_ARG, "NULL probe buffer");
         if (((uintptr_t)dst | (uintptr_t)src) & 15) fail(COOT_ERR_ARG, "probe needs 16-byte aligned pointers");
         ensure_init();

@@ -263,6 +263,11 @@ def test_probe_arguments_checked_on_the_host():
     assert "shape" in coot.last_error()
     assert L.coot_bandwidth_probe(coot.PROBE_READ | (1 << 8), d, s, 1000, None) == ERR_ARG
     assert L.coot_bandwidth_probe(coot.PROBE_COPY | (3 << 8), C.c_void_p(G + 8), s, 1024, None) == ERR_ARG
+    # tiled probes: whole 64-column blocks of 16384 rows only
+    assert L.coot_bandwidth_probe(coot.PROBE_TILED_COPY, d, s, (4 << 20) + 16, None) == ERR_ARG
+    assert "4 MiB" in coot.last_error()
+    assert L.coot_bandwidth_probe(coot.PROBE_TILED_READ2_WRITE1 | (2 << 8), d, s, 1 << 20, None) == ERR_ARG
+    assert L.coot_bandwidth_probe(coot.PROBE_TILED_COPY | (4 << 8), d, s, 4 << 20, None) == ERR_ARG
 
 
 @pytest.mark.parametrize("dt", ["f32", "f64", "bf16"])

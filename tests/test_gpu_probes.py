@@ -1,7 +1,9 @@
 """The streaming probes (the read/write-mix ceilings the fused kernels are
 compared with) move the bytes they claim, in every launch shape: the copy
 reproduces its source, the 2:1 mix writes a XOR b, the write-only probe writes
-its index pattern, the read-only probe leaves its output alone on random data."""
+its index pattern, the read-only probe leaves its output alone on random data;
+the tiled probes (16384-row column-major streams moved tile by tile) copy and
+XOR every element of every column in each tile shape."""
 import numpy as np
 import pytest
 
@@ -41,3 +43,20 @@ def test_probes_move_their_bytes(shape, nbytes):
     coot.bandwidth_probe(coot.PROBE_READ | (shape << 8), dst, src, nbytes)
     torch.cuda.synchronize()
     assert bool((dst == 7).all())
+
+
+@pytest.mark.parametrize("shape", [0, 1, 2, 3])
+def test_tiled_probes_move_every_element(shape):
+    cols = 128
+    n = 16384 * cols
+    g = torch.Generator(device="cuda")
+    g.manual_seed(100 + shape)
+    src = torch.randint(-2 ** 31, 2 ** 31 - 1, (2 * n,), generator=g, device="cuda", dtype=torch.int32)
+    dst = torch.zeros(n, device="cuda", dtype=torch.int32)
+    coot.bandwidth_probe(coot.PROBE_TILED_COPY | (shape << 8), dst, src, 4 * n)
+    torch.cuda.synchronize()
+    assert torch.equal(dst, src[:n])
+    dst.zero_()
+    coot.bandwidth_probe(coot.PROBE_TILED_READ2_WRITE1 | (shape << 8), dst, src, 4 * n)
+    torch.cuda.synchronize()
+    assert torch.equal(dst, src[:n] ^ src[n:])
