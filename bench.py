@@ -555,16 +555,17 @@ def ceilings(torch, coot, nbytes=1 << 30):
 
 def event_stats(torch, fn, reps=21, between=None):
     """median, min and p90 in microseconds of single-call HIP-event timings.  A
-    short spin on the GPU (no memory traffic) is queued before the start event,
-    so the host's preparation of the call overlaps it and the interval is the
-    device's time for the call."""
+    spin on the GPU (no memory traffic, about 0.4 ms) is queued before the start
+    event, so the host's preparation of the call -- a dozen launches for the
+    unfused per-node forms -- overlaps it and the interval is the device's time
+    for the call."""
     fn()
     torch.cuda.synchronize()
     ts = []
     for _ in range(reps):
         if between is not None:
             between()
-        torch.cuda._sleep(200000)
+        torch.cuda._sleep(1000000)
         a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         a.record()
         fn()
@@ -604,6 +605,7 @@ def tiled_workload(args, np, torch, synth, coot):
     # (16384 strided elements, one per cache line: latency, not bandwidth)
     n = 16384
     A = torch.rand(n, n, device="cuda").t()
+    B2 = torch.rand(n, n, device="cuda").t()
     Y = torch.empty(n, n, device="cuda").t()
     X0 = synth.leaf(0)
     for call, fn, nbytes in (("add_eye_16384x16384_f32", lambda: coot.eval(X0 + synth.leaf(1), [A, coot.eye(n, n)], Y),
@@ -615,12 +617,18 @@ def tiled_workload(args, np, torch, synth, coot):
                              ("scale_submat_offset_out_16383x16383_f32",
                               lambda: coot.eval(X0 * 2.0, [coot.submat(A, 1, 1, n - 1, n - 1)],
                                                 coot.submat(Y, 1, 1, n - 1, n - 1)), 8 * (n - 1) * (n - 1)),
+                             # a transposed read and a straight read one element off their
+                             # lines, into an aligned view (64 x 64 tiles)
+                             ("add_trans_submat_offset_in_16383x16383_f32",
+                              lambda: coot.eval(synth.trans(X0) + 0.5 * synth.leaf(1),
+                                                [coot.submat(A, 1, 1, n - 1, n - 1), coot.submat(B2, 1, 1, n - 1, n - 1)],
+                                                coot.submat(Y, 0, 0, n - 2, n - 2)), 12 * (n - 1) * (n - 1)),
                              ("trace_16384x16384_f32", lambda: coot.trace(A), 4 * n)):
         med, mn, p90 = event_stats(torch, fn)
         gbs = nbytes / (med * 1e-6) / 1e9
         res[call] = {"us_median": round(med, 1), "us_min": round(mn, 1), "us_p90": round(p90, 1),
                      "GBps": round(gbs, 1), "frac_of_peak": round(gbs / PEAK_GBS, 4)}
-    del A, Y
+    del A, B2, Y
     torch.cuda.empty_cache()
     # the tiled kernels' access pattern without their arithmetic: 16384-row
     # FP32 streams of 1 GiB moved in tiles of 64..4096 rows (a wave access is

@@ -431,8 +431,7 @@ void run_plan(const Plan& p, const LaunchCfg& cfg_in, const coot_operand* ops, c
     a.splits = G.splits;
     a.aux = G.aux;
     if ((p.kind == K_EW_TILED || p.kind == K_RED_TILED) && !p.thin_k) {
-        if (!p.tile_gen) a.aux = tile_row_shift(p, ops, out);
-        else if (p.tile_tall) a.aux = p.tile_sh;
+        if (!p.tile_gen || p.tile_tall) a.aux = p.tile_sh;
     }
     if (p.red_op < 0) {
         a.out = out->ptr;

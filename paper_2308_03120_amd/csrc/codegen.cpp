@@ -515,27 +515,9 @@ static std::string emit_flat(const Plan& p, const LaunchCfg& c, const std::strin
 // read back transposed (conflict-free both ways).  The tile loop is software
 // pipelined: the operands of the next tile are loaded into registers while
 // the current tile is computed.
-struct TilePlan {
-    std::vector<bool> in_lds;
-    bool any_lds = false;
-};
+typedef TileLds TilePlan;
 
-static TilePlan tile_plan(const Plan& p)
-{
-    TilePlan t;
-    t.in_lds.assign(p.reads.size(), false);
-    int budget = 96 * 1024;
-    for (size_t j = 0; j < p.reads.size(); ++j) {
-        if (!p.reads[j].trans) continue;
-        int bytes = COOT_TILE_LDS * (dtype_prec(p.reads[j].dtype) == 64 ? 8 : 4);
-        if (bytes <= budget) {
-            t.in_lds[j] = true;
-            budget -= bytes;
-            t.any_lds = true;
-        }
-    }
-    return t;
-}
+static TilePlan tile_plan(const Plan& p) { return tile_lds_plan(p); }
 
 static std::string tile_shared_decls(const Plan& p, const TilePlan& tp, const std::string& ind)
 {
@@ -580,7 +562,7 @@ struct TileView {
 // --- square 64 x 64 tiles --------------------------------------------------
 // shifted: the tile grid starts sh rows above the value (the per-call kernels)
 static std::string tile_prefetch_sq(const Plan& p, const TilePlan& tp, const std::string& in, const std::string& ti,
-                                    const std::string& tj, const TileView& v, const std::string& ldf, bool shifted = false)
+                                    const std::string& tj, const TileView& v, const std::string& ldf0, bool shifted = false)
 {
     std::ostringstream o;
     o << in << "{\n";
@@ -611,6 +593,7 @@ static std::string tile_prefetch_sq(const Plan& p, const TilePlan& tp, const std
     o << in << "        const int q = w + 4 * kk;\n";
     for (size_t j = 0; j < p.reads.size(); ++j) {
         const std::string J = std::to_string(j), C = ctype(dtype_prec(p.reads[j].dtype));
+        const std::string ldf = (p.tile_cached >> j) & 1u ? "ldpl" : ldf0;
         if (tp.in_lds[j])
             o << in << "        pt" << J << "[kk] = " << (shifted ? "q >= plo && " : "") << "q < pri ? " << widen(p.reads[j].dtype, ldf + "(a" + J + " + lnc)") << " : (" << C
               << ")0;\n";

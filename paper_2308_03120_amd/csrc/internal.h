@@ -124,6 +124,14 @@ struct Plan {
     std::string body_sig;     // canonical description of the element function
 };
 
+// Which transposed reads of a tiled plan are staged through LDS tiles (in
+// order, while 96 KB last); the others are held in registers.
+struct TileLds {
+    std::vector<bool> in_lds;
+    bool any_lds = false;
+};
+TileLds tile_lds_plan(const Plan& p);
+
 // Rows (0..63) by which a tiled grid starts above the value: the phase, in
 // elements within a 128-byte line, shared by the output's columns (else by
 // most straight reads), so that their column segments begin on lines.

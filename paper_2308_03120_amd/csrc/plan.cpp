@@ -144,6 +144,23 @@ struct Info {
     int prec;
 };
 
+TileLds tile_lds_plan(const Plan& p)
+{
+    TileLds t;
+    t.in_lds.assign(p.reads.size(), false);
+    int budget = 96 * 1024;
+    for (size_t j = 0; j < p.reads.size(); ++j) {
+        if (!p.reads[j].trans) continue;
+        const int bytes = COOT_TILE_LDS * (dtype_prec(p.reads[j].dtype) == 64 ? 8 : 4);
+        if (bytes <= budget) {
+            t.in_lds[j] = true;
+            budget -= bytes;
+            t.any_lds = true;
+        }
+    }
+    return t;
+}
+
 int64_t tile_row_shift(const Plan& p, const coot_operand* ops, const coot_operand* out)
 {
     int votes[64] = {0};
@@ -423,19 +440,6 @@ Plan make_plan(int red_op_in, int dim, const coot_expr* expr, const coot_operand
         // start, less the shift, on 4-element boundaries
         P.tile_tall = !any_trans && lr >= 6;
         P.tile_sh = P.tile_tall ? (int)tile_row_shift(P, ops, out) : 0;
-        // a read whose shifted column segments start inside a 128-byte line
-        // shares its first and last line with the neighbouring steps: those
-        // loads go through the caches (a nontemporal load refetches the line)
-        P.tile_cached = 0;
-        if (P.tile_tall)
-            for (size_t j = 0; j < P.reads.size(); ++j) {
-                const Read& r = P.reads[j];
-                const uintptr_t u = (uintptr_t)ops[r.slot].ptr;
-                const int64_t sz = itemsize(r.dtype);
-                const bool on_lines = u % (uintptr_t)sz == 0 && (P.cols == 1 || (r.ld * sz) % 128 == 0) &&
-                                      ((int64_t)(u % 128) / sz - P.tile_sh) * sz % 128 == 0;
-                if (!on_lines) P.tile_cached |= 1u << j;
-            }
         P.tile_v4 = false;
         if (P.tile_tall && lr + lc == 12) {
             const int64_t sh = P.tile_sh;
@@ -487,6 +491,30 @@ Plan make_plan(int red_op_in, int dim, const coot_expr* expr, const coot_operand
             P.thin_rows = sr;
             P.thin_v = V;
             P.thin_vec = vec;
+        }
+    }
+    // 64 x 64 and tall tiles: the grid shift, and the reads whose column
+    // segments start inside a 128-byte line once shifted (a straight read) or
+    // at all (a read through trans(), whose segments run along its own
+    // columns): each shares its first and last line with the neighbouring
+    // steps, so those loads go through the caches (a nontemporal load
+    // refetches the line).  A transposed read held in registers touches a
+    // line per lane for every step: always through the caches.
+    P.tile_cached = 0;
+    if ((P.kind == K_EW_TILED || P.kind == K_RED_TILED) && !P.thin_k && (!P.tile_gen || P.tile_tall)) {
+        if (!P.tile_gen) P.tile_sh = (int)tile_row_shift(P, ops, out);
+        const TileLds lds = tile_lds_plan(P);
+        for (size_t j = 0; j < P.reads.size(); ++j) {
+            const Read& r = P.reads[j];
+            const uintptr_t u = (uintptr_t)ops[r.slot].ptr;
+            const int64_t sz = itemsize(r.dtype);
+            bool on_lines = u % 128 == 0 && (r.ld * sz) % 128 == 0;
+            if (!r.trans)
+                on_lines = u % (uintptr_t)sz == 0 && (P.cols == 1 || (r.ld * sz) % 128 == 0) &&
+                           ((int64_t)(u % 128) / sz - P.tile_sh) * sz % 128 == 0;
+            else if (!lds.in_lds[j])
+                on_lines = false;
+            if (!on_lines) P.tile_cached |= 1u << j;
         }
     }
     if (P.red_op >= 0 && (P.red_op == COOT_RED_ACCU || P.red_op == COOT_RED_SUM || P.red_op == COOT_RED_DOT) &&
@@ -653,8 +681,12 @@ int config_index(const LaunchCfg& c)
 // 1000 -> 757 us, FP64 1530 -> 1492 us; FP64 log(|x| + 1) 980 -> 862 us,
 // FP64 sin(x) % cos(y) 1215 -> 1150 us with 256 threads x 4 vectors; FP32
 // log, sin and cos and every exp stay faster with one vector per thread).
+// Only large values gain: over 102 such random trees of 2^10 to 2^26
+// elements, 256 x 4 took 0.71-0.82x the time of 64 x 1 from 2^23 elements
+// on and 0.99-1.29x below.
 static bool alu_heavy(const Plan& p)
 {
+    if (p.rows * p.cols < (int64_t(1) << 23)) return false;
     for (const PNode& n : p.nodes) {
         if (n.op == COOT_SCAL_POW) return true;
         const bool lg = n.op == COOT_LOG || n.op == COOT_LOG2 || n.op == COOT_LOG10;
