@@ -621,7 +621,10 @@ Plan make_plan_cached(int red_op, int dim, const coot_expr* expr, const coot_ope
             put(k, o.gen[0]);
             put(k, o.gen[1]);
         }
-        uint8_t a = (uint8_t)((uintptr_t)o.ptr & 15) | (o.ptr ? 0 : 0x80);
+        // the pointer's place in its 128-byte line: vector widths, the tiled
+        // grid's shift and the load policy of tiled reads follow from it
+        put(k, (uint8_t)((uintptr_t)o.ptr & 127));
+        uint8_t a = o.ptr ? 0 : 0x80;
         if (rel && out_ok && ohi > olo && sane(o)) {
             uint64_t lo, hi;
             extent(o, o.dtype, &lo, &hi);
