@@ -183,3 +183,36 @@ def test_whole_tall_tiles_four_rows_per_access(dt, r, c):
     coot.eval(t, [dA, coot.eye(r, c, odt)], Y)
     torch.cuda.synchronize()
     assert same(host(Y), oracle.evaluate(t.postfix(), [A, E], "emu")), (dt, r, c)
+
+
+@pytest.mark.parametrize("dt", ["f32", "f64", "bf16"])
+@pytest.mark.parametrize("off", [(4, 2), (1, 1)])
+def test_tall_tiles_in_place_on_a_view(dt, off):
+    """V = 2*V + 1 in place on a 3000 x 45 view of a 3012 x 48 matrix (whole
+    and partial tall tiles; 4 rows per access when the view starts 4 rows
+    into aligned columns, single elements and cached loads one row in):
+    every element of the view updated once, bit-exact, everything else
+    unchanged."""
+    R0, C0 = 3012, 48
+    i0, j0 = off
+    r, c = 3000, 45
+    g = np.random.default_rng(3000 + i0 + list(ODT).index(dt))
+    M = mat(g, (R0, C0), dt)
+    dM = dev(M)
+    before = host(dM)
+    V = coot.submat(dM, i0, j0, i0 + r - 1, j0 + c - 1)
+    tree = x * 2.0 + 1.0
+    src = coot.kernel_source(None, -1, tree, [V], V)
+    assert "whole tall tile" in src and (("4 rows per access" in src) == (i0 % 4 == 0)), off
+    coot.eval(tree, [V], V)
+    torch.cuda.synchronize()
+    after = host(dM)
+    sub = synth.Mat(np.asfortranarray(M.data[i0:i0 + r, j0:j0 + c]), dt)
+    want = oracle.evaluate(tree.postfix(), [sub], "emu")
+    got = after[i0:i0 + r, j0:j0 + c]
+    if dt == "bf16":
+        want = oracle.round_to("bf16", want.reshape(-1, order="F")).reshape(want.shape, order="F")
+    assert same(got, want), (dt, off)
+    mask = np.ones((R0, C0), dtype=bool)
+    mask[i0:i0 + r, j0:j0 + c] = False
+    assert np.array_equal(after[mask], before[mask])
