@@ -137,3 +137,35 @@ def test_transposed_integer_reads_and_generators(g):
     coot.eval(x + y, [dev(B), coot.fill(700, 300, 2.7, "i32")], Y)
     torch.cuda.synchronize()
     assert np.array_equal(Y.cpu().numpy(), B.data + 2.0)
+
+
+@pytest.mark.parametrize("idt", ["i32", "u32"])
+@pytest.mark.parametrize("i0", [4, 1])
+def test_integer_views_on_tall_tiles(g, idt, i0):
+    """An integer view (3000 x 45 of a 3012 x 48 matrix, 4 rows in: 4-row
+    accesses; one row in: single elements) read by tall tiles: element-wise
+    results bit-exact against the oracle, the count of a predicate and the
+    index of the maximum exact."""
+    lo, hi = (-2 ** 31, 2 ** 31) if idt == "i32" else (0, 2 ** 32)
+    R0, C0, r, c, j0 = 3012, 48, 3000, 45, 2
+    M = imat(g, (R0, C0), idt, lo, hi)
+    dM = to_dev(M)
+    V = operand(dM, idt)
+    V.ptr += (i0 + j0 * R0) * 4
+    V.n_rows, V.n_cols = r, c
+    sub = synth.Mat(np.asfortranarray(M.data[i0:i0 + r, j0:j0 + c]), idt)
+    B = synth.Mat(np.asfortranarray(g.uniform(-3e9, 3e9, (r, c))), "f64")
+    dB = dev(B)
+    tree = x * 0.5 + y
+    Y = out(r, c, "f64")
+    src = coot.kernel_source(None, -1, tree, [V, dB], operand(Y, "f64"))
+    assert "tall tile" in src
+    coot.eval(tree, [V, dB], operand(Y, "f64"))
+    torch.cuda.synchronize()
+    assert np.array_equal(values(Y, "f64"), oracle.evaluate(tree.postfix(), [sub, B], "emu"))
+    vals = sub.data.astype(np.float64)
+    thr = float(np.median(vals))
+    cnt = coot.reduce("count", X > thr, [V]).cpu().numpy()
+    assert int(cnt[0]) == int((vals > thr).sum())
+    im = int(coot.reduce("index_max", X, [V]).cpu().numpy()[0])
+    assert im == int(np.argmax(vals.reshape(-1, order="F")))
