@@ -583,6 +583,7 @@ def tiled_workload(args, np, torch, synth, coot):
     res = {}
     cases = (("square_16384x16384_f32", 16384, 16384, torch.float32),
              ("square_16384x8192_f64", 16384, 8192, torch.float64),
+             ("square_16384x16384_bf16", 16384, 16384, torch.bfloat16),
              ("thin_2x67108864_f32", 2, 1 << 26, torch.float32),
              ("thin_8388608x12_f32", 1 << 23, 12, torch.float32))
     for name, r, c, tdt in cases:

@@ -711,10 +711,24 @@ LaunchCfg default_config(const Plan& p)
     case K_RED_COL: c = {2, 64, 4}; break;
     // tiled element-wise: shape-adaptive (thin) tiles run best as one pass
     // (split 8: 2 x 2^26 and 2^23 x 12 FP32 adds 12% faster than split 4),
-    // 64 x 64 tiles as 2 blocks per CU (16384^2 adds 2-3% faster); tiled
-    // reductions as 8 blocks per CU
-    case K_EW_TILED: c = p.tile_gen ? LaunchCfg{1, 256, 8} : LaunchCfg{1, 256, 1}; break;
+    // 64 x 64 tiles as 2 blocks per CU when every operand has 4- or 8-byte
+    // elements (16384^2 FP32 and 16384 x 8192 FP64 adds 2-3% faster), as one
+    // pass when one has 2-byte elements (16384^2 BF16 add: 1914 us as 2
+    // blocks per CU, 706 us as one pass; over 76 random 16-bit trees 1.27x
+    // the per-tree best against 1.04x); tiled reductions as 8 blocks per CU
+    case K_EW_TILED: {
+        bool narrow = itemsize(p.out_dtype) < 4;
+        for (const Read& r : p.reads) narrow = narrow || itemsize(r.dtype) < 4;
+        c = p.tile_gen || narrow ? LaunchCfg{1, 256, 8} : LaunchCfg{1, 256, 1};
+        break;
+    }
     case K_RED_TILED: c = {1, 256, 4}; break;
+    // per-row reductions: 64-thread blocks (799 random trees: 1.04x the
+    // per-tree best on geometric mean against 1.11x for 256-thread blocks);
+    // per-column reductions of short columns: 64-thread blocks, 2 per CU
+    // (268 trees: 1.06x against 1.11x)
+    case K_RED_ROW: c = {1, 64, 8}; break;
+    case K_RED_COLT: c = {1, 64, 2}; break;
     default: c = {4, 256, 8}; break;
     }
     return c;

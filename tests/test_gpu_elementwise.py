@@ -287,3 +287,24 @@ def test_plan_cache_keeps_pointer_dependent_checks(g):
         coot.eval(t2, [da, db], O)
         torch.cuda.synchronize()
         assert same(host(O), em2), off
+
+
+@pytest.mark.parametrize("dt", ["bf16", "f16"])
+def test_shape_adaptive_tiles_converted_types(g, dt):
+    """Shape-adaptive tiles (a side of 17 to 63 elements, a transposed read)
+    on 16-bit storage, whose loads are unconditional with the value zeroed
+    outside the tile: bit-exact element-wise results, and the sum and the
+    index of the maximum of the same tree against the oracle."""
+    x, y = leaves(2)
+    for (r, c) in [(33, 4100), (4100, 33), (63, 129), (40, 1000), (17, 65)]:
+        A, B = mats_like(g, [(r, c), (c, r)], dt)
+        t = trans(y) + x % x
+        src = coot.kernel_source(None, -1, t, [dev(A), dev(B)], empty(r, c, "f32"))
+        assert "// thin value:" not in src and "tall tile" not in src, (r, c)
+        check_tree(t, [A, B], out_dt="f32")
+        check_tree(t, [A, B], out_dt=dt)
+        got = coot.reduce("accu", t, [dev(A), dev(B)]).double().cpu().numpy()
+        o, _, asum = oracle.reduce("accu", t.postfix(), [A, B], mode="emu")
+        assert abs(got[0] - o[0]) <= 1e-6 * asum[0], (r, c, got, o)
+        im = int(coot.reduce("index_max", t, [dev(A), dev(B)]).cpu().numpy()[0])
+        assert im == int(oracle.reduce("index_max", t.postfix(), [A, B], mode="emu")[1][0]), (r, c)
