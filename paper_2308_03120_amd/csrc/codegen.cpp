@@ -1705,17 +1705,31 @@ std::string batch_kernel_source(const Plan& py, const Plan* pr, bool has_out, in
         o << in << "    int l = " << sb << " + qq + pp * kp;\n";
         o << in << "    const i64 dya = (i64)dp + (i64)dq * R;\n";
         o << in << "    const int dl = dq + dp * kp;\n";
+        // a straight read converted on load (16-bit, integer) loads
+        // unconditionally, an element past the unit reading the unit's first:
+        // behind the per-element test the compiler waited for each load to
+        // convert it before issuing the next
+        auto converted = [&](size_t j) {
+            return !py.reads[j].trans && py.reads[j].dtype != COOT_F32 && py.reads[j].dtype != COOT_F64;
+        };
+        bool any_conv = false;
+        for (size_t j = 0; j < nr; ++j) any_conv = any_conv || converted(j);
+        if (any_conv) o << in << "    const i64 yz = (i64)u.p0 + (i64)u.q0 * R;\n";
         o << in << "    for (int e0 = " << t << "; e0 < n; e0 += " << U << " * " << nt << ") {\n";
         for (size_t j = 0; j < nr; ++j)
             o << in << "        " << ctype(dtype_prec(py.reads[j].dtype)) << " v" << j << "[" << U << "];\n";
         o << in << "        i64 ys[" << U << "];\n";
         o << in << "#pragma unroll\n" << in << "        for (int e = 0; e < " << U << "; ++e) {\n";
         o << in << "            ys[e] = ya;\n";
+        for (size_t j = 0; j < nr; ++j)
+            if (converted(j))
+                o << in << "            v" << j << "[e] = "
+                  << widen(py.reads[j].dtype, "ldpl(L" + std::to_string(j) + " + (e0 + e * " + nt + " < n ? ya : yz))") << ";\n";
         o << in << "            if (e0 + e * " << nt << " < n) {\n";
         for (size_t j = 0; j < nr; ++j) {
             if (py.reads[j].trans)
                 o << in << "                v" << j << "[e] = " << widen(py.reads[j].dtype, "st" + std::to_string(j) + "[l]") << ";\n";
-            else
+            else if (!converted(j))
                 o << in << "                v" << j << "[e] = " << widen(py.reads[j].dtype, "ldpl(L" + std::to_string(j) + " + ya)") << ";\n";
         }
         o << in << "            }\n";

@@ -12,7 +12,7 @@ import oracle
 import synth
 from synth import leaf
 
-from gpu_util import need_gpu, torch
+from gpu_util import TORCH_DT, need_gpu, torch
 
 pytestmark = pytest.mark.gpu
 
@@ -82,6 +82,48 @@ def test_small_ragged_batch_against_oracle(dt):
         assert np.array_equal(got, em), i
         o, _, _ = oracle.reduce("accu", (Ytree % Ytree).postfix(), [Am, Bm], mode="emu")
         assert abs(rh[i] - o[0]) <= (1e-6 if dt == "f32" else 1e-13) * abs(o[0]), (i, rh[i], o[0])
+    plan.close()
+
+
+@pytest.mark.parametrize("dts", [("f32", "bf16"), ("f16", "f16")])
+def test_sixteen_bit_operands(dts):
+    """16-bit A_i (staged through LDS) and B_i (read straight and widened on
+    load, every element of a unit's last pass loading the unit's first when it
+    falls past the unit): Y_i in FP32 bit for bit, r_i within 1e-6."""
+    g = np.random.default_rng(9)
+    shapes = np.concatenate([np.array([[1, 1], [1, 70], [70, 1], [64, 64], [65, 63], [130, 7], [300, 41]]),
+                             g.integers(1, 200, (40, 2))])
+    sizes = shapes[:, 0] * shapes[:, 1]
+    padded = (sizes + 63) // 64 * 64
+    offs = np.zeros(len(shapes), np.int64)
+    offs[1:] = np.cumsum(padded)[:-1]
+    total = int(padded.sum()) + 64
+    host = [synth.store(g.uniform(-1, 1, total), dt) for dt in dts]
+    devs = []
+    for h, dt in zip(host, dts):
+        t = torch.from_numpy(h.view(np.int16)).view(TORCH_DT[dt]) if dt != "f32" else torch.from_numpy(h)
+        devs.append(t.cuda())
+    dY = torch.full((total,), float("nan"), dtype=torch.float32, device="cuda")
+    red = torch.zeros(len(shapes), dtype=torch.float32, device="cuda")
+    ptrs = [[devs[0].data_ptr() + int(o) * devs[0].element_size(), devs[1].data_ptr() + int(o) * devs[1].element_size()]
+            for o in offs]
+    code = {"f32": coot.F32, "bf16": coot.BF16, "f16": coot.F16}
+    plan = coot.BatchPlan(Ytree, [code[dts[0]], code[dts[1]]], ptrs, [[int(c), int(r)] for r, c in shapes],
+                          out_ptrs=[dY.data_ptr() + int(o) * 4 for o in offs], out_dtype=coot.F32,
+                          red_tree=Rtree, red_op="accu", red_out=red, red_dtype=coot.F32)
+    plan.run()
+    torch.cuda.synchronize()
+    Yh = dY.cpu().numpy().astype(np.float64)
+    rh = red.cpu().numpy().astype(np.float64)
+    for i, (r, c) in enumerate(shapes):
+        n = r * c
+        Am = synth.Mat(np.asfortranarray(host[0][offs[i]:offs[i] + n].reshape((r, c), order="F")), dts[0])
+        Bm = synth.Mat(np.asfortranarray(host[1][offs[i]:offs[i] + n].reshape((c, r), order="F")), dts[1])
+        em = oracle.evaluate(Ytree.postfix(), [Am, Bm], "emu")
+        got = Yh[offs[i]:offs[i] + n].reshape((c, r), order="F")
+        assert np.array_equal(got, em), (dts, i)
+        o, _, _ = oracle.reduce("accu", (Ytree % Ytree).postfix(), [Am, Bm], mode="emu")
+        assert abs(rh[i] - o[0]) <= 1e-6 * abs(o[0]), (dts, i, rh[i], o[0])
     plan.close()
 
 
