@@ -458,11 +458,11 @@ def validate(red_op, dim, tree, operands: Sequence, out) -> int:
     return _check(lib().coot_validate(rc, dim, C.byref(e), arr, n, C.byref(o)))
 
 
-def kernel_source(red_op, dim, tree, operands: Sequence, out, cfg=None) -> str:
+def kernel_source(red_op, dim, tree, operands: Sequence, out, cfg=None, pairwise: bool = False) -> str:
     e = expr(tree, cfg)
     arr, n = _ops(operands)
     o = operand(out)
-    rc = -1 if red_op is None else _red_code(red_op, False)
+    rc = -1 if red_op is None else _red_code(red_op, pairwise)
     size = _check(lib().coot_kernel_source(rc, dim, C.byref(e), arr, n, C.byref(o), None, 0))
     buf = C.create_string_buffer(size + 1)
     _check(lib().coot_kernel_source(rc, dim, C.byref(e), arr, n, C.byref(o), buf, size + 1))

@@ -267,6 +267,47 @@ static std::string accumulate_into(const Plan& p, const std::string& args, const
     }
 }
 
+// A compensated FP32 sum whose tree is one FP16 leaf (accu, sum, mean of the
+// stored values) adds each half straight from its 32-bit storage word: the
+// mixed-precision FMA w.half * 1 + s converts the half inside the add with one
+// rounding, the value the add of the converted half gives, so both adds of the
+// TwoSum take the half without a conversion instruction in front of them (with
+// the conversion first these sums ran 4-5% slower than plain accumulation).
+static bool f16_mix_sum(const Plan& p)
+{
+    return p.reads.size() == 1 && p.reads[0].dtype == COOT_F16 && !p.reads[0].trans &&
+           p.nodes[p.root].op == COOT_LEAF && !p.product_form && !p.gen_index && acc_type(p) == "AccKF" &&
+           p.ve % 2 == 0 && (p.red_op == COOT_RED_ACCU || p.red_op == COOT_RED_SUM || p.red_op == COOT_RED_MEAN);
+}
+
+static const char* const F16_MIX_SRC = R"(#ifndef COOT_F16_MIX
+#define COOT_F16_MIX
+// w's low (HI = 0) or high (HI = 1) half as FP16, times 1, plus s: one rounding
+template <int HI> CD float f16_add(u32 w, float s)
+{
+    float r;
+    if (HI) asm("v_fma_mix_f32 %0, %1, 1.0, %2 op_sel:[1,0,0] op_sel_hi:[1,0,0]" : "=v"(r) : "v"(w), "v"(s));
+    else asm("v_fma_mix_f32 %0, %1, 1.0, %2 op_sel_hi:[1,0,0]" : "=v"(r) : "v"(w), "v"(s));
+    return r;
+}
+// AccKF::add of one half of w, the half read inside both adds
+template <int HI> CD void acc_add_f16(AccKF& a, u32 w)
+{
+    const float t = f16_add<HI>(w, a.s);
+    const float z = t - a.s;
+    a.c += (a.s - (t - z)) + f16_add<HI>(w, -z);
+    a.s = t;
+}
+#endif
+)";
+
+// element k (an unrolled index) of the FP16 vector `vec` added to `acc`
+static std::string f16_mix_add(const std::string& vec, const std::string& acc)
+{
+    return "{ const u32 w = (u32)" + vec + "[k & ~1] | ((u32)" + vec + "[k | 1] << 16); if (k & 1) acc_add_f16<1>(" +
+           acc + ", w); else acc_add_f16<0>(" + acc + ", w); }";
+}
+
 static std::string put_value(const Plan& p, const std::string& where, const std::string& v)
 {
     return std::string(p.out_dtype == COOT_F64 ? "put_f64(" : "put_f32(") + "a.res, " + where + ", " + v + ");";
@@ -417,7 +458,9 @@ static std::string emit_flat(const Plan& p, const LaunchCfg& c, const std::strin
     const int VE = p.ve, EPT = c.ept;
     const std::string OS = ew ? stype(p.out_dtype) : "";
     const int rp = p.nodes[p.root].prec;
+    const bool mix = !ew && f16_mix_sum(p);
     std::ostringstream s;
+    if (mix) s << F16_MIX_SRC;
     s << "extern \"C\" __global__ void __launch_bounds__(512) " << name << "(const coot_kargs a)\n{\n";
     s << decl_reads(p, !p.alias_out);
     if (ew) s << "    " << OS << "* " << (p.alias_out ? "" : "__restrict__ ") << "O = (" << OS << "*)a.out;\n";
@@ -464,8 +507,9 @@ static std::string emit_flat(const Plan& p, const LaunchCfg& c, const std::strin
             o << "            const i64 v = " << b << " + e * bs;\n            if (" << (guarded ? "v < nv" : "true")
               << ") {\n";
             o << "#pragma unroll\n                for (int k = 0; k < " << VE << "; ++k) { const i64 gi = v * " << VE
-              << " + k; (void)gi; if (e & 1) " << increasing(p, accumulate(p, args, "gi", "acc2")) << " else "
-              << increasing(p, accumulate(p, args, "gi")) << " }\n";
+              << " + k; (void)gi; if (e & 1) "
+              << (mix ? f16_mix_add(buf + "0[e]", "acc2") : increasing(p, accumulate(p, args, "gi", "acc2"))) << " else "
+              << (mix ? f16_mix_add(buf + "0[e]", "acc") : increasing(p, accumulate(p, args, "gi"))) << " }\n";
             o << "            }\n        }\n";
             return o.str();
         };
@@ -1351,7 +1395,9 @@ static std::string emit_thin(const Plan& p, const std::string& name)
 static std::string emit_col(const Plan& p, const LaunchCfg& c, const std::string& name)
 {
     const int VE = p.ve, EPT = c.ept;
+    const bool mix = f16_mix_sum(p);
     std::ostringstream s;
+    if (mix) s << F16_MIX_SRC;
     s << "extern \"C\" __global__ void __launch_bounds__(512) " << name << "(const coot_kargs a)\n{\n";
     s << decl_reads(p, true);
     s << "    const int lane = threadIdx.x & 63;\n";
@@ -1435,7 +1481,7 @@ static std::string emit_col(const Plan& p, const LaunchCfg& c, const std::string
         s << "                const i64 v = base + e * 64;\n                if (v < nvr) {\n";
         std::string args = arglist(p, [](int j) { return "r" + std::to_string(j) + "[e][k]"; }, "gi + j * a.rows, gi, j");
         s << "#pragma unroll\n                    for (int k = 0; k < " << VE << "; ++k) { const i64 gi = rs0 + v * " << VE
-          << " + k; (void)gi; " << accumulate(p, args, "gi") << " }\n";
+          << " + k; (void)gi; " << (mix ? f16_mix_add("r0[e]", "acc") : accumulate(p, args, "gi")) << " }\n";
         s << "                }\n            }\n        }\n";
     }
     std::string targs = arglist(p, [](int j) { return "ldnt(C" + std::to_string(j) + " + r)"; },

@@ -213,6 +213,39 @@ def test_batched_kernels_compile_for_gfx950(tmp_path):
     assert "_comb" not in src2
 
 
+def test_fp16_leaf_sums_add_from_the_storage_word(tmp_path):
+    """Compensated sums whose tree is one FP16 leaf (accu, per-column sum) add
+    each half with the mixed-precision FMA straight from its storage word;
+    BF16 leaves, the pairwise variant and FP16 products keep the conversion
+    first.  The FP16 kernels compile for gfx950."""
+    import shutil
+
+    n = 4096
+    acc_out, col_out = F(1, 1, "f32", ptr=9 * G), F(1, n, "f32", ptr=9 * G)
+    x, y = leaves(2)
+    fused = [coot.kernel_source("accu", -1, x, [F(n, n, "f16", ptr=G)], acc_out),
+             coot.kernel_source("sum", 0, x, [F(n, n, "f16", ptr=G)], col_out)]
+    for s in fused:
+        assert "acc_add_f16<1>" in s and "v_fma_mix_f32" in s
+    plain = [coot.kernel_source("accu", -1, x, [F(n, n, "bf16", ptr=G)], acc_out),
+             coot.kernel_source("accu", -1, x, [F(n, n, "f16", ptr=G)], acc_out, pairwise=True),
+             coot.kernel_source("accu", -1, x % y, [F(n, n, "f16", ptr=G), F(n, n, "f16", ptr=2 * G)], acc_out)]
+    for s in plain:
+        assert "acc_add_f16" not in s
+    hipcc = shutil.which("hipcc") or "/opt/rocm/bin/hipcc"
+    if not os.path.exists(hipcc):
+        pytest.skip("hipcc not available")
+    for i, src in enumerate(fused):
+        f = tmp_path / f"k{i}.hip"
+        f.write_text("#include <hip/hip_runtime.h>\n" + src)
+        r = subprocess.run([hipcc, "--offload-arch=gfx950", "-O3", "-std=c++17", "-ffp-contract=off", "-Xclang",
+                            "-target-feature", "-Xclang", "-packed-fp32-ops", "--cuda-device-only", "-S", str(f), "-o",
+                            str(tmp_path / f"k{i}.s")], capture_output=True, text=True)
+        assert r.returncode == 0, r.stderr[-2000:]
+        asm = (tmp_path / f"k{i}.s").read_text()
+        assert "v_fma_mix_f32" in asm and "v_cvt_f32_f16_sdwa" not in asm
+
+
 def test_batch_aliasing_rejected_before_any_device_work():
     """coot_batch_create checks every item's output against the memory the
     launch reads and writes before it allocates or launches anything, so the
