@@ -280,9 +280,9 @@ static bool f16_mix_sum(const Plan& p)
            p.ve % 2 == 0 && (p.red_op == COOT_RED_ACCU || p.red_op == COOT_RED_SUM || p.red_op == COOT_RED_MEAN);
 }
 
-static const char* const F16_MIX_SRC = R"(#ifndef COOT_F16_MIX
-#define COOT_F16_MIX
-// w's low (HI = 0) or high (HI = 1) half as FP16, times 1, plus s: one rounding
+// (each kernel source holds one copy: a module of many kernels wraps each in a
+// namespace of its own)
+static const char* const F16_MIX_SRC = R"(// w's low (HI = 0) or high (HI = 1) half as FP16, times 1, plus s: one rounding
 template <int HI> CD float f16_add(u32 w, float s)
 {
     float r;
@@ -298,7 +298,6 @@ template <int HI> CD void acc_add_f16(AccKF& a, u32 w)
     a.c += (a.s - (t - z)) + f16_add<HI>(w, -z);
     a.s = t;
 }
-#endif
 )";
 
 // element k (an unrolled index) of the FP16 vector `vec` added to `acc`
@@ -1587,7 +1586,7 @@ static std::string emit_row(const Plan& p, const std::string& name)
                "h[u] = pp[0]; l[u] = pp[1]; }\n"
                "#pragma unroll\n"
                "                for (int u = 0; u < 8; ++u) if (t + u < s1) { x.add(h[u]); x.add(l[u]); } }";
-        put = put_sum_result(p, "r", "(y.s + y.c)");
+        put = put_sum_result(p, "r", "(y.hi() + y.lo())");
     } else {
         const std::string mx = red_is_max(p.red_op) ? "true" : "false";
         acc = "AccI<double, " + mx + ">";

@@ -242,7 +242,10 @@ struct AccKF {
         merge(o);
     }
     CD double hi() const { return (double)s; }
-    CD double lo() const { return (double)c; }
+    /* Once the sum is infinite or NaN every later TwoSum makes c NaN; the
+     * value is then s alone (inf + finite = inf, inf + -inf = NaN, as in
+     * IEEE addition). */
+    CD double lo() const { return __builtin_isfinite(s) ? (double)c : 0.0; }
 };
 
 /* Plain FP32 sum (the "pairwise only" variant: per-thread running sum, then
@@ -297,7 +300,7 @@ struct AccKD {
         merge(o);
     }
     CD double hi() const { return s; }
-    CD double lo() const { return c; }
+    CD double lo() const { return __builtin_isfinite(s) ? c : 0.0; }  // as AccKF::lo
 };
 
 /* Variance accumulator, FP64 for every storage type: the count c, a shift k
@@ -526,7 +529,7 @@ CD double combine_sums(const double* part, i64 first, i64 count, i64 stride)
             }
     }
     a = block_reduce(a, lds_kd);
-    return a.s + a.c;
+    return a.hi() + a.lo();
 }
 
 template <bool MAX>
@@ -573,7 +576,7 @@ CD double combine_sums_seq(const double* part, i64 first, i64 count, i64 stride)
                 a.add(l[u]);
             }
     }
-    return a.s + a.c;
+    return a.hi() + a.lo();
 }
 
 template <bool MAX>

@@ -323,3 +323,17 @@ def test_tall_tile_kernels_compile_for_gfx950(tmp_path, monkeypatch, dt):
         assert coot.precompile("index_max", -1, x % y, [A, B], F(1, 1, "u64", ptr=9 * G)) in (0, 1)
     E = coot.eye(r, c, odt)
     assert coot.precompile(None, -1, x * 0.5 + leaves(2)[1], [F(r, c, dt, ld=ld, ptr=G), E], F(r, c, odt, ptr=3 * G)) in (0, 1)
+
+
+def test_fp16_leaf_sums_share_a_module():
+    """Many kernels compiled into one code object each sit in a namespace of
+    their own, so every FP16 leaf sum carries its own copy of the
+    mixed-precision helpers (a shared include guard left the second kernel
+    without them)."""
+    from synth import leaf as lf
+
+    coot.precompile_begin()
+    for ept in (1, 2, 4, 8):
+        coot.precompile("accu", -1, lf(0), [F(1 << 20, 1, "f16", ptr=G)], F(1, 1, "f32", ptr=9 * G), cfg=(ept, 256, 8))
+        coot.precompile("sum", 0, lf(0), [F(4096, 64, "f16", ptr=G)], F(1, 64, "f32", ptr=9 * G), cfg=(ept, 256, 8))
+    assert coot.precompile_end(64) == 8

@@ -72,3 +72,62 @@ def test_compensated_sum_is_exact_where_plain_fp32_is_not(dt):
         assert rp > 1e-6, (op, dt, plain, exact, rp)
         # with the launch configuration stated explicitly the results are the same
         assert coot.reduce(op, tree, ops, cfg=FLAT_CFG).double().item() == comp
+
+
+def test_fp16_leaf_sums_special_values():
+    """Compensated FP16 leaf sums (accu, per-column sum) add each half from
+    its storage word through the mixed-precision FMA: infinities and NaNs
+    propagate as in IEEE addition, subnormal halves count at their value and
+    the largest half sums exactly."""
+    g = np.random.default_rng(11)
+    r, c = 4099, 6
+    v = g.uniform(-1, 1, (r, c))
+    v[:, 1] = 2.0 ** -24 * g.integers(1, 1024, r)   # subnormal halves only
+    v[:, 2] = 65504.0                               # the largest half
+    v[100, 3] = np.inf
+    v[7, 4], v[3000, 4] = np.inf, -np.inf
+    v[2048, 5] = np.nan
+    M = synth.Mat(np.asfortranarray(synth.store(v, "f16")), "f16")
+    w = oracle.widen16("f16", M.data)
+    X = synth.leaf(0)
+    dM = dev(M)
+    col = coot.reduce("sum", X, [dM], dim=0).double().cpu().numpy().reshape(-1)
+    for j in (0, 1, 2):
+        exact = float(np.sum(w[:, j]))   # FP64 sums of halves: exact for these columns
+        assert abs(col[j] - exact) <= 1e-6 * abs(exact), (j, col[j], exact)
+    assert col[1] > 0 and col[2] == float(np.float32(r * 65504.0))
+    assert col[3] == np.inf and np.isnan(col[4]) and np.isnan(col[5])
+    for cols, expect in (([0, 1, 2], None), ([0, 3], np.inf), ([4], "nan"), ([5, 0], "nan")):
+        sub = synth.Mat(np.asfortranarray(M.data[:, cols]), "f16")
+        got = coot.reduce("accu", X, [dev(sub)]).double().item()
+        if expect is None:
+            exact = float(np.sum(w[:, cols]))
+            assert abs(got - exact) <= 1e-6 * abs(exact), (cols, got, exact)
+        elif expect == "nan":
+            assert np.isnan(got), cols
+        else:
+            assert got == expect, (cols, got)
+
+
+@pytest.mark.parametrize("dt", ["f32", "f64"])
+def test_compensated_sums_propagate_infinities(dt):
+    """An infinite term makes every later TwoSum correction NaN; accu and the
+    sums along either dimension (row sums through the per-row combine) still
+    return inf for one infinity and NaN for both signs or a NaN."""
+    g = np.random.default_rng(12)
+    for r, c in ((5000, 8), (8, 300000)):
+        v = g.uniform(-1, 1, (r, c))
+        v[r // 2, 1] = np.inf                     # column 1 and row r//2: +inf
+        v[1, 2], v[r - 1, 2] = np.inf, -np.inf    # column 2: NaN
+        v[0, 3] = np.nan                          # column 3 and row 0: NaN
+        M = synth.Mat(np.asfortranarray(synth.store(v, dt)), dt)
+        X = synth.leaf(0)
+        dM = dev(M)
+        col = coot.reduce("sum", X, [dM], dim=0).double().cpu().numpy().reshape(-1)
+        assert col[1] == np.inf and np.isnan(col[2]) and np.isnan(col[3]) and np.isfinite(col[0]), (r, c)
+        row = coot.reduce("sum", X, [dM], dim=1).double().cpu().numpy().reshape(-1)
+        assert np.isnan(row[0]) and row[1] == np.inf and row[r - 1] == -np.inf, (r, c)
+        assert row[r // 2] == np.inf and np.isfinite(row[2]), (r, c)
+        assert np.isnan(coot.reduce("accu", X, [dM]).double().item())
+        one = synth.Mat(np.asfortranarray(M.data[:, :2]), dt)
+        assert coot.reduce("accu", X, [dev(one)]).double().item() == np.inf
